@@ -1,0 +1,282 @@
+/*
+ * CPU oracle for the checkerboard Metropolis dynamics of the 3D Edwards-Anderson
+ * spin glass with bimodal couplings (Lulli, Bernaschi, Parisi, "Highly optimized
+ * simulations on single- and multi-GPU systems of 3D Ising spin glass",
+ * arXiv:1411.0127).
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load this file.  It shares no code with
+ * the GPU library: it is the plain definition of what the GPU path computes, one
+ * signed byte per spin, one sample at a time, in the order the paper states it.
+ *
+ * Conventions (readings of the paper, each justified where it is used):
+ *   - extents Lx, Ly, Lz are even (Sec. 1: checkerboard needs L = 2n);
+ *   - site index i = x + Lx*(y + Ly*z);
+ *   - J[d*V + i] is the coupling of the bond between i and its +d neighbour
+ *     (periodic), d = 0,1,2 for x,y,z; every site owns three bonds, 3V in all;
+ *   - "red" sites have x+y+z even and are updated first, then the "blue" ones;
+ *     one red pass plus one blue pass is one sweep (Sec. 1; psFlip definition
+ *     in Sec. 4.1 times red + blue);
+ *   - the random number used by site i in a sweep is R[i], an unsigned integer
+ *     handed in by the caller; the generators that produce it are below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* MINSTD (Sec. 3, Lehmer / Park-Miller congruential generator):             */
+/*   R_{n+1} = 16807 * R_n  mod  (2^31 - 1).                                  */
+/* Written with a plain 64-bit product and the % operator: slow and obvious.  */
+/* ------------------------------------------------------------------------- */
+uint32_t oc_minstd_next(uint32_t r)
+{
+    return (uint32_t)(((uint64_t)16807u * (uint64_t)r) % 2147483647ull);
+}
+
+/* Advance every per-site MINSTD state once and return the new values.
+ * One draw per site per sweep, shared by every sample coded at that site
+ * (asynchronous multispin coding, Sec. 4). */
+void oc_minstd_draws(int64_t V, uint32_t *state, uint32_t *R)
+{
+    for (int64_t i = 0; i < V; ++i) {
+        state[i] = oc_minstd_next(state[i]);
+        R[i] = state[i];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* MT19937 (Sec. 3; M. Matsumoto and T. Nishimura, ACM TOMACS 8 (1998) 3-30). */
+/* State of 624 words, initialised by the published init_genrand recurrence;  */
+/* a full twist regenerates all 624 words when they are used up; outputs are  */
+/* tempered.                                                                  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t mt[624];
+    int32_t mti;
+} oc_mt;
+
+void oc_mt_init(oc_mt *s, uint32_t seed)
+{
+    s->mt[0] = seed;
+    for (int k = 1; k < 624; ++k) {
+        uint32_t prev = s->mt[k - 1];
+        s->mt[k] = 1812433253u * (prev ^ (prev >> 30)) + (uint32_t)k;
+    }
+    s->mti = 624;
+}
+
+static void oc_mt_twist(oc_mt *s)
+{
+    for (int k = 0; k < 624; ++k) {
+        uint32_t y = (s->mt[k] & 0x80000000u) | (s->mt[(k + 1) % 624] & 0x7fffffffu);
+        uint32_t v = s->mt[(k + 397) % 624] ^ (y >> 1);
+        if (y & 1u)
+            v ^= 0x9908b0dfu;
+        s->mt[k] = v;
+    }
+    s->mti = 0;
+}
+
+uint32_t oc_mt_next(oc_mt *s)
+{
+    if (s->mti >= 624)
+        oc_mt_twist(s);
+    uint32_t y = s->mt[s->mti++];
+    y ^= y >> 11;
+    y ^= (y << 7) & 0x9d2c5680u;
+    y ^= (y << 15) & 0xefc60000u;
+    y ^= y >> 18;
+    return y;
+}
+
+int64_t oc_mt_sizeof(void) { return (int64_t)sizeof(oc_mt); }
+
+void oc_mt_init_many(int64_t n, oc_mt *s, const uint32_t *seeds)
+{
+    for (int64_t c = 0; c < n; ++c)
+        oc_mt_init(&s[c], seeds[c]);
+}
+
+void oc_mt_outputs(uint32_t seed, int64_t n, uint32_t *out)
+{
+    oc_mt s;
+    oc_mt_init(&s, seed);
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = oc_mt_next(&s);
+}
+
+/* One stream per x-y column c = x + Lx*y; within a sweep the column's site at
+ * height z takes the column's next output, z = 0, 1, ..., Lz-1 in order. */
+void oc_mt_draws(int Lx, int Ly, int Lz, oc_mt *cols, uint32_t *R)
+{
+    for (int y = 0; y < Ly; ++y)
+        for (int x = 0; x < Lx; ++x) {
+            oc_mt *s = &cols[x + (int64_t)Lx * y];
+            for (int z = 0; z < Lz; ++z)
+                R[x + (int64_t)Lx * (y + (int64_t)Ly * z)] = oc_mt_next(s);
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Integer acceptance thresholds (Sec. 4): a flip with energy change dE > 0 is */
+/* accepted when the integer random number R is below R_max * exp(-beta dE),   */
+/* called EXP4, EXP8, EXP12.  Reading: R_max is the size of the generator's    */
+/* output range (2^31 - 1 for MINSTD, whose outputs lie in [1, 2^31 - 2];      */
+/* 2^32 for MT19937), the product is rounded up, and the test is strict, so     */
+/* R < T holds exactly when R < R_max * p; beta = 0 then accepts every          */
+/* proposal and beta = +inf none.  T[k-1] is the threshold for dE = 4k.        */
+/* ------------------------------------------------------------------------- */
+void oc_thresholds(double beta, uint64_t range, uint64_t T[3])
+{
+    for (int k = 1; k <= 3; ++k) {
+        double dE = 4.0 * k;
+        double p = exp(-(beta * dE));
+        T[k - 1] = (uint64_t)ceil((double)range * p);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One Metropolis sweep of one sample (Sec. 1 checkerboard; Sec. 4 P_flip).   */
+/* s: V spins in {-1,+1}; J: 3V couplings in {-1,+1}; R: one number per site. */
+/* ------------------------------------------------------------------------- */
+static inline int64_t idx(int Lx, int Ly, int x, int y, int z)
+{
+    return x + (int64_t)Lx * (y + (int64_t)Ly * z);
+}
+
+void oc_sweep(int Lx, int Ly, int Lz, int8_t *s, const int8_t *J, const uint32_t *R,
+              const uint64_t T[3])
+{
+    const int64_t V = (int64_t)Lx * Ly * Lz;
+    for (int colour = 0; colour < 2; ++colour)
+        for (int z = 0; z < Lz; ++z)
+            for (int y = 0; y < Ly; ++y)
+                for (int x = 0; x < Lx; ++x) {
+                    if (((x + y + z) & 1) != colour)
+                        continue;
+                    const int xp = (x + 1) % Lx, xm = (x + Lx - 1) % Lx;
+                    const int yp = (y + 1) % Ly, ym = (y + Ly - 1) % Ly;
+                    const int zp = (z + 1) % Lz, zm = (z + Lz - 1) % Lz;
+                    const int64_t i = idx(Lx, Ly, x, y, z);
+                    /* local field: the three bonds the site owns and the three
+                     * bonds its -d neighbours own towards it */
+                    int h = J[0 * V + i] * s[idx(Lx, Ly, xp, y, z)]
+                          + J[1 * V + i] * s[idx(Lx, Ly, x, yp, z)]
+                          + J[2 * V + i] * s[idx(Lx, Ly, x, y, zp)]
+                          + J[0 * V + idx(Lx, Ly, xm, y, z)] * s[idx(Lx, Ly, xm, y, z)]
+                          + J[1 * V + idx(Lx, Ly, x, ym, z)] * s[idx(Lx, Ly, x, ym, z)]
+                          + J[2 * V + idx(Lx, Ly, x, y, zm)] * s[idx(Lx, Ly, x, y, zm)];
+                    /* H = -sum J s_i s_k, so flipping s_i changes it by 2 s_i h */
+                    const int dE = 2 * s[i] * h;
+                    int accept;
+                    if (dE <= 0)
+                        accept = 1;
+                    else
+                        accept = (uint64_t)R[i] < T[dE / 4 - 1];
+                    if (accept)
+                        s[i] = (int8_t)(-s[i]);
+                }
+}
+
+/* Number of unsatisfied bonds U (bonds with -J s_i s_k = +1); the energy of
+ * Eq. (1) is E = 2U - 3V. */
+int64_t oc_unsatisfied(int Lx, int Ly, int Lz, const int8_t *s, const int8_t *J)
+{
+    const int64_t V = (int64_t)Lx * Ly * Lz;
+    int64_t U = 0;
+    for (int z = 0; z < Lz; ++z)
+        for (int y = 0; y < Ly; ++y)
+            for (int x = 0; x < Lx; ++x) {
+                const int64_t i = idx(Lx, Ly, x, y, z);
+                const int64_t nb[3] = {idx(Lx, Ly, (x + 1) % Lx, y, z),
+                                       idx(Lx, Ly, x, (y + 1) % Ly, z),
+                                       idx(Lx, Ly, x, y, (z + 1) % Lz)};
+                for (int d = 0; d < 3; ++d)
+                    U += (-J[d * V + i] * s[i] * s[nb[d]]) > 0;
+            }
+    return U;
+}
+
+/* Number of sites where two replicas differ; q = 1 - 2 N / V. */
+int64_t oc_ndiff(int64_t V, const int8_t *a, const int8_t *b)
+{
+    int64_t n = 0;
+    for (int64_t i = 0; i < V; ++i)
+        n += a[i] != b[i];
+    return n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exact Gibbs averages (Eq. (3)) by enumeration of all 2^V configurations,   */
+/* V <= 24.  Outputs <E>, <E^2> and the probability of each energy level      */
+/* E = -3V + 2U, U = 0..3V (hist has 3V+1 entries).                           */
+/* ------------------------------------------------------------------------- */
+int oc_gibbs(int Lx, int Ly, int Lz, const int8_t *J, double beta, double *meanE,
+             double *meanE2, double *hist)
+{
+    const int64_t V = (int64_t)Lx * Ly * Lz;
+    if (V > 24)
+        return -1;
+    int8_t *s = (int8_t *)malloc((size_t)V);
+    double *w = (double *)calloc((size_t)(3 * V + 1), sizeof(double));
+    if (!s || !w) {
+        free(s);
+        free(w);
+        return -2;
+    }
+    /* count states per U first, then weight: exact in double for V <= 24 */
+    for (uint64_t c = 0; c < (1ull << V); ++c) {
+        for (int64_t i = 0; i < V; ++i)
+            s[i] = (c >> i) & 1 ? 1 : -1;
+        w[oc_unsatisfied(Lx, Ly, Lz, s, J)] += 1.0;
+    }
+    int64_t Umin = 0;
+    while (w[Umin] == 0.0)
+        ++Umin;
+    double Z = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int64_t U = 0; U <= 3 * V; ++U) {
+        double E = 2.0 * U - 3.0 * V;
+        double b = w[U] * exp(-beta * 2.0 * (double)(U - Umin));
+        hist[U] = b;
+        Z += b;
+        e1 += b * E;
+        e2 += b * E * E;
+    }
+    for (int64_t U = 0; U <= 3 * V; ++U)
+        hist[U] /= Z;
+    *meanE = e1 / Z;
+    *meanE2 = e2 / Z;
+    free(s);
+    free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* n sweeps of S samples sharing one stream set (prng 0: per-site MINSTD       */
+/* states, 1: per-column MT19937 states), thresholds fixed.  Records the       */
+/* unsatisfied-bond count of every sample after every sweep when U != NULL     */
+/* (U[t*S + j]).  s: S*V bytes; J: S*3V bytes, sample-major.                    */
+/* ------------------------------------------------------------------------- */
+int oc_run(int Lx, int Ly, int Lz, int S, int8_t *s, const int8_t *J, int prng, void *state,
+           int64_t nsweeps, const uint64_t T[3], int64_t *U)
+{
+    const int64_t V = (int64_t)Lx * Ly * Lz;
+    uint32_t *R = (uint32_t *)malloc((size_t)V * sizeof(uint32_t));
+    if (!R)
+        return -2;
+    for (int64_t t = 0; t < nsweeps; ++t) {
+        if (prng == 0)
+            oc_minstd_draws(V, (uint32_t *)state, R);
+        else
+            oc_mt_draws(Lx, Ly, Lz, (oc_mt *)state, R);
+        for (int j = 0; j < S; ++j) {
+            oc_sweep(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V, R, T);
+            if (U)
+                U[t * S + j] = oc_unsatisfied(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V);
+        }
+    }
+    free(R);
+    return 0;
+}

@@ -1,0 +1,125 @@
+"""Seeded synthetic inputs for the 3D +-J Edwards-Anderson spin glass.
+
+This module is shared by the CPU oracle (through the tests) and by the GPU
+library's callers.  It holds no part of the Metropolis method: it only turns
+user seeds into the quenched couplings, the initial spins and the initial
+state of the per-site / per-column random streams.  The paper draws all of
+these "at random" (Sec. 1, bimodal distribution P(J)); a reproducible keyed
+generator stands in for its system random pool.
+
+Generator: SplitMix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014).  Its n-th output from state
+``k`` is ``mix64(k + n * GAMMA)`` for n = 1, 2, ...; that definition makes it
+counter-based, so any word can be produced on its own.  The GPU library
+implements the same published definition in its own device code.
+
+Conventions (this project's, stated once here):
+
+* site index ``i = x + L*(y + L*z)``;
+* ``key(seed, tag, r) = out(out(seed, 1 + tag), 1 + r)`` where
+  ``out(k, n) = mix64(k + n*GAMMA)``;
+* coupling word of bond (i, i + d^) for d in {x, y, z} = 0, 1, 2:
+  ``out(key(coupling_seed, TAG_J, 0), 1 + 3*i + d)``; bit j set <=> J = -1 for
+  sample j (bit mapping of Sec. 4);
+* initial spin word of site i, replica r: ``out(key(spin_seed, TAG_SPIN, r), 1 + i)``;
+  bit j set <=> sigma = +1 for sample j;
+* MINSTD seed of site i, replica r:
+  ``1 + ((out(key(spin_seed, TAG_MINSTD, r), 1 + i) >> 33) mod (2**31 - 2))``,
+  a value in [1, 2**31 - 2], i.e. a valid non-zero MINSTD state;
+* MT19937 seed of column c = x + L*y, replica r:
+  ``out(key(spin_seed, TAG_MT, r), 1 + c) & 0xffffffff``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+TAG_J = 1
+TAG_SPIN = 2
+TAG_MINSTD = 3
+TAG_MT = 4
+
+MINSTD_MODULUS = 2**31 - 1
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def out(key, n) -> np.ndarray:
+    """n-th SplitMix64 output (n >= 1) of a generator whose state starts at ``key``."""
+    key = np.uint64(int(key) & 0xFFFFFFFFFFFFFFFF)
+    n = np.asarray(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return mix64(key + n * GAMMA)
+
+
+def out_scalar(key: int, n: int) -> int:
+    return int(out(key, np.array([n], dtype=np.uint64))[0])
+
+
+def key(seed: int, tag: int, replica: int) -> int:
+    return out_scalar(out_scalar(seed, 1 + tag), 1 + replica)
+
+
+def _chunks(total: int, chunk: int = 1 << 24):
+    for start in range(0, total, chunk):
+        yield start, min(total, start + chunk)
+
+
+def coupling_words(L: int, coupling_seed: int) -> np.ndarray:
+    """uint64 array J[3][L^3]; J[d][i] is the bond between i and i + d^ (periodic)."""
+    V = L**3
+    k = key(coupling_seed, TAG_J, 0)
+    J = np.empty((3, V), dtype=np.uint64)
+    for a, b in _chunks(V):
+        i = np.arange(a, b, dtype=np.uint64)
+        for d in range(3):
+            J[d, a:b] = out(k, np.uint64(1 + d) + np.uint64(3) * i)
+    return J
+
+
+def spin_words(L: int, spin_seed: int, replica: int) -> np.ndarray:
+    """uint64 array S[L^3] of initial spin words (bit j = sample j, 1 <=> +1)."""
+    V = L**3
+    k = key(spin_seed, TAG_SPIN, replica)
+    S = np.empty(V, dtype=np.uint64)
+    for a, b in _chunks(V):
+        S[a:b] = out(k, np.arange(a + 1, b + 1, dtype=np.uint64))
+    return S
+
+
+def minstd_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
+    """uint32 array of per-site MINSTD seeds in [1, 2^31 - 2]."""
+    V = L**3
+    k = key(spin_seed, TAG_MINSTD, replica)
+    s = np.empty(V, dtype=np.uint32)
+    for a, b in _chunks(V):
+        h = out(k, np.arange(a + 1, b + 1, dtype=np.uint64)) >> np.uint64(33)
+        s[a:b] = (np.uint64(1) + h % np.uint64(MINSTD_MODULUS - 1)).astype(np.uint32)
+    return s
+
+
+def mt_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
+    """uint32 array of per-column MT19937 seeds, column c = x + L*y."""
+    k = key(spin_seed, TAG_MT, replica)
+    c = np.arange(1, L * L + 1, dtype=np.uint64)
+    return (out(k, c) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def gauge_words(L: int, gauge_seed: int) -> np.ndarray:
+    """Random per-site gauge words g_i for the gauge-symmetry checks."""
+    k = key(gauge_seed, 7, 0)
+    return out(k, np.arange(1, L**3 + 1, dtype=np.uint64))
+
+
+def site_index(L: int, x, y, z):
+    return np.asarray(x) + L * (np.asarray(y) + L * np.asarray(z))

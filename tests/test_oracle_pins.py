@@ -1,0 +1,380 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test would catch a plausible slip in the oracle (a dropped bond, a wrong
+sign, a swapped index, a wrong colour order, a <= for a <, a wrong generator
+constant).  None of them re-types the oracle's own formula: they use published
+check values, an independent library implementation (numpy's MT19937), closed
+forms, invariants, exact enumeration, and the table printed in Sec. 4.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+M31 = 2**31 - 1
+
+
+def _rand_lattice(ext, seed):
+    rng = np.random.default_rng(seed)
+    V = ext[0] * ext[1] * ext[2]
+    s = rng.choice(np.array([-1, 1], dtype=np.int8), V)
+    J = rng.choice(np.array([-1, 1], dtype=np.int8), (3, V))
+    return s, J
+
+
+def _coords(ext):
+    Lx, Ly, Lz = ext
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    return x.ravel(), y.ravel(), z.ravel()
+
+
+def _site_bonds(ext, x, y, z):
+    """(direction, owner index) of the six bonds of site (x, y, z)."""
+    Lx, Ly, Lz = ext
+    i = lambda a, b, c: (a % Lx) + Lx * ((b % Ly) + Ly * (c % Lz))
+    return [(0, i(x, y, z)), (1, i(x, y, z)), (2, i(x, y, z)),
+            (0, i(x - 1, y, z)), (1, i(x, y - 1, z)), (2, i(x, y, z - 1))]
+
+
+# ---------------------------------------------------------------------------
+# Generators
+# ---------------------------------------------------------------------------
+def test_minstd_published_check_value():
+    # Park & Miller (CACM 1988): from seed 1 the 10000th state is 1043618065.
+    r = 1
+    for _ in range(10000):
+        r = oracle.minstd_next(r)
+    assert r == 1043618065
+
+
+def test_minstd_per_site_streams_jump_ahead():
+    # The draw of sweep t at a site with seed s is 16807^(t+1) s mod (2^31 - 1):
+    # computed here by modular exponentiation, not by iterating.
+    L = 4
+    seeds = si.minstd_seeds(L, 11, 0)
+    lat = oracle.OracleLattice((L, L, L), 1, si.coupling_words(L, 1), si.spin_words(L, 11, 0),
+                               oracle.MINSTD, seeds)
+    for t in range(5):
+        R = lat.draws()
+        a = pow(16807, t + 1, M31)
+        expect = (a * seeds.astype(object)) % M31
+        assert np.array_equal(R.astype(object), expect)
+
+
+def test_mt19937_published_check_values():
+    # init_genrand(5489): first output 3499211612; the 10000th is 4123659995
+    # (the check value the C++ standard library specifies for mt19937).
+    out = oracle.mt19937_outputs(5489, 10000)
+    assert int(out[0]) == 3499211612
+    assert int(out[9999]) == 4123659995
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**31 + 7, 2**32 - 1])
+def test_mt19937_matches_numpy_legacy(seed):
+    # numpy's legacy RandomState seeds MT19937 with init_genrand for an integer
+    # seed: an independent implementation; 2000 outputs cross three twists.
+    ref = np.random.RandomState(seed)._bit_generator.random_raw(2000).astype(np.uint32)
+    assert np.array_equal(oracle.mt19937_outputs(seed, 2000), ref)
+
+
+def test_mt19937_column_stream_layout():
+    # Site (x, y, z) takes output t*Lz + z of its column's stream at sweep t.
+    ext = (4, 2, 6)
+    Lx, Ly, Lz = ext
+    seeds = np.array([17, 99, 3, 12345, 7, 8, 2**32 - 5, 42], dtype=np.uint32)
+    V = Lx * Ly * Lz
+    lat = oracle.OracleLattice(ext, 1, np.zeros((3, V), np.uint64), np.zeros(V, np.uint64),
+                               oracle.MT19937, seeds)
+    Rs = [lat.draws() for _ in range(3)]
+    for c, sd in enumerate(seeds):
+        ref = np.random.RandomState(int(sd))._bit_generator.random_raw(3 * Lz).astype(np.uint32)
+        x, y = c % Lx, c // Lx
+        for t in range(3):
+            for z in range(Lz):
+                assert Rs[t][x + Lx * (y + Ly * z)] == ref[t * Lz + z]
+
+
+# ---------------------------------------------------------------------------
+# Thresholds
+# ---------------------------------------------------------------------------
+def test_thresholds_edge_cases():
+    assert list(oracle.thresholds(0.0, oracle.MINSTD)) == [M31] * 3
+    assert list(oracle.thresholds(0.0, oracle.MT19937)) == [2**32] * 3
+    assert list(oracle.thresholds(math.inf, oracle.MINSTD)) == [0, 0, 0]
+    # exp(-4 beta) = 1/2 exactly in binary64 for beta = ln2/4
+    b = math.log(2.0) / 4
+    assert int(oracle.thresholds(b, oracle.MT19937)[0]) == 2**31
+    assert int(oracle.thresholds(b, oracle.MINSTD)[0]) == 2**30  # ceil((2^31-1)/2)
+    assert int(oracle.thresholds(b, oracle.MT19937)[1]) == 2**30
+    for beta in (0.1, 0.5, 1 / 0.7, 1 / 1.1, 3.0):
+        T = [int(v) for v in oracle.thresholds(beta, oracle.MINSTD)]
+        assert T[0] >= T[1] >= T[2] >= 0
+        for k in range(3):
+            p = math.exp(-4 * (k + 1) * beta)
+            assert abs(T[k] - M31 * p) <= 1.0
+
+
+# ---------------------------------------------------------------------------
+# Update rule: ΔE table of Sec. 4, the printed mask, and energy differences
+# ---------------------------------------------------------------------------
+def _load_dE_table(golden_dir):
+    rows = []
+    with open(os.path.join(golden_dir, "paper_dE_table.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                a, b = line.split()
+                rows.append((int(a), int(b)))
+    return dict(rows)
+
+
+def _paper_mask(v, r, T):
+    """The flip mask printed in Sec. 4, evaluated on one bit: v = sum of bond bits."""
+    s2, s1, s0 = (v >> 2) & 1, (v >> 1) & 1, v & 1
+    c12, c8, c4 = int(r < T[2]), int(r < T[1]), int(r < T[0])
+    return c12 | (1 - s2) | ((s2 & (s2 ^ s1)) & (c8 | (c4 & (1 - s0))))
+
+
+def test_dE_table_and_mask_against_oracle(golden_dir):
+    table = _load_dE_table(golden_dir)
+    assert sorted(table) == list(range(7))
+    ext = (4, 4, 4)
+    V = 64
+    beta = 0.4
+    T = [int(v) for v in oracle.thresholds(beta, oracle.MINSTD)]
+    site = (1, 2, 1)  # x+y+z even: red
+    i0 = site[0] + 4 * (site[1] + 4 * site[2])
+    bonds = _site_bonds(ext, *site)
+    for v in range(7):
+        s = np.ones(V, dtype=np.int8)
+        J = np.ones((3, V), dtype=np.int8)
+        for k, (d, owner) in enumerate(bonds):
+            J[d, owner] = 1 if k < v else -1  # all spins +1: J=+1 satisfied
+        # the table's dE is the oracle's energy difference of the flip
+        U0 = oracle.unsatisfied(ext, s, J)
+        s2 = s.copy()
+        s2[i0] = -1
+        assert 2 * (oracle.unsatisfied(ext, s2, J) - U0) == table[v]
+        # the oracle's decision equals the paper's mask in every R region
+        for r in (0, T[2] - 1, T[2], T[1] - 1, T[1], T[0] - 1, T[0], M31 - 1):
+            R = np.full(V, M31 - 1, dtype=np.uint32)
+            R[i0] = r
+            new = oracle.sweep_once(ext, s, J, R, np.array(T, dtype=np.uint64))
+            assert int(new[i0] != s[i0]) == _paper_mask(v, r, T), (v, r)
+
+
+@pytest.mark.parametrize("ext,beta,seed", [((4, 4, 6), 0.9, 5), ((2, 4, 4), 0.3, 6), ((6, 2, 2), 2.0, 7)])
+def test_update_rule_is_metropolis_on_energy_differences(ext, beta, seed):
+    """Red sites decide on the old state, blue sites on the state after the red
+    pass; each flips iff dE <= 0 or R < T(dE), dE from the energy function."""
+    s, J = _rand_lattice(ext, seed)
+    V = s.size
+    T = [int(v) for v in oracle.thresholds(beta, oracle.MINSTD)]
+    rng = np.random.default_rng(seed + 100)
+    cand = np.array([1, max(T[2] - 1, 1), T[2] + 1, T[1] - 1, T[1], T[0] - 1, T[0], M31 - 1], dtype=np.int64)
+    R = rng.choice(cand, V).astype(np.uint32)
+    new = oracle.sweep_once(ext, s, J, R, np.array(T, dtype=np.uint64))
+    x, y, z = _coords(ext)
+    red = (x + y + z) % 2 == 0
+
+    def expect(state, i):
+        U0 = oracle.unsatisfied(ext, state, J)
+        s2 = state.copy()
+        s2[i] = -s2[i]
+        dE = 2 * (oracle.unsatisfied(ext, s2, J) - U0)
+        return dE <= 0 or R[i] < T[dE // 4 - 1]
+
+    for i in np.flatnonzero(red):
+        assert (new[i] != s[i]) == expect(s, i)
+    mid = s.copy()
+    mid[red] = new[red]
+    for i in np.flatnonzero(~red):
+        assert (new[i] != mid[i]) == expect(mid, i)
+
+
+# ---------------------------------------------------------------------------
+# Energy function: closed forms and symmetries
+# ---------------------------------------------------------------------------
+def test_energy_closed_forms():
+    ext = (4, 6, 2)
+    V = 48
+    up = np.ones(V, dtype=np.int8)
+    ferro = np.ones((3, V), dtype=np.int8)
+    assert oracle.unsatisfied(ext, up, ferro) == 0
+    assert oracle.unsatisfied(ext, up, -ferro) == 3 * V
+    x, y, z = _coords(ext)
+    neel = np.where((x + y + z) % 2 == 0, 1, -1).astype(np.int8)
+    assert oracle.unsatisfied(ext, neel, ferro) == 3 * V
+    # one flipped spin in a ferromagnet breaks its six bonds
+    one = up.copy()
+    one[7] = -1
+    assert oracle.unsatisfied(ext, one, ferro) == 6
+
+
+def test_energy_symmetries():
+    ext = (4, 4, 4)
+    s, J = _rand_lattice(ext, 3)
+    U = oracle.unsatisfied(ext, s, J)
+    assert oracle.unsatisfied(ext, (-s).astype(np.int8), J) == U          # global flip
+    assert oracle.unsatisfied(ext, s, (-J).astype(np.int8)) == 3 * 64 - U  # J -> -J: E -> -E
+    g = np.random.default_rng(4).choice(np.array([-1, 1], dtype=np.int8), 64)
+    Lx, Ly, Lz = ext
+    x, y, z = _coords(ext)
+    nb = [((x + 1) % Lx) + Lx * (y + Ly * z), x + Lx * (((y + 1) % Ly) + Ly * z), x + Lx * (y + Ly * ((z + 1) % Lz))]
+    Jg = np.stack([J[d] * g * g[nb[d]] for d in range(3)]).astype(np.int8)
+    assert oracle.unsatisfied(ext, (s * g).astype(np.int8), Jg) == U     # gauge invariance
+
+
+# ---------------------------------------------------------------------------
+# Dynamics: beta = 0, T = 0, gauge, splitting, bit planes
+# ---------------------------------------------------------------------------
+def _seeded(L, S, prng, cseed=1, sseed=2, r=0):
+    seeds = si.minstd_seeds(L, sseed, r) if prng == oracle.MINSTD else si.mt_seeds(L, sseed, r)
+    return oracle.OracleLattice((L, L, L), S, si.coupling_words(L, cseed), si.spin_words(L, sseed, r), prng, seeds)
+
+
+@pytest.mark.parametrize("prng", [oracle.MINSTD, oracle.MT19937])
+def test_beta_zero_accepts_everything(prng):
+    lat = _seeded(6, 64, prng)
+    s0 = lat.s.copy()
+    U0 = lat.unsatisfied()
+    for t in range(1, 4):
+        lat.sweep(1, 0.0)
+        assert np.array_equal(lat.s, s0 if t % 2 == 0 else -s0)
+        assert np.array_equal(lat.unsatisfied(), U0)
+
+
+def test_zero_temperature_is_monotone_and_stream_independent():
+    a = _seeded(8, 16, oracle.MINSTD, sseed=2)
+    b = _seeded(8, 16, oracle.MINSTD, sseed=2)
+    b.state = si.minstd_seeds(8, 999, 3).copy()  # other random numbers, same start
+    prev = a.unsatisfied()
+    for _ in range(6):
+        a.sweep(1, math.inf)
+        b.sweep(1, math.inf)
+        U = a.unsatisfied()
+        assert np.all(U <= prev)
+        prev = U
+        assert np.array_equal(a.s, b.s)
+
+
+@pytest.mark.parametrize("prng", [oracle.MINSTD, oracle.MT19937])
+def test_gauge_symmetry_of_the_dynamics(prng):
+    L = 6
+    Jw = si.coupling_words(L, 5)
+    Sw = si.spin_words(L, 6, 0)
+    g = si.gauge_words(L, 77)
+    x, y, z = _coords((L, L, L))
+    nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z), x + L * (y + L * ((z + 1) % L))]
+    Jg = np.stack([Jw[d] ^ g ^ g[nb[d]] for d in range(3)])
+    seeds = si.minstd_seeds(L, 6, 0) if prng == oracle.MINSTD else si.mt_seeds(L, 6, 0)
+    a = oracle.OracleLattice((L, L, L), 64, Jw, Sw, prng, seeds)
+    b = oracle.OracleLattice((L, L, L), 64, Jg, Sw ^ g, prng, seeds)
+    for _ in range(4):
+        a.sweep(1, 0.8)
+        b.sweep(1, 0.8)
+        assert np.array_equal(b.words(), a.words() ^ g)
+
+
+def test_call_splitting_and_run_agree():
+    a = _seeded(6, 8, oracle.MT19937)
+    b = _seeded(6, 8, oracle.MT19937)
+    a.sweep(5, 1.2)
+    for _ in range(5):
+        b.sweep(1, 1.2)
+    c = _seeded(6, 8, oracle.MT19937)
+    c.run(2, 1.2)
+    c.run(3, 1.2)
+    assert np.array_equal(a.s, b.s) and np.array_equal(a.s, c.s)
+
+
+def test_sample_is_its_bit_plane():
+    L = 6
+    full = _seeded(L, 64, oracle.MINSTD)
+    full.sweep(3, 0.9)
+    for j in (0, 17, 63):
+        Jw = (si.coupling_words(L, 1) >> np.uint64(j)) & np.uint64(1)
+        Sw = (si.spin_words(L, 2, 0) >> np.uint64(j)) & np.uint64(1)
+        one = oracle.OracleLattice((L, L, L), 1, Jw, Sw, oracle.MINSTD, si.minstd_seeds(L, 2, 0))
+        one.sweep(3, 0.9)
+        assert np.array_equal(one.s[0], full.s[j])
+
+
+def test_overlap_limits():
+    a = _seeded(4, 64, oracle.MINSTD)
+    b = _seeded(4, 64, oracle.MINSTD)
+    assert np.all(oracle.overlap(a, b) == 1.0)
+    b.s = (-b.s).astype(np.int8)
+    assert np.all(oracle.overlap(a, b) == -1.0)
+
+
+# ---------------------------------------------------------------------------
+# Exact enumeration and the Gibbs law of the dynamics (Eq. 3)
+# ---------------------------------------------------------------------------
+def test_enumeration_closed_forms():
+    ext = (2, 2, 4)
+    V = 16
+    _, J = _rand_lattice(ext, 8)
+    # beta = 0: <E> = 0 and <E^2> = sum over pairs of bonds joining the same two sites
+    e1, e2, hist = oracle.gibbs(ext, J, 0.0)
+    assert abs(e1) < 1e-12
+    Lx, Ly, Lz = ext
+    x, y, z = _coords(ext)
+    ends = []
+    for d, (dx, dy, dz) in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+        k = ((x + dx) % Lx) + Lx * (((y + dy) % Ly) + Ly * ((z + dz) % Lz))
+        for i in range(V):
+            ends.append((frozenset((i, int(k[i]))), int(J[d, i])))
+    expect = sum(ja * jb for (pa, ja) in ends for (pb, jb) in ends if pa == pb)
+    assert abs(e2 - expect) < 1e-9
+    assert abs(hist.sum() - 1) < 1e-12
+    # an unfrustrated (gauge-ferromagnetic) coupling set has E_min = -3V
+    g = np.random.default_rng(9).choice(np.array([-1, 1], dtype=np.int8), V)
+    nb = [((x + 1) % Lx) + Lx * (y + Ly * z), x + Lx * (((y + 1) % Ly) + Ly * z), x + Lx * (y + Ly * ((z + 1) % Lz))]
+    Jg = np.stack([g * g[nb[d]] for d in range(3)]).astype(np.int8)
+    e1, _, hist = oracle.gibbs(ext, Jg, 8.0)
+    assert abs(e1 + 3 * V) < 1e-6 and hist[0] > 1 - 1e-6
+    # gauge invariance of the whole distribution
+    _, _, h1 = oracle.gibbs(ext, J, 0.7)
+    Jgg = np.stack([J[d] * g * g[nb[d]] for d in range(3)]).astype(np.int8)
+    _, _, h2 = oracle.gibbs(ext, Jgg, 0.7)
+    assert np.allclose(h1, h2, atol=1e-14)
+
+
+def _binned_mean_err(series, nbins=40):
+    n = len(series) // nbins * nbins
+    b = series[:n].reshape(nbins, -1).mean(axis=1)
+    return series[:n].mean(), b.std(ddof=1) / math.sqrt(nbins)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1 / 0.7, 2.0])
+def test_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
+    """Time averages of E and E^2 of the oracle's dynamics agree with exact
+    enumeration within 5 standard errors (binned), for 8 coupling samples."""
+    ext = (2, 2, 4)
+    V = 16
+    S = 8
+    rng = np.random.default_rng(2024)
+    Jw = rng.integers(0, 2**63, size=(3, V), dtype=np.uint64)
+    Sw = rng.integers(0, 2**63, size=V, dtype=np.uint64)
+    seeds = rng.integers(1, M31 - 1, size=V, dtype=np.uint32)
+    lat = oracle.OracleLattice(ext, S, Jw, Sw, oracle.MINSTD, seeds)
+    lat.run(2000, beta)
+    U = lat.run(60000, beta, record=True)
+    E = 2.0 * U - 3.0 * V
+    n = E.shape[0]
+    for j in range(S):
+        e1, e2, hist = oracle.gibbs(ext, lat.J[j], beta)
+        # the binned error cannot be smaller than that of n independent draws
+        var1 = e2 - e1 * e1
+        Eu = 2.0 * np.arange(3 * V + 1) - 3.0 * V
+        var2 = float((hist * Eu**4).sum()) - e2 * e2
+        m, err = _binned_mean_err(E[:, j])
+        err = max(err, math.sqrt(max(var1, 0.0) / n))
+        assert abs(m - e1) < 5 * err, (j, m, e1, err)
+        m2, err2 = _binned_mean_err(E[:, j] ** 2)
+        err2 = max(err2, math.sqrt(max(var2, 0.0) / n))
+        assert abs(m2 - e2) < 5 * err2, (j, m2, e2, err2)
