@@ -1,0 +1,158 @@
+/*
+ * sg.h -- C ABI of libsg, a gfx950 (MI355X) engine for the checkerboard Metropolis
+ * dynamics of the 3D Edwards-Anderson spin glass with bimodal couplings, using
+ * asynchronous multispin coding: 64 disorder samples per uint64 word, one bit per
+ * spin, one random number per site word shared by its 64 samples.
+ *
+ * Method: M. Lulli, M. Bernaschi, G. Parisi, "Highly optimized simulations on single-
+ * and multi-GPU systems of 3D Ising spin glass", arXiv:1411.0127.
+ *   Hamiltonian and couplings ........ Sec. 1, Eqs. (1)-(2)
+ *   red/blue checkerboard, balance ... Sec. 1
+ *   MINSTD, MT19937 .................. Sec. 3
+ *   Metropolis, integer thresholds,
+ *   bit encoding, bond bits, bit sum,
+ *   flip mask ........................ Sec. 4
+ *   psFlip ........................... Sec. 4.1
+ *
+ * Data layout on the device (one cubic lattice of side L, V = L^3 sites,
+ * site index i = x + L*(y + L*z)):
+ *   spins     uint64 S[V]     bit j = sample j, 1 <=> sigma = +1 (Sec. 4 bit mapping)
+ *   couplings uint64 J[3][V]  J[d][i] = bond (i, i + d^), d = x,y,z; bit j = 1 <=> J = -1
+ * One sweep = every red site (x+y+z even) once, then every blue site once.
+ *
+ * Random streams (this library's convention; all keyed, so results do not depend
+ * on the kernel, tile shape or launch split):
+ *   SG_MINSTD  one MINSTD stream per site and replica; in sweep t (t = 0, 1, ...)
+ *              site i draws 16807^(t+1) * seed_i mod (2^31 - 1);
+ *   SG_MT19937 one MT19937 stream per x-y column and replica, seeded with
+ *              init_genrand; in sweep t the site at height z draws the column's
+ *              output number t*L + z.
+ * The seeds, the initial spins and (unless given) the couplings come from the
+ * SplitMix64 keyed generator documented with the seeded-input module
+ * (Steele, Lea, Flood 2014), evaluated on the device.
+ *
+ * Acceptance: a proposal with dE > 0 is accepted iff R < T(dE) with
+ * T(dE) = ceil(R_range * exp(-beta * dE)), R_range = 2^31 - 1 (MINSTD) or 2^32
+ * (MT19937); dE <= 0 is always accepted (Sec. 4, P_flip and EXP4/EXP8/EXP12).
+ *
+ * Conventions of every entry point:
+ *   - returns SG_OK (0) or a negative SG_E* code; sg_last_error() then holds a
+ *     message (per thread);
+ *   - device memory belongs to the caller: a lattice lives inside one caller
+ *     buffer of at least sg_footprint() bytes, which the library never frees;
+ *     it must stay allocated until sg_destroy() of this lattice and of every
+ *     replica created from it;
+ *   - host pointers are borrowed for the duration of the call;
+ *   - work is queued on the hipStream_t given at creation (NULL = default
+ *     stream); calls that return data to the host synchronise that stream;
+ *   - a handle must not be used from two threads at once.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_lattice sg_lattice;
+
+enum { SG_MINSTD = 0, SG_MT19937 = 1 };
+
+enum {
+    SG_OK = 0,
+    SG_EINVAL = -1,    /* bad argument: L odd or out of [2, 2048], nsamples not in [1,64],
+                          beta < 0 or NaN, unknown prng, NULL where a pointer is needed,
+                          buffer too small, wrong element count */
+    SG_ENOMEM = -2,    /* host allocation failed */
+    SG_EDEVICE = -3,   /* a HIP call or kernel launch failed (message has the HIP error) */
+    SG_EMISMATCH = -4  /* lattices that must match (size, samples, couplings) do not */
+};
+
+/* Sweep kernels.  Every kernel gives bit-identical spins; they differ in speed.
+ * SG_KERNEL_TWOPASS: one launch per colour, in place, one lane per site word.
+ * SG_KERNEL_FUSED:   one launch per sweep; each workgroup marches a tile of x-y
+ *                    columns along z, red plane k then blue plane k-1, in-plane
+ *                    neighbours exchanged through LDS, old/new spins in two
+ *                    buffers and tile-edge red sites recomputed by both tiles. */
+enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2 };
+
+/* Bytes of device memory a lattice needs.  own_couplings = 1 for a lattice that
+ * holds its couplings (sg_lattice_create), 0 for a replica that reads another
+ * lattice's (sg_lattice_create_replica). */
+int sg_footprint(int L, int prng, int own_couplings, size_t *dev_bytes);
+
+/* Create a lattice of side L (even, 2..2048) holding nsamples (1..64) samples.
+ * J_host: 3*L^3 coupling words in the layout above, or NULL to generate them
+ *         from coupling_seed (Sec. 1: J = +-1 with probability 1/2 each);
+ * spin_seed, replica: key the initial spins and the random streams;
+ * dev_buf, dev_bytes: caller's device buffer (>= sg_footprint(L, prng, 1));
+ * stream: hipStream_t for all work on this lattice, or NULL.
+ * Bits j >= nsamples are simulated like the others and ignored by observables. */
+int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host,
+                      uint64_t coupling_seed, uint64_t spin_seed, uint32_t replica,
+                      void *dev_buf, size_t dev_bytes, void *stream, sg_lattice **out);
+
+/* A replica (Sec. 2: same couplings, its own initial spins and evolution):
+ * shares base's coupling buffer, draws its spins and streams from
+ * (spin_seed, replica).  dev_buf >= sg_footprint(L, prng, 0). */
+int sg_lattice_create_replica(const sg_lattice *base, uint64_t spin_seed, uint32_t replica,
+                              void *dev_buf, size_t dev_bytes, void *stream,
+                              sg_lattice **out);
+
+/* Queue nsweeps >= 0 sweeps at inverse temperature beta >= 0 (beta = +inf allowed:
+ * only dE <= 0 is accepted). */
+int sg_sweep(sg_lattice *lat, int64_t nsweeps, double beta);
+
+/* The same for n lattices that share one coupling buffer (replicas), moving the
+ * couplings once per sweep for all of them when the kernel allows; all must have
+ * the same L, prng and stream. */
+int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double beta);
+
+/* Observables of Sec. 1, Eq. (1), per sample j < nsamples:
+ * unsat[j] = number of unsatisfied bonds (-J s_i s_k = +1) among the 3V bonds,
+ * e_per_spin[j] = (2*unsat[j] - 3V) / V.  Either output may be NULL. */
+int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin);
+
+/* Two-replica overlap per sample: ndiff[j] = number of sites where the replicas
+ * differ, q[j] = 1 - 2*ndiff[j]/V.  a, b: same L and nsamples. */
+int sg_overlap(const sg_lattice *a, const sg_lattice *b, int64_t *ndiff, double *q);
+
+/* Spins as +-1 bytes, sample-major: out[j*V + i], j < nsamples; n = nsamples*V. */
+int sg_get_spins(const sg_lattice *lat, int8_t *out, size_t n);
+
+/* Raw spin words (n = V) and coupling words (n = 3V). */
+int sg_get_words(const sg_lattice *lat, uint64_t *out, size_t n);
+int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n);
+int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n);
+
+/* The random number each site used in the last sweep (n = V), for checks. */
+int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n);
+
+/* Integer thresholds T[k-1] for dE = 4k, k = 1,2,3 (Sec. 4, EXP4/EXP8/EXP12). */
+int sg_thresholds(double beta, int prng, uint64_t T[3]);
+
+/* Sweeps done so far; setting it (resume from a checkpoint) also moves the
+ * MINSTD streams; for MT19937 only a lattice that has not swept may be moved
+ * forward, by regenerating its streams up to that point. */
+int64_t sg_sweep_count(const sg_lattice *lat);
+int sg_set_sweep_count(sg_lattice *lat, int64_t t);
+
+/* Choose the sweep kernel and, for SG_KERNEL_FUSED, its tile: tile_x pairs of
+ * sites per row (x extent 2*tile_x), tile_y rows, z_chunk planes per workgroup
+ * (0 = default).  Invalid shapes return SG_EINVAL and change nothing. */
+int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk);
+
+/* Release the handle (never the caller's device buffer). */
+int sg_destroy(sg_lattice *lat);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

@@ -1,0 +1,150 @@
+// Initialisation and random-stream kernels of libsg (gfx950).
+//  - couplings, spins and MINSTD seeds from the SplitMix64 keyed generator;
+//  - MT19937 (Matsumoto-Nishimura 1998) per-column streams: init_genrand, and a
+//    per-sweep fill of the L draws every column needs (Sec. 3 of the paper: a
+//    per-stream MT19937 whose state is laid out so that consecutive streams are
+//    consecutive in memory, word k of stream c at k*ncols + c).
+#include "sg_internal.h"
+
+namespace sg {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n, int per_thread = 1)
+{
+    int64_t g = (n + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+    if (g > 65536)
+        g = 65536;
+    if (g < 1)
+        g = 1;
+    return (int)g;
+}
+
+__global__ void k_init_couplings(uint64_t *__restrict__ J, int64_t V, uint64_t key)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t n = 1ull + 3ull * (uint64_t)i;
+        J[i] = sm_out(key, n);
+        J[V + i] = sm_out(key, n + 1);
+        J[2 * V + i] = sm_out(key, n + 2);
+    }
+}
+
+__global__ void k_init_spins(uint64_t *__restrict__ S, int64_t V, uint64_t key)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
+        S[i] = sm_out(key, 1ull + (uint64_t)i);
+}
+
+__global__ void k_init_minstd(uint32_t *__restrict__ seeds, int64_t V, uint64_t key)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
+        seeds[i] = minstd_seed_from(sm_out(key, 1ull + (uint64_t)i));
+}
+
+__global__ void k_minstd_draws(const uint32_t *__restrict__ seeds, uint32_t *__restrict__ R, int64_t V, uint32_t a)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
+        R[i] = minstd_jump(a, seeds[i]);
+}
+
+// init_genrand of column c's stream with seed = low 32 bits of its keyed word.
+__global__ void k_init_mt(uint32_t *__restrict__ st, int ncols, uint64_t key)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols)
+        return;
+    uint32_t v = (uint32_t)sm_out(key, 1ull + (uint64_t)c);
+    st[c] = v;
+    for (int k = 1; k < kMtN; ++k) {
+        v = 1812433253u * (v ^ (v >> 30)) + (uint32_t)k;
+        st[(size_t)k * ncols + c] = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t mt_temper(uint32_t y)
+{
+    y ^= y >> 11;
+    y ^= (y << 7) & 0x9D2C5680u;
+    y ^= (y << 15) & 0xEFC60000u;
+    y ^= y >> 18;
+    return y;
+}
+
+// Draws of sweep t: column c produces its outputs t*L .. t*L + L - 1 and writes
+// output t*L + z to R[z*L*L + c].  The twist is done one word at a time, right
+// before the word is output: word i of a new block is computed from word i and
+// i+1 of the previous block and word i+397 (already renewed when i+397 >= 624
+// wraps), which is exactly the order of the sequential in-place twist.
+__global__ void k_mt_fill(uint32_t *__restrict__ st, uint32_t *__restrict__ R, int L, int64_t t)
+{
+    const int ncols = L * L;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols)
+        return;
+    int i = (int)(((int64_t)t * L) % kMtN);
+    uint32_t cur = st[(size_t)i * ncols + c];
+    for (int z = 0; z < L; ++z) {
+        const int i1 = (i + 1 == kMtN) ? 0 : i + 1;
+        int im = i + 397;
+        im = (im >= kMtN) ? im - kMtN : im;
+        const uint32_t nxt = st[(size_t)i1 * ncols + c];
+        const uint32_t y = (cur & 0x80000000u) | (nxt & 0x7FFFFFFFu);
+        uint32_t v = st[(size_t)im * ncols + c] ^ (y >> 1);
+        v ^= (y & 1u) ? 0x9908B0DFu : 0u;
+        st[(size_t)i * ncols + c] = v;
+        R[(size_t)z * ncols + c] = mt_temper(v);
+        // word i1 is renewed next, and its value before that renewal is the one
+        // just read (for i1 = 0 that is the word renewed at the start of this
+        // block, which is what the next block's first step reads)
+        cur = nxt;
+        i = i1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s)
+{
+    const int64_t V = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_init_couplings, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, J, V, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s)
+{
+    const int64_t V = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_init_spins, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, S, V, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_minstd(uint32_t *seeds, int L, uint64_t key, hipStream_t s)
+{
+    const int64_t V = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_init_minstd, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, seeds, V, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_minstd_draws(const uint32_t *seeds, uint32_t *R, int L, uint32_t a, hipStream_t s)
+{
+    const int64_t V = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_minstd_draws, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, seeds, R, V, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s)
+{
+    const int ncols = L * L;
+    hipLaunchKernelGGL(k_init_mt, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s, state, ncols, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_mt_fill(uint32_t *state, uint32_t *rbuf, int L, int64_t t, hipStream_t s)
+{
+    const int ncols = L * L;
+    hipLaunchKernelGGL(k_mt_fill, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s, state, rbuf, L, t);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,599 @@
+// Host side of the libsg C ABI (include/sg.h): argument checks, the memory carve
+// of a lattice inside the caller's device buffer, per-sweep host scalars
+// (thresholds, MINSTD multiplier), kernel choice and launches, readbacks.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+thread_local std::string g_err;
+constexpr uint32_t kM31 = 0x7FFFFFFFu;
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool valid_L(int L) { return L >= 2 && L <= 2048 && (L % 2) == 0; }
+bool valid_prng(int prng) { return prng == SG_MINSTD || prng == SG_MT19937; }
+
+// 16807^(t+1) mod (2^31 - 1) by square and multiply.
+uint32_t minstd_multiplier(int64_t t)
+{
+    uint64_t result = 1, base = 16807;
+    uint64_t e = (uint64_t)t + 1;
+    while (e) {
+        if (e & 1)
+            result = (result * base) % kM31;
+        base = (base * base) % kM31;
+        e >>= 1;
+    }
+    return (uint32_t)result;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return SG_OK;
+    return hip_fail(e, what);
+}
+
+uint64_t g_coupling_id = 1;  // identity of caller-provided coupling sets
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SG_EDEVICE;
+}
+
+Carve carve(int L, int prng, bool own_J)
+{
+    const size_t V = (size_t)L * L * L;
+    Carve c{};
+    size_t off = 0;
+    c.spins0 = off;
+    off = align_up(off + 8 * V);
+    c.spins1 = off;
+    off = align_up(off + 8 * V);
+    c.J = off;
+    if (own_J)
+        off = align_up(off + 24 * V);
+    c.seeds = off;
+    if (prng == SG_MINSTD)
+        off = align_up(off + 4 * V);
+    c.mt_state = off;
+    if (prng == SG_MT19937)
+        off = align_up(off + (size_t)4 * kMtN * L * L);
+    c.rbuf = off;
+    if (prng == SG_MT19937)
+        off = align_up(off + 4 * V);
+    c.scratch = off;
+    off = align_up(off + 8 * ((size_t)kMaxReduceBlocks * 64 + 64));
+    c.total = off;
+    return c;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+namespace {
+
+// The handle handed out: the lattice plus the identity of its couplings
+// (lattices with equal ids hold the same couplings).
+struct Handle : sg_lattice {
+    uint64_t coupling_id = 0;
+};
+
+Handle *H(sg_lattice *p) { return static_cast<Handle *>(p); }
+const Handle *H(const sg_lattice *p) { return static_cast<const Handle *>(p); }
+
+int init_streams(sg_lattice *lat)
+{
+    hipError_t e = launch_init_spins(lat->spins[0], lat->L, lat->key_spin, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init spins");
+    if (lat->prng == SG_MINSTD)
+        e = launch_init_minstd(lat->seeds, lat->L, lat->key_minstd, lat->stream);
+    else
+        e = launch_init_mt(lat->mt_state, lat->L, lat->key_mt, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init streams");
+    return SG_OK;
+}
+
+int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32_t replica, void *dev_buf,
+          size_t dev_bytes, void *stream, bool own_J)
+{
+    const Carve c = carve(L, prng, own_J);
+    if (dev_bytes < c.total)
+        return fail(SG_EINVAL, "device buffer too small: need " + std::to_string(c.total) + " bytes");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
+        return fail(SG_EINVAL, "device buffer must be 256-byte aligned");
+    lat->L = L;
+    lat->nsamples = nsamples;
+    lat->prng = prng;
+    lat->V = (int64_t)L * L * L;
+    lat->spin_seed = spin_seed;
+    lat->replica = replica;
+    lat->key_spin = derive_key(spin_seed, kTagSpin, replica);
+    lat->key_minstd = derive_key(spin_seed, kTagMinstd, replica);
+    lat->key_mt = derive_key(spin_seed, kTagMt, replica);
+    lat->base = static_cast<uint8_t *>(dev_buf);
+    lat->bytes = dev_bytes;
+    lat->spins[0] = reinterpret_cast<uint64_t *>(lat->base + c.spins0);
+    lat->spins[1] = reinterpret_cast<uint64_t *>(lat->base + c.spins1);
+    if (own_J)
+        lat->J = reinterpret_cast<uint64_t *>(lat->base + c.J);
+    lat->seeds = prng == SG_MINSTD ? reinterpret_cast<uint32_t *>(lat->base + c.seeds) : nullptr;
+    lat->mt_state = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.mt_state) : nullptr;
+    lat->rbuf = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.rbuf) : nullptr;
+    lat->scratch = reinterpret_cast<uint64_t *>(lat->base + c.scratch);
+    lat->stream = static_cast<hipStream_t>(stream);
+    lat->cur = 0;
+    lat->t = 0;
+    return SG_OK;
+}
+
+bool use_fused(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
+{
+    if (lat->kernel == SG_KERNEL_TWOPASS)
+        return false;
+    if (lat->tile_x > 0) {
+        tx = lat->tile_x;
+        ty = lat->tile_y;
+        zc = lat->z_chunk;
+    } else {
+        fused_default_shape(lat->L, nrep, tx, ty, zc);
+    }
+    return fused_shape_ok(lat->L, nrep, tx, ty, zc);
+}
+
+// One sweep of n (1 or 2) lattices that share couplings, stream and sweep count.
+int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
+{
+    sg_lattice *l0 = lats[0];
+    const int64_t t = l0->t;
+    hipError_t e;
+    if (l0->prng == SG_MT19937) {
+        for (int r = 0; r < n; ++r) {
+            e = launch_mt_fill(lats[r]->mt_state, lats[r]->rbuf, lats[r]->L, t, l0->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "MT19937 fill");
+        }
+    }
+    SweepArgs a{};
+    a.J = l0->J;
+    a.nrep = n;
+    a.L = l0->L;
+    a.prng = l0->prng;
+    a.minstd_a = minstd_multiplier(t);
+    a.T = T;
+    for (int r = 0; r < n; ++r) {
+        a.src[r] = lats[r]->spins[lats[r]->cur];
+        a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
+        a.rnd[r] = l0->prng == SG_MINSTD ? lats[r]->seeds : lats[r]->rbuf;
+    }
+    int tx = 0, ty = 0, zc = 0;
+    if (use_fused(l0, n, tx, ty, zc)) {
+        e = launch_sweep_fused(a, tx, ty, zc, l0->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "fused sweep launch");
+        for (int r = 0; r < n; ++r)
+            lats[r]->cur ^= 1;
+    } else {
+        e = launch_sweep_twopass(a, l0->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "two-pass sweep launch");
+    }
+    for (int r = 0; r < n; ++r)
+        lats[r]->t += 1;
+    return SG_OK;
+}
+
+int check_beta(double beta)
+{
+    if (std::isnan(beta) || beta < 0)
+        return fail(SG_EINVAL, "beta must be >= 0");
+    return SG_OK;
+}
+
+int count_to_host(sg_lattice *lat, int nblocks, int64_t *out)
+{
+    uint64_t *out64 = lat->scratch + (size_t)kMaxReduceBlocks * 64;
+    hipError_t e = launch_reduce_partials(lat->scratch, nblocks, out64, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "reduce launch");
+    uint64_t host[64];
+    e = hipMemcpyAsync(host, out64, sizeof(host), hipMemcpyDeviceToHost, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "readback");
+    e = hipStreamSynchronize(lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "synchronize");
+    for (int j = 0; j < 64; ++j)
+        out[j] = (int64_t)host[j];
+    return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sg_last_error(void) { return g_err.c_str(); }
+
+int sg_footprint(int L, int prng, int own_couplings, size_t *dev_bytes)
+{
+    if (!valid_L(L))
+        return fail(SG_EINVAL, "L must be even and in [2, 2048]");
+    if (!valid_prng(prng))
+        return fail(SG_EINVAL, "unknown prng");
+    if (!dev_bytes)
+        return fail(SG_EINVAL, "dev_bytes is NULL");
+    *dev_bytes = carve(L, prng, own_couplings != 0).total;
+    return SG_OK;
+}
+
+int sg_thresholds(double beta, int prng, uint64_t T[3])
+{
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    if (!valid_prng(prng))
+        return fail(SG_EINVAL, "unknown prng");
+    if (!T)
+        return fail(SG_EINVAL, "T is NULL");
+    // Sec. 4: accept dE > 0 iff R < R_range * exp(-beta dE); rounding the product
+    // up makes the integer comparison exact.
+    const double range = prng == SG_MINSTD ? 2147483647.0 : 4294967296.0;
+    for (int k = 1; k <= 3; ++k) {
+        const double dE = 4.0 * k;
+        const double prob = std::exp(-(beta * dE));
+        T[k - 1] = (uint64_t)std::ceil(range * prob);
+    }
+    return SG_OK;
+}
+
+int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host, uint64_t coupling_seed,
+                      uint64_t spin_seed, uint32_t replica, void *dev_buf, size_t dev_bytes, void *stream,
+                      sg_lattice **out)
+{
+    if (!out)
+        return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!valid_L(L))
+        return fail(SG_EINVAL, "L must be even and in [2, 2048]");
+    if (nsamples < 1 || nsamples > 64)
+        return fail(SG_EINVAL, "nsamples must be in [1, 64]");
+    if (!valid_prng(prng))
+        return fail(SG_EINVAL, "unknown prng");
+    if (!dev_buf)
+        return fail(SG_EINVAL, "dev_buf is NULL");
+    Handle *lat = new (std::nothrow) Handle();
+    if (!lat)
+        return fail(SG_ENOMEM, "out of host memory");
+    int rc = setup(lat, L, nsamples, prng, spin_seed, replica, dev_buf, dev_bytes, stream, true);
+    if (rc != SG_OK) {
+        delete lat;
+        return rc;
+    }
+    lat->coupling_seed = coupling_seed;
+    hipError_t e;
+    if (J_host) {
+        e = hipMemcpyAsync(lat->J, J_host, (size_t)24 * lat->V, hipMemcpyHostToDevice, lat->stream);
+        lat->coupling_id = (g_coupling_id++) << 1;  // even: caller's couplings
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);  // J_host is only borrowed
+    } else {
+        lat->key_j = derive_key(coupling_seed, kTagJ, 0);
+        e = launch_init_couplings(lat->J, L, lat->key_j, lat->stream);
+        lat->coupling_id = (coupling_seed << 1) | 1;  // odd: generated from a seed
+    }
+    if (e != hipSuccess) {
+        delete lat;
+        return hip_fail(e, "couplings");
+    }
+    rc = init_streams(lat);
+    if (rc == SG_OK) {
+        e = hipStreamSynchronize(lat->stream);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "create");
+    }
+    if (rc != SG_OK) {
+        delete lat;
+        return rc;
+    }
+    *out = lat;
+    return SG_OK;
+}
+
+int sg_lattice_create_replica(const sg_lattice *base, uint64_t spin_seed, uint32_t replica, void *dev_buf,
+                              size_t dev_bytes, void *stream, sg_lattice **out)
+{
+    if (!out || !base)
+        return fail(SG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!dev_buf)
+        return fail(SG_EINVAL, "dev_buf is NULL");
+    Handle *lat = new (std::nothrow) Handle();
+    if (!lat)
+        return fail(SG_ENOMEM, "out of host memory");
+    int rc = setup(lat, base->L, base->nsamples, base->prng, spin_seed, replica, dev_buf, dev_bytes, stream, false);
+    if (rc != SG_OK) {
+        delete lat;
+        return rc;
+    }
+    lat->J = base->J;
+    lat->J_owner = base->J_owner ? base->J_owner : base;
+    lat->coupling_seed = base->coupling_seed;
+    lat->coupling_id = H(base)->coupling_id;
+    lat->kernel = base->kernel;
+    lat->tile_x = base->tile_x;
+    lat->tile_y = base->tile_y;
+    lat->z_chunk = base->z_chunk;
+    rc = init_streams(lat);
+    if (rc == SG_OK) {
+        hipError_t e = hipStreamSynchronize(lat->stream);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "create replica");
+    }
+    if (rc != SG_OK) {
+        delete lat;
+        return rc;
+    }
+    *out = lat;
+    return SG_OK;
+}
+
+int sg_sweep(sg_lattice *lat, int64_t nsweeps, double beta)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    uint64_t T[3];
+    sg_thresholds(beta, lat->prng, T);
+    const Thresholds th{T[0], T[1], T[2]};
+    for (int64_t i = 0; i < nsweeps; ++i) {
+        int rc = sweep_once(&lat, 1, th);
+        if (rc != SG_OK)
+            return rc;
+    }
+    return SG_OK;
+}
+
+int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double beta)
+{
+    if (!lats || n < 1)
+        return fail(SG_EINVAL, "no lattices");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    for (int r = 0; r < n; ++r) {
+        if (!lats[r])
+            return fail(SG_EINVAL, "NULL lattice");
+        if (lats[r]->L != lats[0]->L || lats[r]->prng != lats[0]->prng || lats[r]->J != lats[0]->J ||
+            lats[r]->stream != lats[0]->stream || lats[r]->t != lats[0]->t)
+            return fail(SG_EMISMATCH, "replicas must share L, prng, couplings, stream and sweep count");
+        for (int q = 0; q < r; ++q)
+            if (lats[q] == lats[r])
+                return fail(SG_EINVAL, "a lattice appears twice");
+    }
+    uint64_t T[3];
+    sg_thresholds(beta, lats[0]->prng, T);
+    const Thresholds th{T[0], T[1], T[2]};
+    for (int64_t i = 0; i < nsweeps; ++i)
+        for (int r = 0; r < n; r += 2) {
+            const int m = (n - r) >= 2 ? 2 : 1;
+            int rc = sweep_once(lats + r, m, th);
+            if (rc != SG_OK)
+                return rc;
+        }
+    return SG_OK;
+}
+
+int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    int nblocks = 0;
+    hipError_t e = launch_count_unsat(lat->spins[lat->cur], lat->J, lat->L, lat->scratch, nblocks, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "energy launch");
+    int64_t U[64];
+    int rc = count_to_host(lat, nblocks, U);
+    if (rc != SG_OK)
+        return rc;
+    for (int j = 0; j < lat->nsamples; ++j) {
+        if (unsat)
+            unsat[j] = U[j];
+        if (e_per_spin)
+            e_per_spin[j] = (2.0 * (double)U[j] - 3.0 * (double)lat->V) / (double)lat->V;
+    }
+    return SG_OK;
+}
+
+int sg_overlap(const sg_lattice *a, const sg_lattice *b, int64_t *ndiff, double *q)
+{
+    if (!a || !b)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (a->L != b->L || a->nsamples != b->nsamples || H(a)->coupling_id != H(b)->coupling_id)
+        return fail(SG_EMISMATCH, "overlap needs lattices of equal size, samples and couplings");
+    sg_lattice *wa = const_cast<sg_lattice *>(a);
+    if (b->stream != a->stream) {
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "synchronize");
+    }
+    int nblocks = 0;
+    hipError_t e = launch_count_diff(a->spins[a->cur], b->spins[b->cur], a->V, wa->scratch, nblocks, a->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "overlap launch");
+    int64_t N[64];
+    int rc = count_to_host(wa, nblocks, N);
+    if (rc != SG_OK)
+        return rc;
+    for (int j = 0; j < a->nsamples; ++j) {
+        if (ndiff)
+            ndiff[j] = N[j];
+        if (q)
+            q[j] = 1.0 - 2.0 * (double)N[j] / (double)a->V;
+    }
+    return SG_OK;
+}
+
+int sg_get_words(const sg_lattice *lat, uint64_t *out, size_t n)
+{
+    if (!lat || !out)
+        return fail(SG_EINVAL, "NULL argument");
+    if (n != (size_t)lat->V)
+        return fail(SG_EINVAL, "n must be L^3");
+    hipError_t e = hipMemcpyAsync(out, lat->spins[lat->cur], 8 * n, hipMemcpyDeviceToHost, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    return check_hip(e, "get words");
+}
+
+int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n)
+{
+    if (!lat || !in)
+        return fail(SG_EINVAL, "NULL argument");
+    if (n != (size_t)lat->V)
+        return fail(SG_EINVAL, "n must be L^3");
+    hipError_t e = hipMemcpyAsync(lat->spins[lat->cur], in, 8 * n, hipMemcpyHostToDevice, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    return check_hip(e, "set words");
+}
+
+int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n)
+{
+    if (!lat || !out)
+        return fail(SG_EINVAL, "NULL argument");
+    if (n != (size_t)(3 * lat->V))
+        return fail(SG_EINVAL, "n must be 3 L^3");
+    hipError_t e = hipMemcpyAsync(out, lat->J, 8 * n, hipMemcpyDeviceToHost, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    return check_hip(e, "get couplings");
+}
+
+int sg_get_spins(const sg_lattice *lat, int8_t *out, size_t n)
+{
+    if (!lat || !out)
+        return fail(SG_EINVAL, "NULL argument");
+    const size_t V = (size_t)lat->V;
+    if (n != (size_t)lat->nsamples * V)
+        return fail(SG_EINVAL, "n must be nsamples * L^3");
+    std::vector<uint64_t> w;
+    try {
+        w.resize(V);
+    } catch (...) {
+        return fail(SG_ENOMEM, "out of host memory");
+    }
+    int rc = sg_get_words(lat, w.data(), V);
+    if (rc != SG_OK)
+        return rc;
+    for (int j = 0; j < lat->nsamples; ++j) {
+        int8_t *o = out + (size_t)j * V;
+        for (size_t i = 0; i < V; ++i)
+            o[i] = ((w[i] >> j) & 1ull) ? 1 : -1;
+    }
+    return SG_OK;
+}
+
+int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
+{
+    if (!lat || !out)
+        return fail(SG_EINVAL, "NULL argument");
+    if (n != (size_t)lat->V)
+        return fail(SG_EINVAL, "n must be L^3");
+    if (lat->t == 0)
+        return fail(SG_EINVAL, "no sweep done yet");
+    hipError_t e;
+    if (lat->prng == SG_MT19937) {
+        e = hipMemcpyAsync(out, lat->rbuf, 4 * n, hipMemcpyDeviceToHost, lat->stream);
+    } else {
+        // MINSTD draws are a function of (seed, sweep): evaluate the last sweep's on
+        // the host from the device's seeds, with the device's own jump function.
+        std::vector<uint32_t> seeds(n);
+        e = hipMemcpyAsync(seeds.data(), lat->seeds, 4 * n, hipMemcpyDeviceToHost, lat->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);
+        if (e == hipSuccess) {
+            const uint32_t a = minstd_multiplier(lat->t - 1);
+            for (size_t i = 0; i < n; ++i)
+                out[i] = minstd_jump(a, seeds[i]);
+        }
+        return check_hip(e, "get randoms");
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    return check_hip(e, "get randoms");
+}
+
+int64_t sg_sweep_count(const sg_lattice *lat) { return lat ? lat->t : -1; }
+
+int sg_set_sweep_count(sg_lattice *lat, int64_t t)
+{
+    if (!lat || t < 0)
+        return fail(SG_EINVAL, "bad argument");
+    if (lat->prng == SG_MINSTD) {
+        lat->t = t;
+        return SG_OK;
+    }
+    if (t < lat->t || lat->t != 0)
+        return fail(SG_EINVAL, "an MT19937 lattice can only be moved forward before its first sweep");
+    for (int64_t k = 0; k < t; ++k) {
+        hipError_t e = launch_mt_fill(lat->mt_state, lat->rbuf, lat->L, k, lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "MT19937 fill");
+    }
+    lat->t = t;
+    return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
+}
+
+int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (kind != SG_KERNEL_AUTO && kind != SG_KERNEL_TWOPASS && kind != SG_KERNEL_FUSED)
+        return fail(SG_EINVAL, "unknown kernel");
+    if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0 || z_chunk != 0)) {
+        if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
+            return fail(SG_EINVAL, "invalid fused tile shape");
+    }
+    lat->kernel = kind;
+    if (kind == SG_KERNEL_FUSED) {
+        lat->tile_x = tile_x;
+        lat->tile_y = tile_y;
+        lat->z_chunk = z_chunk;
+    } else {
+        lat->tile_x = lat->tile_y = lat->z_chunk = 0;
+    }
+    return SG_OK;
+}
+
+int sg_destroy(sg_lattice *lat)
+{
+    delete H(lat);
+    return SG_OK;
+}
+
+}  // extern "C"

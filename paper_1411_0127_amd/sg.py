@@ -1,0 +1,221 @@
+"""Python binding of libsg (include/sg.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP library; PyTorch only provides the device
+buffer each lattice lives in and the stream its work is queued on.  If the
+library is missing this module raises at import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsg.so")
+
+SG_MINSTD = 0
+SG_MT19937 = 1
+SG_OK = 0
+SG_EINVAL = -1
+SG_ENOMEM = -2
+SG_EDEVICE = -3
+SG_EMISMATCH = -4
+SG_KERNEL_AUTO = 0
+SG_KERNEL_TWOPASS = 1
+SG_KERNEL_FUSED = 2
+
+PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937}
+KERNELS = {"auto": SG_KERNEL_AUTO, "twopass": SG_KERNEL_TWOPASS, "fused": SG_KERNEL_FUSED}
+
+# Every function the header declares, with its ctypes signature.
+_p = ctypes.c_void_p
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+_d = ctypes.c_double
+SIGNATURES = {
+    "sg_footprint": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "sg_lattice_create": (_i, [_i, _i, _i, _p, _u64, _u64, _u32, _p, _sz, _p, ctypes.POINTER(_p)]),
+    "sg_lattice_create_replica": (_i, [_p, _u64, _u32, _p, _sz, _p, ctypes.POINTER(_p)]),
+    "sg_sweep": (_i, [_p, _i64, _d]),
+    "sg_sweep_replicas": (_i, [ctypes.POINTER(_p), _i, _i64, _d]),
+    "sg_energy": (_i, [_p, _p, _p]),
+    "sg_overlap": (_i, [_p, _p, _p, _p]),
+    "sg_get_spins": (_i, [_p, _p, _sz]),
+    "sg_get_words": (_i, [_p, _p, _sz]),
+    "sg_set_words": (_i, [_p, _p, _sz]),
+    "sg_get_couplings": (_i, [_p, _p, _sz]),
+    "sg_get_randoms": (_i, [_p, _p, _sz]),
+    "sg_thresholds": (_i, [_d, _i, _p]),
+    "sg_sweep_count": (_i64, [_p]),
+    "sg_set_sweep_count": (_i, [_p, _i64]),
+    "sg_set_kernel": (_i, [_p, _i, _i, _i, _i]),
+    "sg_destroy": (_i, [_p]),
+    "sg_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libsg.so not found at {LIB_PATH}; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class SGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsg error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != SG_OK:
+        raise SGError(rc, lib.sg_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def thresholds(beta: float, prng="minstd") -> np.ndarray:
+    T = np.zeros(3, dtype=np.uint64)
+    _check(lib.sg_thresholds(float(beta), PRNGS[prng], _ptr(T)))
+    return T
+
+
+def footprint(L: int, prng="minstd", own_couplings: bool = True) -> int:
+    n = _sz()
+    _check(lib.sg_footprint(int(L), PRNGS[prng], int(bool(own_couplings)), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+class Lattice:
+    """One replica of up to 64 coded samples of a cubic L^3 lattice on the GPU."""
+
+    def __init__(self, L: int, nsamples: int = 64, prng="minstd", coupling_seed: int = 1, spin_seed: int = 2,
+                 replica: int = 0, couplings: Optional[np.ndarray] = None, device=None, stream=None,
+                 _base: "Optional[Lattice]" = None):
+        torch = _torch()
+        self.L = int(L)
+        self.nsamples = int(nsamples)
+        self.prng = PRNGS[prng]
+        self.V = self.L ** 3
+        self.device = torch.device(device if device is not None else "cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._base = _base
+        self.nbytes = footprint(self.L, self.prng, own_couplings=_base is None)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        h = _p()
+        sptr = _p(stream.cuda_stream)
+        if _base is None:
+            jp = None
+            if couplings is not None:
+                self._J = np.ascontiguousarray(couplings, dtype=np.uint64)
+                if self._J.size != 3 * self.V:
+                    raise ValueError("couplings must hold 3*L^3 words")
+                jp = _ptr(self._J)
+            _check(lib.sg_lattice_create(self.L, self.nsamples, self.prng, jp, int(coupling_seed) & (2**64 - 1),
+                                         int(spin_seed) & (2**64 - 1), int(replica), _p(self.buf.data_ptr()),
+                                         self.nbytes, sptr, ctypes.byref(h)))
+        else:
+            _check(lib.sg_lattice_create_replica(_base.handle, int(spin_seed) & (2**64 - 1), int(replica),
+                                                 _p(self.buf.data_ptr()), self.nbytes, sptr, ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def replica_of(cls, base: "Lattice", spin_seed: int, replica: int, stream=None) -> "Lattice":
+        return cls(base.L, base.nsamples, base.prng, spin_seed=spin_seed, replica=replica, device=base.device,
+                   stream=stream if stream is not None else base.stream, _base=base)
+
+    # -- dynamics -----------------------------------------------------------------
+    def sweep(self, n: int, beta: float):
+        _check(lib.sg_sweep(self.handle, int(n), float(beta)))
+
+    def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0):
+        _check(lib.sg_set_kernel(self.handle, KERNELS[kind] if isinstance(kind, str) else int(kind),
+                                 int(tile_x), int(tile_y), int(z_chunk)))
+
+    @property
+    def t(self) -> int:
+        return int(lib.sg_sweep_count(self.handle))
+
+    def set_sweep_count(self, t: int):
+        _check(lib.sg_set_sweep_count(self.handle, int(t)))
+
+    # -- observables ------------------------------------------------------------------
+    def energy(self):
+        """(unsatisfied-bond counts int64[nsamples], energy per spin float64[nsamples])."""
+        U = np.zeros(self.nsamples, dtype=np.int64)
+        e = np.zeros(self.nsamples, dtype=np.float64)
+        _check(lib.sg_energy(self.handle, _ptr(U), _ptr(e)))
+        return U, e
+
+    def spins(self) -> np.ndarray:
+        out = np.empty((self.nsamples, self.V), dtype=np.int8)
+        _check(lib.sg_get_spins(self.handle, _ptr(out), out.size))
+        return out
+
+    def words(self) -> np.ndarray:
+        out = np.empty(self.V, dtype=np.uint64)
+        _check(lib.sg_get_words(self.handle, _ptr(out), out.size))
+        return out
+
+    def set_words(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.uint64)
+        _check(lib.sg_set_words(self.handle, _ptr(w), w.size))
+
+    def couplings(self) -> np.ndarray:
+        out = np.empty((3, self.V), dtype=np.uint64)
+        _check(lib.sg_get_couplings(self.handle, _ptr(out), out.size))
+        return out
+
+    def randoms(self) -> np.ndarray:
+        out = np.empty(self.V, dtype=np.uint32)
+        _check(lib.sg_get_randoms(self.handle, _ptr(out), out.size))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib.sg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sweep_replicas(lats: Sequence[Lattice], n: int, beta: float):
+    arr = (_p * len(lats))(*[l.handle for l in lats])
+    _check(lib.sg_sweep_replicas(arr, len(lats), int(n), float(beta)))
+
+
+def overlap(a: Lattice, b: Lattice):
+    nd = np.zeros(a.nsamples, dtype=np.int64)
+    q = np.zeros(a.nsamples, dtype=np.float64)
+    _check(lib.sg_overlap(a.handle, b.handle, _ptr(nd), _ptr(q)))
+    return nd, q

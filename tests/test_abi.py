@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the header
+declares, and its host-only functions (sizes, thresholds, argument checks) behave.
+No GPU work is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "sg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def sgmod():
+    from paper_1411_0127_amd import sg
+
+    return sg
+
+
+def test_library_exports_every_declared_symbol(sgmod):
+    names = _declared()
+    assert len(names) >= 15
+    raw = ctypes.CDLL(sgmod.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), f"libsg.so does not export {n}"
+    assert sorted(sgmod.SIGNATURES) == names, "binding and header disagree"
+
+
+def test_library_is_built_for_gfx950(sgmod):
+    data = open(sgmod.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_thresholds_agree_with_oracle(sgmod, prng):
+    p = oracle.MINSTD if prng == "minstd" else oracle.MT19937
+    rng = np.random.default_rng(1)
+    betas = [0.0, math.inf, math.log(2) / 4, 1 / 0.7, 1 / 1.1] + list(rng.uniform(0, 3, 200))
+    for b in betas:
+        assert np.array_equal(sgmod.thresholds(b, prng), oracle.thresholds(b, p)), b
+
+
+def test_host_argument_checks(sgmod):
+    with pytest.raises(sgmod.SGError) as e:
+        sgmod.footprint(15)
+    assert e.value.code == sgmod.SG_EINVAL
+    with pytest.raises(sgmod.SGError):
+        sgmod.footprint(0)
+    with pytest.raises(sgmod.SGError):
+        sgmod.footprint(4096)
+    with pytest.raises(sgmod.SGError):
+        sgmod.thresholds(float("nan"))
+    with pytest.raises(sgmod.SGError):
+        sgmod.thresholds(-1.0)
+    h = ctypes.c_void_p()
+    rc = sgmod.lib.sg_lattice_create(16, 65, 0, None, 1, 2, 0, ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h))
+    assert rc == sgmod.SG_EINVAL and not h.value
+    rc = sgmod.lib.sg_lattice_create(16, 64, 0, None, 1, 2, 0, ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert rc == sgmod.SG_EINVAL and b"too small" in sgmod.lib.sg_last_error()
+
+
+def test_footprint_sizes(sgmod):
+    V = 256**3
+    own = sgmod.footprint(256, "minstd", True)
+    rep = sgmod.footprint(256, "minstd", False)
+    # two spin buffers (8 B each), three coupling words, a 4-byte seed per site
+    assert own - rep >= 24 * V
+    assert rep >= 16 * V + 4 * V
+    mt = sgmod.footprint(256, "mt19937", False)
+    assert mt >= 16 * V + 4 * V + 4 * 624 * 256 * 256

@@ -1,0 +1,286 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Spins are compared bit for bit (integer work: the tolerance is zero), energies and
+overlaps as exact integers.  Each test prints the case it runs before touching the
+GPU, so that a failing run names it.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1411_0127_amd import sg as mod
+
+    return mod
+
+
+PRNG = {"minstd": oracle.MINSTD, "mt19937": oracle.MT19937}
+
+
+def oracle_for(L, S, prng, cseed, sseed, r=0, J=None, words=None):
+    seeds = si.minstd_seeds(L, sseed, r) if PRNG[prng] == oracle.MINSTD else si.mt_seeds(L, sseed, r)
+    return oracle.OracleLattice((L, L, L), S, si.coupling_words(L, cseed) if J is None else J,
+                                si.spin_words(L, sseed, r) if words is None else words, PRNG[prng], seeds)
+
+
+def mask(S):
+    return np.uint64((1 << S) - 1) if S < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def assert_same(gpu_words, ref, S, what):
+    m = mask(S)
+    got = gpu_words & m
+    want = ref.words() & m
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{what}: {bad.size} site words differ, first at site {bad[0]}")
+
+
+# ---------------------------------------------------------------------------
+# inputs and random numbers
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 4, 16, 18])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_device_inputs_and_draws_match(sg, L, prng):
+    say("inputs", L, prng)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=5, spin_seed=6, replica=3)
+    assert np.array_equal(lat.couplings(), si.coupling_words(L, 5))
+    assert np.array_equal(lat.words(), si.spin_words(L, 6, 3))
+    ref = oracle_for(L, 64, prng, 5, 6, 3)
+    for t in range(3):
+        lat.sweep(1, 0.8)
+        R = ref.draws()
+        ref.sweep_with(R, 0.8)
+        assert np.array_equal(lat.randoms(), R), f"draws of sweep {t}"
+
+
+@pytest.mark.parametrize("L,nsweeps", [(8, 170), (18, 80)])
+def test_mt19937_streams_across_twists(sg, L, nsweeps):
+    # 8 or 18 draws per column per sweep: the 624-word blocks end inside sweeps
+    say("mt twists", L, nsweeps)
+    lat = sg.Lattice(L, 64, "mt19937", coupling_seed=1, spin_seed=9)
+    ref = oracle_for(L, 64, "mt19937", 1, 9)
+    for t in range(nsweeps):
+        lat.sweep(1, 0.6)
+        ref.sweep(1, 0.6)
+    assert np.array_equal(lat.randoms(), ref.last_R)
+    assert_same(lat.words(), ref, 64, f"MT19937 L={L} after {nsweeps} sweeps")
+
+
+# ---------------------------------------------------------------------------
+# the small configuration: L=16, one sample, energy after every sweep
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
+def test_single_sample_L16_1000_sweeps_every_sweep(sg, kernel):
+    say("L16 1 sample 1000 sweeps", kernel)
+    L, beta = 16, 1 / 0.7
+    lat = sg.Lattice(L, 1, "minstd", coupling_seed=1, spin_seed=2)
+    lat.set_kernel(kernel)
+    ref = oracle_for(L, 1, "minstd", 1, 2)
+    for t in range(1000):
+        lat.sweep(1, beta)
+        ref.sweep(1, beta)
+        U, e = lat.energy()
+        Uo = ref.unsatisfied()
+        assert U[0] == Uo[0], f"energy differs after sweep {t + 1}"
+        assert e[0] == (2.0 * Uo[0] - 3 * L**3) / L**3
+        assert_same(lat.words(), ref, 1, f"sweep {t + 1}")
+
+
+# ---------------------------------------------------------------------------
+# 64 samples, both kernels, both generators, every sweep
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 4, 8, 16, 18, 32])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
+def test_64_samples_every_sweep(sg, L, prng, kernel):
+    say("64 samples", L, prng, kernel)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=3, spin_seed=4)
+    lat.set_kernel(kernel)
+    ref = oracle_for(L, 64, prng, 3, 4)
+    for t, beta in enumerate([0.9, 0.9, 0.9, 0.3, 2.0, 1 / 1.1]):
+        lat.sweep(1, beta)
+        ref.sweep(1, beta)
+        assert_same(lat.words(), ref, 64, f"L={L} {prng} {kernel} sweep {t + 1}")
+    assert np.array_equal(lat.energy()[0], ref.unsatisfied())
+
+
+@pytest.mark.parametrize("L,tiles", [
+    (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 28, 11)), (34, (17, 27, 34)),
+    (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)),
+])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_fused_tile_shapes_and_ragged_edges(sg, L, tiles, prng):
+    say("tiles", L, tiles, prng)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=8, spin_seed=21)
+    lat.set_kernel("fused", *tiles)
+    ref = oracle_for(L, 64, prng, 8, 21)
+    for t in range(4):
+        lat.sweep(1, 0.75)
+        ref.sweep(1, 0.75)
+        assert_same(lat.words(), ref, 64, f"L={L} tiles={tiles} sweep {t + 1}")
+
+
+# ---------------------------------------------------------------------------
+# replicas, overlap, energies
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [8, 16, 30])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
+def test_two_replicas_in_one_pass(sg, L, prng, kernel):
+    say("replicas", L, prng, kernel)
+    a = sg.Lattice(L, 64, prng, coupling_seed=7, spin_seed=100, replica=0)
+    a.set_kernel(kernel)
+    b = sg.Lattice.replica_of(a, spin_seed=100, replica=1)
+    ra = oracle_for(L, 64, prng, 7, 100, 0)
+    rb = oracle_for(L, 64, prng, 7, 100, 1)
+    for t in range(5):
+        sg.sweep_replicas([a, b], 1, 1 / 0.7)
+        ra.sweep(1, 1 / 0.7)
+        rb.sweep(1, 1 / 0.7)
+        assert_same(a.words(), ra, 64, f"replica 0 sweep {t + 1}")
+        assert_same(b.words(), rb, 64, f"replica 1 sweep {t + 1}")
+    nd, q = sg.overlap(a, b)
+    assert np.array_equal(nd, oracle.ndiff(ra, rb))
+    assert np.array_equal(q, 1.0 - 2.0 * oracle.ndiff(ra, rb) / L**3)
+    nd, q = sg.overlap(a, a)
+    assert np.all(nd == 0) and np.all(q == 1.0)
+    assert np.array_equal(a.energy()[0], ra.unsatisfied())
+    assert np.array_equal(b.energy()[0], rb.unsatisfied())
+
+
+def test_overlap_of_a_spin_flipped_copy(sg):
+    say("overlap -1")
+    a = sg.Lattice(12, 64, "minstd", coupling_seed=1, spin_seed=2)
+    b = sg.Lattice.replica_of(a, spin_seed=2, replica=0)
+    b.set_words(~a.words())
+    nd, q = sg.overlap(a, b)
+    assert np.all(nd == 12**3) and np.all(q == -1.0)
+
+
+def test_overlap_rejects_different_couplings(sg):
+    a = sg.Lattice(8, 64, "minstd", coupling_seed=1, spin_seed=2)
+    b = sg.Lattice(8, 64, "minstd", coupling_seed=3, spin_seed=2)
+    with pytest.raises(sg.SGError) as e:
+        sg.overlap(a, b)
+    assert e.value.code == sg.SG_EMISMATCH
+
+
+# ---------------------------------------------------------------------------
+# limits and properties
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
+def test_beta_zero_flips_every_spin(sg, kernel):
+    say("beta 0", kernel)
+    lat = sg.Lattice(20, 64, "minstd", coupling_seed=1, spin_seed=2)
+    lat.set_kernel(kernel)
+    w0 = lat.words()
+    U0 = lat.energy()[0]
+    for t in range(1, 4):
+        lat.sweep(1, 0.0)
+        assert np.array_equal(lat.words(), w0 if t % 2 == 0 else ~w0)
+        assert np.array_equal(lat.energy()[0], U0)
+
+
+def test_zero_temperature_monotone_and_stream_free(sg):
+    say("T=0")
+    a = sg.Lattice(24, 64, "mt19937", coupling_seed=4, spin_seed=5, replica=0)
+    b = sg.Lattice.replica_of(a, spin_seed=999, replica=7)
+    b.set_words(a.words())
+    prev = a.energy()[0]
+    for _ in range(5):
+        a.sweep(1, math.inf)
+        b.sweep(1, math.inf)
+        U = a.energy()[0]
+        assert np.all(U <= prev)
+        prev = U
+        assert np.array_equal(a.words(), b.words())
+
+
+def test_sweep_splitting_kernels_and_resume(sg):
+    say("splitting")
+    L = 64
+    ref = sg.Lattice(L, 64, "minstd", coupling_seed=2, spin_seed=3)
+    ref.sweep(9, 0.85)
+    two = sg.Lattice(L, 64, "minstd", coupling_seed=2, spin_seed=3)
+    two.set_kernel("twopass")
+    two.sweep(4, 0.85)
+    mid = two.words()
+    two.set_kernel("fused")
+    two.sweep(5, 0.85)
+    assert np.array_equal(two.words(), ref.words())
+    # resume from a checkpoint of spins and the sweep count
+    res = sg.Lattice(L, 64, "minstd", coupling_seed=2, spin_seed=3)
+    res.set_words(mid)
+    res.set_sweep_count(4)
+    res.sweep(5, 0.85)
+    assert np.array_equal(res.words(), ref.words())
+    # MT19937: a fresh lattice can be moved forward, regenerating its streams
+    m1 = sg.Lattice(16, 64, "mt19937", coupling_seed=2, spin_seed=3)
+    m1.sweep(6, 0.85)
+    m2 = sg.Lattice(16, 64, "mt19937", coupling_seed=2, spin_seed=3)
+    m2.sweep(2, 0.85)
+    w = m2.words()
+    m3 = sg.Lattice(16, 64, "mt19937", coupling_seed=2, spin_seed=3)
+    m3.set_sweep_count(2)
+    m3.set_words(w)
+    m3.sweep(4, 0.85)
+    assert np.array_equal(m3.words(), m1.words())
+
+
+def test_gauge_symmetry_at_L64(sg):
+    say("gauge")
+    L = 64
+    J = si.coupling_words(L, 13)
+    g = si.gauge_words(L, 14)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    nb = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z), x + L * (y + L * ((z + 1) % L))]
+    Jg = np.stack([J[d] ^ g ^ g[nb[d]] for d in range(3)])
+    a = sg.Lattice(L, 64, "minstd", couplings=J, spin_seed=15)
+    b = sg.Lattice(L, 64, "minstd", couplings=Jg, spin_seed=15)
+    b.set_words(a.words() ^ g)
+    for _ in range(6):
+        a.sweep(1, 0.9)
+        b.sweep(1, 0.9)
+    assert np.array_equal(b.words(), a.words() ^ g)
+
+
+# ---------------------------------------------------------------------------
+# the L=256 configuration on bit planes the oracle can afford
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_L256_two_replicas_on_two_bit_planes(sg, prng):
+    say("L256", prng)
+    L, beta, nsweeps = 256, 1 / 0.7, 2
+    a = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0)
+    b = sg.Lattice.replica_of(a, spin_seed=2, replica=1)
+    sg.sweep_replicas([a, b], nsweeps, beta)
+    J = si.coupling_words(L, 1)
+    for lat, r in ((a, 0), (b, 1)):
+        w = lat.words()
+        S0 = si.spin_words(L, 2, r)
+        for j in (0, 63):
+            sh = np.uint64(j)
+            seeds = si.minstd_seeds(L, 2, r) if prng == "minstd" else si.mt_seeds(L, 2, r)
+            one = oracle.OracleLattice((L, L, L), 1, (J >> sh) & np.uint64(1), (S0 >> sh) & np.uint64(1),
+                                       PRNG[prng], seeds)
+            one.sweep(nsweeps, beta)
+            assert np.array_equal((w >> sh) & np.uint64(1), one.words()), f"replica {r} plane {j}"
