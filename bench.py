@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+A step is one job of the workload: ``sweeps_per_step`` sweeps of every replica
+(couplings read once per sweep for both replicas), then the energy of each replica
+and their overlap read back.  Lattices, couplings and streams are created on the
+device before the timed region.  The JSON line reports ps per spin flip
+(psFlip, lower is better) as ``value``; the roofline object covers the sweep kernel,
+whose average duration per launch is measured with HIP events on the stream the
+kernel runs on.  ``cpu_baseline`` times the CPU oracle on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ps per spin flip (psFlip) + HBM GB/s, single lattice and batched; job p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # L=256 cube, 64 samples per word, 2 replicas sharing the couplings, T=0.7
+    "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd", variant="mt19937",
+               desc="L=256 periodic cube, 64 samples multispin-coded per uint64, 2 replicas sharing "
+                    "J=+-1 (p=1/2), random start, T=0.7, 1000 sweeps per step, MINSTD per-site streams "
+                    "(MT19937 per-column streams as variant)"),
+    # L=1024 cube, 64 samples, one replica, T=1.1, 100 sweeps
+    "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd", variant=None,
+               desc="L=1024 periodic cube, 64 samples multispin-coded per uint64, J=+-1 (p=1/2), "
+                    "random start, T=1.1, 100 sweeps per step, MINSTD per-site streams"),
+    # L=16 cube, 1 sample, energy after every sweep
+    "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=None,
+               desc="L=16 periodic cube, 1 sample, T=0.7, 1000 sweeps per step, MINSTD"),
+}
+
+
+def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
+    """Bytes one fused sweep launch must move per lattice site.
+
+    Couplings: 3 words read once for all replicas (24 B).  Per replica: the spin
+    word read and written (16 B) and the stream word read: the MINSTD seed (4 B)
+    or the MT19937 draw (4 B) -- the MT19937 fill kernel's state traffic is not
+    part of the sweep kernel.
+    """
+    return 24 + replicas * (16 + 4)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels_sweep_fused.hip", "sg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1411_0127_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{workload}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(args, wl):
+    import torch
+
+    from paper_1411_0127_amd import sg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    L, R, beta, nsw = wl["L"], wl["replicas"], wl["beta"], args.sweeps or wl["sweeps"]
+    V = L**3
+
+    def measure(prng):
+        base = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
+        lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
+        if args.kernel != "auto":
+            for l in lats:
+                l.set_kernel(args.kernel)
+
+        def step(ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            if R == 1:
+                lats[0].sweep(nsw, beta)
+            else:
+                sg.sweep_replicas(lats, nsw, beta)
+            if ev is not None:
+                ev[1].record(stream)
+            out = [l.energy() for l in lats]
+            if R >= 2:
+                out.append(sg.overlap(lats[0], lats[1]))
+            return out
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            last = step(events[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sweep_ms = [a.elapsed_time(b) for a, b in events]
+        res = dict(
+            wall_s=wall,
+            ms_per_step=wall * 1e3 / args.steps,
+            sweep_ms_per_step=sweep_ms,
+            launch_ms=sum(sweep_ms) / (args.steps * nsw),
+            energy_per_spin=[float(x) for x in last[0][1][:4]],
+        )
+        flips = R * 64 * V * nsw
+        res["ps_per_flip"] = res["ms_per_step"] * 1e9 / flips
+        res["sweep_ps_per_flip"] = (sum(sweep_ms) / args.steps) * 1e9 / flips
+        for l in lats:
+            l.close()
+        del lats, base
+        torch.cuda.empty_cache()
+        return res
+
+    main = measure(wl["prng"])
+    variant = measure(wl["variant"]) if (wl.get("variant") and not args.no_variant) else None
+    return main, variant
+
+
+def cpu_baseline(wl, budget_s: float):
+    """The oracle as it stands, single-threaded, on one sample of one replica."""
+    import numpy as np
+
+    import oracle
+    import seeded_inputs as si
+
+    L, beta = wl["L"], wl["beta"]
+    L = min(L, 256)
+    J = si.coupling_words(L, 1) & np.uint64(1)
+    S0 = si.spin_words(L, 2, 0) & np.uint64(1)
+    lat = oracle.OracleLattice((L, L, L), 1, J, S0, oracle.MINSTD, si.minstd_seeds(L, 2, 0))
+    t0 = time.perf_counter()
+    lat.run(1, beta)
+    one = time.perf_counter() - t0
+    n = max(1, min(int(budget_s / max(one, 1e-9)), 2000))
+    t0 = time.perf_counter()
+    lat.run(n, beta)
+    dt = time.perf_counter() - t0
+    return dict(value=dt * 1e12 / (L**3 * n), unit="ps/flip", cores=1, kind="oracle",
+                sample=f"L={L} cube, 1 of the 64 samples, 1 replica, {n} MINSTD sweeps at T={1 / beta:.2f}, "
+                       f"one byte per spin, single thread ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "twopass"])
+    ap.add_argument("--no-variant", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent lattices and replicas would shard by job placement, one GPU each).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    wl = WORKLOADS[args.workload]
+    main_res, variant = run_gpu(args, wl)
+    L, R = wl["L"], wl["replicas"]
+    V = L**3
+    bps = algorithmic_bytes_per_site(wl["prng"], R)
+    achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
+    traffic = load_traffic(args.workload)
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["ps_per_flip"], 6),
+        "unit": "ps/flip",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["desc"],
+            "L": L,
+            "samples_per_word": 64,
+            "replicas": R,
+            "sweeps_per_step": args.sweeps or wl["sweeps"],
+            "prng": wl["prng"],
+            "kernel": args.kernel,
+            "parallelism": "single GPU",
+        },
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "sg::k_fused (one launch per sweep, all replicas)",
+            "bytes_per_site": bps,
+            "launch_ms": round(main_res["launch_ms"], 5),
+        },
+    }
+    if variant is not None:
+        line["variants"] = {
+            wl["variant"]: {
+                "ps_per_flip": round(variant["ps_per_flip"], 6),
+                "ms_per_step": round(variant["ms_per_step"], 4),
+                "sweep_launch_ms": round(variant["launch_ms"], 5),
+            }
+        }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -23,9 +23,12 @@
 // because a site's random number depends only on (stream, site, sweep).  A z-chunk
 // likewise recomputes the red plane below and above it.
 //
-// Launch.  One workgroup per (tile, z-chunk); block ids are spread so that
-// consecutive tiles land on the same XCD (blocks are dealt to the 8 XCDs round
-// robin), where their shared ring rows meet in the same L2.
+// Launch.  One workgroup per (tile, z-chunk), tiles numbered x fastest; block ids
+// are spread so that consecutive tiles land on the same XCD (blocks are dealt to
+// the 8 XCDs round robin), where their shared ring columns meet in the same L2.
+#include <type_traits>
+#include <utility>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -40,6 +43,7 @@ struct FusedParams {
     int TXp, TY, ZC;     // tile: pairs, rows, planes
     int EX, EY;          // lanes per tile row (TXp + 2), tile rows incl. ring (TY + 4)
     int ntx, nty, nzc;   // tiles along x, y, z
+    int WE;              // waves holding the even tile rows
     uint32_t a;          // MINSTD multiplier of this sweep
     Thresholds T;
 };
@@ -51,248 +55,342 @@ struct Plane {
     uint32_t rlo[NREP], rhi[NREP];
 };
 
-template <int NREP>
-__device__ __forceinline__ void load_plane(const FusedParams &p, int64_t off, int64_t V, bool lane, bool full,
-                                           Plane<NREP> &d)
+// Raw buffer access.  A plane of an array gets its own descriptor (base = the
+// plane, size = the plane's bytes), so 32-bit offsets suffice at any L; a lane
+// that must not touch memory uses an offset past the end, which the hardware
+// turns into a dropped store or a zero load.  Every load and store of the march
+// is then issued unconditionally and in a fixed order, which lets the compiler
+// wait for exactly the plane a step needs while later planes are in flight.
+constexpr uint32_t kOOB = 0x80000000u;
+constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer format word of gfx9 descriptors
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, int64_t byte_off, uint32_t nbytes)
 {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(static_cast<const char *>(base)) + byte_off,
+                                             (short)0, (int)nbytes, kRsrcFlags);
+}
+
+__device__ __forceinline__ void ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t &lo, uint64_t &hi)
+{
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+}
+
+__device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t lo, uint64_t hi)
+{
+    u32x4 v;
+    v.x = (uint32_t)lo;
+    v.y = (uint32_t)(lo >> 32);
+    v.z = (uint32_t)hi;
+    v.w = (uint32_t)(hi >> 32);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Per-lane byte offsets inside a plane (kOOB where the lane reads nothing).
+struct Offsets {
+    uint32_t s;   // spins and J[y]: every lane of the tile
+    uint32_t f;   // J[x], J[z]: lanes whose red sites are computed
+    uint32_t r;   // random-stream words (4 bytes per site)
+};
+
+template <int NREP>
+__device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Offsets &o, Plane<NREP> &d)
+{
+    const int64_t LL = (int64_t)p.L * p.L;
+    const int64_t V = LL * p.L;
+    const uint32_t pb = (uint32_t)(LL * 8);
+    const int64_t qo = (int64_t)q * LL * 8;
+#pragma unroll
+    for (int r = 0; r < NREP; ++r)
+        ld_pair(plane_rsrc(p.src[r], qo, pb), o.s, d.slo[r], d.shi[r]);
+    ld_pair(plane_rsrc(p.J, V * 8 + qo, pb), o.s, d.jylo, d.jyhi);
+    ld_pair(plane_rsrc(p.J, qo, pb), o.f, d.jxlo, d.jxhi);
+    ld_pair(plane_rsrc(p.J, 2 * V * 8 + qo, pb), o.f, d.jzlo, d.jzhi);
 #pragma unroll
     for (int r = 0; r < NREP; ++r) {
-        d.slo[r] = 0;
-        d.shi[r] = 0;
-        d.rlo[r] = 0;
-        d.rhi[r] = 0;
-    }
-    d.jxlo = d.jxhi = d.jylo = d.jyhi = d.jzlo = d.jzhi = 0;
-    if (lane) {
-#pragma unroll
-        for (int r = 0; r < NREP; ++r) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(p.src[r] + off);
-            d.slo[r] = v.x;
-            d.shi[r] = v.y;
-        }
-        const ulonglong2 jy = *reinterpret_cast<const ulonglong2 *>(p.J + V + off);
-        d.jylo = jy.x;
-        d.jyhi = jy.y;
-    }
-    if (full) {
-        const ulonglong2 jx = *reinterpret_cast<const ulonglong2 *>(p.J + off);
-        const ulonglong2 jz = *reinterpret_cast<const ulonglong2 *>(p.J + 2 * V + off);
-        d.jxlo = jx.x;
-        d.jxhi = jx.y;
-        d.jzlo = jz.x;
-        d.jzhi = jz.y;
-#pragma unroll
-        for (int r = 0; r < NREP; ++r) {
-            const uint2 rr = *reinterpret_cast<const uint2 *>(p.rnd[r] + off);
-            d.rlo[r] = rr.x;
-            d.rhi[r] = rr.y;
-        }
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[r], (int64_t)q * LL * 4, pb / 2), o.r,
+                                                            0, 0);
+        d.rlo[r] = v.x;
+        d.rhi[r] = v.y;
     }
 }
 
-__device__ __forceinline__ uint64_t pick(bool c, uint64_t a, uint64_t b) { return c ? a : b; }
+// Half H of a pair: 0 = even x, 1 = odd x.
+template <int H, int NREP>
+__device__ __forceinline__ uint64_t sp(const Plane<NREP> &d, int r) { return H ? d.shi[r] : d.slo[r]; }
 
-// Largest workgroup per replica count: two replicas hold twice the spin state, so
-// they get a 512-lane bound and with it up to 256 registers per lane.
-template <int NREP>
-struct MaxThreads {
-    static constexpr int value = NREP == 1 ? 1024 : 512;
+// Lane-constant data of the march.
+struct Lane {
+    int nl, set_words;
+    int me, ixm, ixp, iym, iyp;
+    bool lane;
 };
 
+// Values carried from one step to the next.
+template <int NREP>
+struct Carry {
+    uint64_t jzm2lo, jzm2hi;                 // jz of plane k-2
+    uint64_t jxl, jyulo, jyuhi;              // neighbour couplings of plane k-1 (read at step k-1)
+    uint64_t rn1[NREP], rn2[NREP];           // new red words of planes k-1, k-2
+};
+
+// Step k of the march with the lane's half H = (y + k) & 1 known at compile time:
+// red of plane k (pair half H), then blue of plane k-1 (half H), then publish the
+// words the neighbours need at step k+1.  A, B, C hold planes k-1, k, k+1.
+template <int PRNG, int NREP, int H>
+__device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_blue,
+                                           bool do_publish, const Plane<NREP> &A, const Plane<NREP> &B,
+                                           const Plane<NREP> &C, Carry<NREP> &cy, uint64_t (&rn)[NREP],
+                                           uint64_t (&wlo)[NREP], uint64_t (&whi)[NREP], uint64_t &jxl,
+                                           uint64_t &jyulo, uint64_t &jyuhi)
+{
+    const uint64_t *S = lds + ((k + 2) & 1) * c.set_words;
+    const int ixn = H ? c.ixp : c.ixm;  // lane holding the x-neighbour outside the pair
+    jxl = S[2 * NREP * c.nl + c.ixm];
+    jyulo = S[(2 * NREP + 1) * c.nl + c.iym];
+    jyuhi = S[(2 * NREP + 2) * c.nl + c.iym];
+
+    // ---- red site of plane k: x = 2m + H -----------------------------------------
+    {
+        const uint64_t jxp = H ? B.jxhi : B.jxlo;
+        const uint64_t jxm = H ? B.jxlo : jxl;
+        const uint64_t jyp = H ? B.jyhi : B.jylo;
+        const uint64_t jym = H ? jyuhi : jyulo;
+        const uint64_t jzp = H ? B.jzhi : B.jzlo;
+        const uint64_t jzm = H ? A.jzhi : A.jzlo;
+#pragma unroll
+        for (int r = 0; r < NREP; ++r) {
+            const uint64_t nbx = S[r * c.nl + ixn];
+            const uint64_t nym = S[r * c.nl + c.iym];
+            const uint64_t nyp = S[r * c.nl + c.iyp];
+            const uint64_t s = sp<H>(B, r);
+            const uint64_t other = sp<1 - H>(B, r);
+            const uint64_t nxp = H ? nbx : other;
+            const uint64_t nxm = H ? other : nbx;
+            uint32_t R = H ? B.rhi[r] : B.rlo[r];
+            if (PRNG == SG_MINSTD)
+                R = minstd_jump(p.a, R);
+            rn[r] = s ^ flip_mask(s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r), jxp, jyp, jzp, jxm, jym, jzm, R,
+                                  p.T);
+        }
+    }
+
+    // ---- blue site of plane k-1: same x; its neighbours are all new red ------------
+    if (do_blue) {
+        const uint64_t jxp = H ? A.jxhi : A.jxlo;
+        const uint64_t jxm = H ? A.jxlo : cy.jxl;
+        const uint64_t jyp = H ? A.jyhi : A.jylo;
+        const uint64_t jym = H ? cy.jyuhi : cy.jyulo;
+        const uint64_t jzp = H ? A.jzhi : A.jzlo;
+        const uint64_t jzm = H ? cy.jzm2hi : cy.jzm2lo;
+#pragma unroll
+        for (int r = 0; r < NREP; ++r) {
+            const uint64_t nbx = S[(NREP + r) * c.nl + ixn];
+            const uint64_t nym = S[(NREP + r) * c.nl + c.iym];
+            const uint64_t nyp = S[(NREP + r) * c.nl + c.iyp];
+            const uint64_t s = sp<H>(A, r);
+            const uint64_t nxp = H ? nbx : cy.rn1[r];
+            const uint64_t nxm = H ? cy.rn1[r] : nbx;
+            uint32_t R = H ? A.rhi[r] : A.rlo[r];
+            if (PRNG == SG_MINSTD)
+                R = minstd_jump(p.a, R);
+            const uint64_t bn =
+                s ^ flip_mask(s, nxp, nyp, rn[r], nxm, nym, cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+            wlo[r] = H ? cy.rn1[r] : bn;
+            whi[r] = H ? bn : cy.rn1[r];
+        }
+    }
+
+    // ---- publish: new red of plane k, old blue (half H) and couplings of k+1 ------
+    if (do_publish) {
+        uint64_t *W = lds + ((k + 3) & 1) * c.set_words;
+#pragma unroll
+        for (int r = 0; r < NREP; ++r) {
+            W[r * c.nl + c.me] = sp<H>(C, r);
+            W[(NREP + r) * c.nl + c.me] = rn[r];
+        }
+        W[2 * NREP * c.nl + c.me] = C.jxhi;
+        W[(2 * NREP + 1) * c.nl + c.me] = C.jylo;
+        W[(2 * NREP + 2) * c.nl + c.me] = C.jyhi;
+    }
+}
+
+// Largest workgroup: 512 lanes, so that two workgroups can share a CU.
+constexpr int kMaxThreads = 512;
+
+template <int I>
+using IC = std::integral_constant<int, I>;
+
+// Planes in flight: a ring of NS planes holds k-1 .. k+NS-2 at step k, so a plane is
+// requested NS-3 steps before the step that first reads it.
+// Six planes for one replica; two replicas hold twice the spins, five planes.
+template <int NREP>
+struct Ring {
+    static constexpr int value = NREP == 1 ? 6 : 5;
+};
+
+template <int PRNG, int NREP, int... Is>
+__device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint64_t *lds, std::integer_sequence<int, Is...>);
+
 template <int PRNG, int NREP>
-__global__ __launch_bounds__(MaxThreads<NREP>::value) void k_fused(FusedParams p)
+__global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    const int nl = p.EX * p.EY;
-    // one LDS set: blue_old[NREP][nl], red_new[NREP][nl], jx_hi[nl], jy_lo[nl], jy_hi[nl]
-    const int set_words = nl * (2 * NREP + 3);
+    Lane c;
+    fused_march<PRNG, NREP>(p, c, lds, std::make_integer_sequence<int, Ring<NREP>::value>{});
+}
+
+template <int PRNG, int NREP, int... Is>
+__device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint64_t *lds, std::integer_sequence<int, Is...>)
+{
+    constexpr int NS = sizeof...(Is);
+    // one LDS set: blue_old[NREP], red_new[NREP], jx_hi, jy_lo, jy_hi, each with a slot
+    // per tile lane plus one that threads outside the tile write, so that every
+    // thread publishes without a branch
+    c.nl = p.EX * p.EY + 1;
+    c.set_words = c.nl * (2 * NREP + 3);
 
     // ---- tile of this workgroup ---------------------------------------------
     const int nb = gridDim.x;
     const int b = blockIdx.x;
     const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-    const int ty = tile % p.nty;
-    const int rest = tile / p.nty;
-    const int tx = rest % p.ntx;
-    const int zc = rest / p.ntx;
+    // x fastest: the workgroups that run together on an XCD read one band of rows
+    // across the whole plane, long contiguous runs of every array
+    const int tx = tile % p.ntx;
+    const int rest = tile / p.ntx;
+    const int ty = rest % p.nty;
+    const int zc = rest / p.nty;
     const int TXe = min(p.TXp, p.P - tx * p.TXp);
     const int TYe = min(p.TY, p.L - ty * p.TY);
     const int z0 = zc * p.ZC;
     const int ZCe = min(p.ZC, p.L - z0);
 
-    // ---- lane roles -----------------------------------------------------------
+    // ---- lanes: waves hold tile rows of one parity (even rows first) ---------------
+    // so the pair half a lane updates, (y + k) & 1, is the same across its wave.
     const int lid = threadIdx.x;
-    const bool lane = lid < nl;
-    const int ex = lane ? lid % p.EX : 0;
-    const int ey = lane ? lid / p.EX : 0;
-    const bool full = lane && ey >= 1 && ey <= TYe + 2;  // rows whose red sites are computed
-    const bool inter = lane && ex >= 1 && ex <= TXe && ey >= 2 && ey <= TYe + 1;
+    const int cls = lid < 64 * p.WE ? 0 : 1;
+    const int idx = cls ? lid - 64 * p.WE : lid;
+    const int rows_cls = cls ? p.EY / 2 : (p.EY + 1) / 2;
+    c.lane = idx < p.EX * rows_cls;
+    const int ex = c.lane ? idx % p.EX : 0;
+    const int ey = c.lane ? 2 * (idx / p.EX) + cls : cls;
+    const bool full = c.lane && ey >= 1 && ey <= TYe + 2;  // rows whose red sites are computed
+    const bool inter = c.lane && ex >= 1 && ex <= TXe && ey >= 2 && ey <= TYe + 1;
     const int m = (tx * p.TXp + ex - 1 + p.P) % p.P;
     const int y = (ty * p.TY + ey - 2 + p.L) % p.L;
-    const int me = lane ? lid : 0;
-    const int ixm = ey * p.EX + max(ex - 1, 0);
-    const int ixp = ey * p.EX + min(ex + 1, p.EX - 1);
-    const int iym = max(ey - 1, 0) * p.EX + ex;
-    const int iyp = min(ey + 1, p.EY - 1) * p.EX + ex;
+    c.me = c.lane ? ey * p.EX + ex : c.nl - 1;
+    c.ixm = ey * p.EX + max(ex - 1, 0);
+    c.ixp = ey * p.EX + min(ex + 1, p.EX - 1);
+    c.iym = max(ey - 1, 0) * p.EX + ex;
+    c.iyp = min(ey + 1, p.EY - 1) * p.EX + ex;
+    // parity of the row, the same for the whole wave (L is even, so wrapping keeps it)
+    const int ypar = __builtin_amdgcn_readfirstlane((ty * p.TY + ey) & 1);
 
     const int L = p.L;
     const int64_t LL = (int64_t)L * L;
-    const int64_t V = LL * L;
-    const int64_t col = (int64_t)y * L + 2 * m;
-    auto plane_off = [&](int q) -> int64_t {
-        int qq = q % L;
-        qq = qq < 0 ? qq + L : qq;
-        return (int64_t)qq * LL + col;
+    const uint32_t col = (uint32_t)y * (uint32_t)L + 2u * (uint32_t)m;  // site index within a plane
+    Offsets o;
+    o.s = c.lane ? col * 8u : kOOB;
+    o.f = full ? col * 8u : kOOB;
+    o.r = full ? col * 4u : kOOB;
+    const uint32_t o_st = inter ? col * 8u : kOOB;
+    Offsets o_none;  // past the last plane a chunk needs: loads issued, nothing read
+    o_none.s = o_none.f = o_none.r = kOOB;
+    auto wrap = [&](int q) -> int {  // q lies in [-2, 2L)
+        return q < 0 ? q + L : (q >= L ? q - L : q);
     };
 
-    // ---- prologue: planes z0-2 .. z0+1 ------------------------------------------
+    // ---- prologue: planes z0-2 .. z0+1 --------------------------------------------
     const int kfirst = z0 - 1;
     const int klast = z0 + ZCe;
-    Plane<NREP> A, B, C, D;  // planes k-1, k, k+1, k+2
-    load_plane<NREP>(p, plane_off(kfirst - 1), V, lane, full, A);
-    load_plane<NREP>(p, plane_off(kfirst), V, lane, full, B);
-    load_plane<NREP>(p, plane_off(kfirst + 1), V, lane, full, C);
-    load_plane<NREP>(p, plane_off(kfirst + 2), V, lane, full, D);
+    Plane<NREP> ring[NS];  // ring[j] starts with plane kfirst - 1 + j
+    ((load_plane<NREP>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
 
-    uint64_t jzm2lo = 0, jzm2hi = 0;         // jz of plane k-2
-    uint64_t jxl_prev = 0, jyulo_prev = 0, jyuhi_prev = 0;  // neighbour couplings of plane k-1
-    uint64_t rn1[NREP], rn2[NREP];           // new red words of planes k-1, k-2
+    Carry<NREP> cy;
+    cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
 #pragma unroll
     for (int r = 0; r < NREP; ++r)
-        rn1[r] = rn2[r] = 0;
+        cy.rn1[r] = cy.rn2[r] = 0;
 
     {
-        // publish plane kfirst: its blue words and its couplings
-        uint64_t *S = lds + ((kfirst + 2) & 1) * set_words;
-        const bool pk = ((y + kfirst + L) & 1) != 0;
-        if (lane) {
+        // publish plane kfirst: its old blue words (half 1-H) and its couplings
+        uint64_t *S = lds + ((kfirst + 2) & 1) * c.set_words;
+        const bool hred = ((ypar + kfirst + L) & 1) != 0;
 #pragma unroll
-            for (int r = 0; r < NREP; ++r)
-                S[r * nl + me] = pick(pk, B.slo[r], B.shi[r]);
-            S[2 * NREP * nl + me] = B.jxhi;
-            S[(2 * NREP + 1) * nl + me] = B.jylo;
-            S[(2 * NREP + 2) * nl + me] = B.jyhi;
-        }
+        for (int r = 0; r < NREP; ++r)
+            S[r * c.nl + c.me] = hred ? ring[1].slo[r] : ring[1].shi[r];
+        S[2 * NREP * c.nl + c.me] = ring[1].jxhi;
+        S[(2 * NREP + 1) * c.nl + c.me] = ring[1].jylo;
+        S[(2 * NREP + 2) * c.nl + c.me] = ring[1].jyhi;
     }
     __syncthreads();
 
-    for (int k = kfirst; k <= klast; ++k) {
-        const bool pk = ((y + k + L) & 1) != 0;  // half updated at this step
-        const uint64_t *S = lds + ((k + 2) & 1) * set_words;
-        const int ixn = pk ? ixp : ixm;
-
-        // ---- neighbours from LDS --------------------------------------------------
-        uint64_t nbx_b[NREP], nym_b[NREP], nyp_b[NREP];
-        uint64_t nbx_r[NREP], nym_r[NREP], nyp_r[NREP];
-#pragma unroll
-        for (int r = 0; r < NREP; ++r) {
-            nbx_b[r] = S[r * nl + ixn];
-            nym_b[r] = S[r * nl + iym];
-            nyp_b[r] = S[r * nl + iyp];
-            nbx_r[r] = S[(NREP + r) * nl + ixn];
-            nym_r[r] = S[(NREP + r) * nl + iym];
-            nyp_r[r] = S[(NREP + r) * nl + iyp];
-        }
-        const uint64_t jxl = S[2 * NREP * nl + ixm];
-        const uint64_t jyulo = S[(2 * NREP + 1) * nl + iym];
-        const uint64_t jyuhi = S[(2 * NREP + 2) * nl + iym];
-
-        // ---- red sites of plane k -----------------------------------------------
-        uint64_t rn[NREP];
-        {
-            const uint64_t jxp = pick(pk, B.jxhi, B.jxlo);
-            const uint64_t jxm = pick(pk, B.jxlo, jxl);
-            const uint64_t jyp = pick(pk, B.jyhi, B.jylo);
-            const uint64_t jym = pick(pk, jyuhi, jyulo);
-            const uint64_t jzp = pick(pk, B.jzhi, B.jzlo);
-            const uint64_t jzm = pick(pk, A.jzhi, A.jzlo);
-#pragma unroll
-            for (int r = 0; r < NREP; ++r) {
-                const uint64_t s = pick(pk, B.shi[r], B.slo[r]);
-                const uint64_t other = pick(pk, B.slo[r], B.shi[r]);
-                const uint64_t nxp = pick(pk, nbx_b[r], other);
-                const uint64_t nxm = pick(pk, other, nbx_b[r]);
-                const uint64_t nzp = pick(pk, C.shi[r], C.slo[r]);
-                const uint64_t nzm = pick(pk, A.shi[r], A.slo[r]);
-                uint32_t R = pk ? B.rhi[r] : B.rlo[r];
-                if (PRNG == SG_MINSTD)
-                    R = minstd_jump(p.a, R);
-                rn[r] = s ^ flip_mask(s, nxp, nyp_b[r], nzp, nxm, nym_b[r], nzm, jxp, jyp, jzp, jxm, jym, jzm,
-                                      R, p.T);
-            }
-        }
-
-        // ---- blue sites of plane k-1 ----------------------------------------------
-        if (k >= z0 + 1) {
-            const uint64_t jxp = pick(pk, A.jxhi, A.jxlo);
-            const uint64_t jxm = pick(pk, A.jxlo, jxl_prev);
-            const uint64_t jyp = pick(pk, A.jyhi, A.jylo);
-            const uint64_t jym = pick(pk, jyuhi_prev, jyulo_prev);
-            const uint64_t jzp = pick(pk, A.jzhi, A.jzlo);
-            const uint64_t jzm = pick(pk, jzm2hi, jzm2lo);
-            const int64_t off = plane_off(k - 1);
-#pragma unroll
-            for (int r = 0; r < NREP; ++r) {
-                const uint64_t s = pick(pk, A.shi[r], A.slo[r]);
-                const uint64_t nxp = pick(pk, nbx_r[r], rn1[r]);
-                const uint64_t nxm = pick(pk, rn1[r], nbx_r[r]);
-                uint32_t R = pk ? A.rhi[r] : A.rlo[r];
-                if (PRNG == SG_MINSTD)
-                    R = minstd_jump(p.a, R);
-                const uint64_t bn = s ^ flip_mask(s, nxp, nyp_r[r], rn[r], nxm, nym_r[r], rn2[r], jxp, jyp, jzp, jxm,
-                                                  jym, jzm, R, p.T);
-                if (inter) {
-                    ulonglong2 w;
-                    w.x = pk ? rn1[r] : bn;
-                    w.y = pk ? bn : rn1[r];
-                    *reinterpret_cast<ulonglong2 *>(p.dst[r] + off) = w;
-                }
-            }
-        }
-
-        // ---- publish for step k+1: new red of plane k, old blue and couplings of k+1
-        if (k < klast) {
-            uint64_t *W = lds + ((k + 3) & 1) * set_words;
-            if (lane) {
-#pragma unroll
-                for (int r = 0; r < NREP; ++r) {
-                    W[r * nl + me] = pick(pk, C.shi[r], C.slo[r]);
-                    W[(NREP + r) * nl + me] = rn[r];
-                }
-                W[2 * NREP * nl + me] = C.jxhi;
-                W[(2 * NREP + 1) * nl + me] = C.jylo;
-                W[(2 * NREP + 2) * nl + me] = C.jyhi;
-            }
-            __syncthreads();
-        }
-
-        // ---- rotate the plane pipeline ------------------------------------------------
-        jzm2lo = A.jzlo;
-        jzm2hi = A.jzhi;
-        jxl_prev = jxl;
-        jyulo_prev = jyulo;
-        jyuhi_prev = jyuhi;
-#pragma unroll
-        for (int r = 0; r < NREP; ++r) {
-            rn2[r] = rn1[r];
-            rn1[r] = rn[r];
-        }
-        A = B;
-        B = C;
-        C = D;
-        if (k + 3 <= klast + 1)
-            load_plane<NREP>(p, plane_off(k + 3), V, lane, full, D);
+    int k = kfirst;
+    // One step with planes (A, B, C) = (k-1, k, k+1); the other ring slots hold
+    // k+2 .. k+NS-2 in flight, and A's slot receives k+NS-1 at the end.  The steps
+    // of one turn of the ring are unrolled, so it turns without register copies.
+#define SG_FUSED_STEP(A, B, C)                                                                                   \
+    {                                                                                                             \
+        uint64_t rn[NREP], wlo[NREP], whi[NREP];                                                                  \
+        _Pragma("unroll") for (int r = 0; r < NREP; ++r) wlo[r] = whi[r] = 0;                                    \
+        uint64_t jxl, jyulo, jyuhi;                                                                               \
+        const bool do_blue = k >= z0 + 1;                                                                         \
+        const bool do_pub = k < klast;                                                                            \
+        if ((ypar + k + L) & 1)                                                                                   \
+            fused_step<PRNG, NREP, 1>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, rn, wlo, whi, jxl, jyulo,     \
+                                      jyuhi);                                                                     \
+        else                                                                                                      \
+            fused_step<PRNG, NREP, 0>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, rn, wlo, whi, jxl, jyulo,     \
+                                      jyuhi);                                                                     \
+        {                                                                                                         \
+            const int64_t qo = (int64_t)wrap(k - 1) * LL * 8;                                                     \
+            const uint32_t ost = do_blue ? o_st : kOOB;                                                           \
+            _Pragma("unroll") for (int r = 0; r < NREP; ++r)                                                     \
+                st_pair(plane_rsrc(p.dst[r], qo, (uint32_t)(LL * 8)), ost, wlo[r], whi[r]);                       \
+        }                                                                                                         \
+        if (do_pub)                                                                                               \
+            __syncthreads();                                                                                      \
+        cy.jzm2lo = A.jzlo;                                                                                       \
+        cy.jzm2hi = A.jzhi;                                                                                       \
+        cy.jxl = jxl;                                                                                             \
+        cy.jyulo = jyulo;                                                                                         \
+        cy.jyuhi = jyuhi;                                                                                         \
+        _Pragma("unroll") for (int r = 0; r < NREP; ++r)                                                         \
+        {                                                                                                         \
+            cy.rn2[r] = cy.rn1[r];                                                                                \
+            cy.rn1[r] = rn[r];                                                                                    \
+        }                                                                                                         \
+        load_plane<NREP>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);                       \
     }
+
+    auto step = [&](auto I) -> bool {
+        constexpr int i = decltype(I)::value;
+        SG_FUSED_STEP(ring[i], ring[(i + 1) % NS], ring[(i + 2) % NS])
+        return ++k <= klast;
+    };
+    while ((step(IC<Is>{}) && ...)) {
+    }
+#undef SG_FUSED_STEP
 }
 
 }  // namespace
 
 static size_t fused_lds_bytes(int nrep, int tile_x, int tile_y)
 {
-    return (size_t)2 * (tile_x + 2) * (tile_y + 4) * (2 * nrep + 3) * sizeof(uint64_t);
+    return (size_t)2 * ((tile_x + 2) * (tile_y + 4) + 1) * (2 * nrep + 3) * sizeof(uint64_t);
 }
 
-static int max_threads(int nrep) { return nrep == 1 ? MaxThreads<1>::value : MaxThreads<2>::value; }
+// Threads of a workgroup: even tile rows fill whole waves, then the odd rows.
+static int fused_waves_even(int tile_x, int tile_y) { return ((tile_x + 2) * ((tile_y + 5) / 2) + 63) / 64; }
+static int fused_threads(int tile_x, int tile_y)
+{
+    return 64 * (fused_waves_even(tile_x, tile_y) + ((tile_x + 2) * ((tile_y + 4) / 2) + 63) / 64);
+}
+static int max_threads(int) { return kMaxThreads; }
 
 static int max_lds_bytes();
 
@@ -301,10 +399,9 @@ bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk)
     if (L < 2 || (L & 1) || nrep < 1 || nrep > 2)
         return false;
     const int P = L / 2;
-    if (tile_x < 1 || tile_x > P || tile_y < 1 || tile_y > L || z_chunk < 1 || z_chunk > L)
+    if (tile_x < 1 || tile_x > P || tile_y < 1 || tile_y > L || z_chunk < 0 || z_chunk > L)
         return false;
-    const int lanes = (tile_x + 2) * (tile_y + 4);
-    if ((lanes + 63) / 64 * 64 > max_threads(nrep))
+    if (fused_threads(tile_x, tile_y) > max_threads(nrep))
         return false;
     if (fused_lds_bytes(nrep, tile_x, tile_y) > (size_t)max_lds_bytes())
         return false;
@@ -327,37 +424,75 @@ static int max_lds_bytes()
 
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk)
 {
-    // Pick the tile that needs the fewest lanes (whole waves, ragged tiles
-    // included) per pair of the lattice plane.
+    // Measured on MI355X: tiles 32 or 16 pairs wide that divide the row, so that
+    // the workgroups running together read whole rows; 8 or 16 rows tall.
     const int P = L / 2;
+    z_chunk = 0;  // chosen at launch from the occupancy
+    const int pref[][2] = {{32, 8}, {16, 16}, {16, 8}, {8, 16}};
+    for (const auto &c : pref) {
+        if (P % c[0] == 0 && P >= c[0] && L >= c[1] && fused_threads(c[0], c[1]) <= max_threads(nrep) &&
+            fused_lds_bytes(nrep, c[0], c[1]) <= (size_t)max_lds_bytes()) {
+            tile_x = c[0];
+            tile_y = c[1];
+            return;
+        }
+    }
+    // small or odd-shaped planes: the tile needing the fewest lanes per pair
     double best = 1e30;
     tile_x = 1;
     tile_y = 1;
     for (int tx = 1; tx <= P && tx <= 126; ++tx)
         for (int ty = 1; ty <= L && ty <= 252; ++ty) {
-            const int lanes = (tx + 2) * (ty + 4);
-            const int threads = (lanes + 63) / 64 * 64;
+            const int threads = fused_threads(tx, ty);
             if (threads > max_threads(nrep) || fused_lds_bytes(nrep, tx, ty) > (size_t)max_lds_bytes())
                 continue;
             const int64_t ntx = (P + tx - 1) / tx, nty = (L + ty - 1) / ty;
             const double cost = (double)(ntx * nty * threads) / ((double)P * L);
-            if (cost < best - 1e-9 || (cost < best + 1e-9 && lanes > (tile_x + 2) * (tile_y + 4))) {
+            if (cost < best - 1e-9) {
                 best = cost;
                 tile_x = tx;
                 tile_y = ty;
             }
         }
-    // z chunks: enough workgroups to fill 256 CUs a few times over, chunks of at
-    // least 16 planes (each chunk recomputes two red planes and loads four extra)
-    const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((L + tile_y - 1) / tile_y);
-    int zc = L;
-    while (zc >= 32 && tiles * ((L + zc - 1) / zc) < 1024)
-        zc = (zc + 1) / 2;
-    z_chunk = zc;
+}
+
+// z chunk length for a grid of `tiles` tiles: each workgroup marches ZC + 2
+// steps, workgroups run in rounds of `slots`; take the chunk count with the
+// shortest rounds * (ZC + 4) (four extra planes are loaded per chunk).
+static int choose_z_chunk(int L, int64_t tiles, int64_t slots)
+{
+    int best_zc = L;
+    double best = 1e300;
+    for (int nzc = 1; nzc <= L && nzc <= 128; ++nzc) {
+        const int zc = (L + nzc - 1) / nzc;
+        const int64_t n = (L + zc - 1) / zc;
+        const int64_t rounds = (tiles * n + slots - 1) / slots;
+        const double cost = (double)rounds * (zc + 4);
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_zc = zc;
+        }
+    }
+    return best_zc;
 }
 
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, hipStream_t s)
 {
+    if (z_chunk == 0) {
+        // workgroups resident at once: CUs x workgroups per CU
+        const int threads = fused_threads(tile_x, tile_y);
+        const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess)
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const void *fn = a.nrep == 1 ? (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 1> : (const void *)k_fused<SG_MT19937, 1>)
+                                     : (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 2> : (const void *)k_fused<SG_MT19937, 2>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        const int P = a.L / 2;
+        const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((a.L + tile_y - 1) / tile_y);
+        z_chunk = choose_z_chunk(a.L, tiles, (int64_t)cus * per_cu);
+    }
     FusedParams p;
     p.J = a.J;
     for (int r = 0; r < 2; ++r) {
@@ -377,8 +512,8 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.nzc = (p.L + z_chunk - 1) / z_chunk;
     p.a = a.minstd_a;
     p.T = a.T;
-    const int nl = p.EX * p.EY;
-    const int threads = (nl + 63) / 64 * 64;
+    p.WE = fused_waves_even(tile_x, tile_y);
+    const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
     if (threads > max_threads(a.nrep) || lds > (size_t)max_lds_bytes())
         return hipErrorInvalidConfiguration;

@@ -149,18 +149,26 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     return SG_OK;
 }
 
-bool use_fused(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
+// Kernel for a sweep of nrep lattices: 1 = fused (shape in tx, ty, zc), 0 = two-pass,
+// negative = error (an explicitly chosen fused shape that does not fit nrep).
+int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
 {
     if (lat->kernel == SG_KERNEL_TWOPASS)
-        return false;
+        return 0;
     if (lat->tile_x > 0) {
         tx = lat->tile_x;
         ty = lat->tile_y;
         zc = lat->z_chunk;
-    } else {
-        fused_default_shape(lat->L, nrep, tx, ty, zc);
+        if (!fused_shape_ok(lat->L, nrep, tx, ty, zc))
+            return fail(SG_EINVAL, "the chosen fused tile does not fit " + std::to_string(nrep) + " replica(s)");
+        return 1;
     }
-    return fused_shape_ok(lat->L, nrep, tx, ty, zc);
+    fused_default_shape(lat->L, nrep, tx, ty, zc);
+    if (fused_shape_ok(lat->L, nrep, tx, ty, zc))
+        return 1;
+    if (lat->kernel == SG_KERNEL_FUSED)
+        return fail(SG_EINVAL, "no fused tile fits this lattice");
+    return 0;
 }
 
 // One sweep of n (1 or 2) lattices that share couplings, stream and sweep count.
@@ -189,7 +197,10 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
         a.rnd[r] = l0->prng == SG_MINSTD ? lats[r]->seeds : lats[r]->rbuf;
     }
     int tx = 0, ty = 0, zc = 0;
-    if (use_fused(l0, n, tx, ty, zc)) {
+    const int kind = pick_kernel(l0, n, tx, ty, zc);
+    if (kind < 0)
+        return kind;
+    if (kind == 1) {
         e = launch_sweep_fused(a, tx, ty, zc, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "fused sweep launch");

@@ -65,36 +65,62 @@ __host__ __device__ __forceinline__ uint32_t minstd_jump(uint32_t a, uint32_t s)
 // full adders into a 3-bit count v = 0..6 per sample, dE = 4v - 12, and the flip
 // mask keeps every sample with v <= 3, those with v = 4 if R < T4, v = 5 if
 // R < T8 and v = 6 if R < T12.  One R per word (asynchronous multispin coding).
+// flip_mask returns the mask; the new spin word is s ^ mask.
 // ---------------------------------------------------------------------------
 struct Thresholds {
     uint64_t t4, t8, t12;
 };
 
-__device__ __forceinline__ void full_add(uint64_t a, uint64_t b, uint64_t c, uint64_t &sum, uint64_t &carry)
+// v_bfi_b32: bits of a where m is 1, bits of b where m is 0.
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t a, uint32_t b)
 {
-    const uint64_t t = a ^ b;
-    sum = t ^ c;
-    carry = (t & c) | (~t & a);
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
+    return r;
 }
 
+// 32 samples of the update.  x[k] = J_k ^ n_k; the bond bit is b_k = x[k] ^ ~s.
+// The complement of s is carried through the adder instead of being applied to
+// all six inputs: a three-input sum of (x ^ c) is sum(x) ^ c, a majority of
+// (x ^ c) is maj(x) ^ c, and c cancels in the XOR of two such terms.
+// a4, a8, a12 are all-ones when R < T4, T8, T12.
+__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                              uint32_t x4, uint32_t x5, uint32_t a4, uint32_t a8, uint32_t a12)
+{
+    const uint32_t ns = ~s;
+    const uint32_t t1 = x0 ^ x1, t2 = x3 ^ x4;
+    const uint32_t s1 = t1 ^ x2, s2 = t2 ^ x5;   // sums of x: sums of b are s1^ns, s2^ns
+    const uint32_t k1 = bfi(t1, x2, x0);         // majority of x0, x1, x2
+    const uint32_t k2 = bfi(t2, x5, x3);
+    const uint32_t c0 = s1 ^ s2;                 // bit 0 of v
+    const uint32_t k3 = bfi(c0, 0u, s1 ^ ns);    // carry of (s1^ns) + (s2^ns)
+    const uint32_t t3 = k1 ^ k2;
+    const uint32_t c1 = t3 ^ k3;                 // bit 1 of v
+    const uint32_t c2 = bfi(t3, k3, k1 ^ ns);    // bit 2 of v
+    // flip if v <= 3, or v = 4 and R < T4, v = 5 and R < T8, v = 6 and R < T12
+    const uint32_t mid = bfi(c0, a8, a4);        // v in {4, 5}
+    const uint32_t hi = bfi(c1, 0u, mid) | a12;  // v >= 4 and accepted
+    return bfi(c2, hi, ~0u);
+}
+
+// Flip mask of a 64-sample word: s the spin word, n0..n5 the neighbour words and
+// j0..j5 the coupling words of the same six bonds, one R for the word.
 __device__ __forceinline__ uint64_t flip_mask(uint64_t s, uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
                                               uint64_t n4, uint64_t n5, uint64_t j0, uint64_t j1, uint64_t j2,
                                               uint64_t j3, uint64_t j4, uint64_t j5, uint32_t R,
                                               const Thresholds &T)
 {
-    const uint64_t ns = ~s;
-    uint64_t a0, a1, b0, b1, c1, c2;
-    full_add(j0 ^ ns ^ n0, j1 ^ ns ^ n1, j2 ^ ns ^ n2, a0, a1);
-    full_add(j3 ^ ns ^ n3, j4 ^ ns ^ n4, j5 ^ ns ^ n5, b0, b1);
-    const uint64_t c0 = a0 ^ b0;
-    full_add(a1, b1, a0 & b0, c1, c2);
     const uint64_t r = (uint64_t)R;
-    const uint64_t all8 = (r < T.t8) ? ~0ull : 0ull;
-    const uint64_t all4 = (r < T.t4) ? ~0ull : 0ull;
-    const uint64_t all12 = (r < T.t12) ? ~0ull : 0ull;
-    // v in {4, 5}: c2 & ~c1; v = 4 needs R < T4, v = 5 needs R < T8
-    const uint64_t mid = all8 | (all4 & ~c0);
-    return all12 | ~c2 | (~c1 & mid);
+    const uint32_t a4 = (r < T.t4) ? ~0u : 0u;
+    const uint32_t a8 = (r < T.t8) ? ~0u : 0u;
+    const uint32_t a12 = (r < T.t12) ? ~0u : 0u;
+    const uint64_t x0 = j0 ^ n0, x1 = j1 ^ n1, x2 = j2 ^ n2, x3 = j3 ^ n3, x4 = j4 ^ n4, x5 = j5 ^ n5;
+    const uint32_t lo = flip_half((uint32_t)s, (uint32_t)x0, (uint32_t)x1, (uint32_t)x2, (uint32_t)x3,
+                                  (uint32_t)x4, (uint32_t)x5, a4, a8, a12);
+    const uint32_t hi = flip_half((uint32_t)(s >> 32), (uint32_t)(x0 >> 32), (uint32_t)(x1 >> 32),
+                                  (uint32_t)(x2 >> 32), (uint32_t)(x3 >> 32), (uint32_t)(x4 >> 32),
+                                  (uint32_t)(x5 >> 32), a4, a8, a12);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // ---------------------------------------------------------------------------

@@ -123,7 +123,7 @@ def test_64_samples_every_sweep(sg, L, prng, kernel):
 
 
 @pytest.mark.parametrize("L,tiles", [
-    (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 28, 11)), (34, (17, 27, 34)),
+    (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 20, 11)), (34, (17, 21, 34)),
     (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)),
 ])
 @pytest.mark.parametrize("prng", ["minstd", "mt19937"])
