@@ -13,7 +13,6 @@ same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -54,11 +53,9 @@ def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
 
 
 def kernel_source_sha() -> str:
-    h = hashlib.sha256()
-    for f in ("kernels_sweep_fused.hip", "sg_internal.h"):
-        with open(os.path.join(ROOT, "paper_1411_0127_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1411_0127_amd.profiling import kernel_source_sha as sha
+
+    return sha()
 
 
 def load_traffic(workload: str):
@@ -174,6 +171,8 @@ def main():
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="also make 3 device copies of BYTES bytes, for counter calibration")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -184,6 +183,15 @@ def main():
 
     wl = WORKLOADS[args.workload]
     main_res, variant = run_gpu(args, wl)
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.empty(args.calibrate_copy, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     L, R = wl["L"], wl["replicas"]
     V = L**3
     bps = algorithmic_bytes_per_site(wl["prng"], R)

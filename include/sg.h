@@ -141,9 +141,11 @@ int64_t sg_sweep_count(const sg_lattice *lat);
 int sg_set_sweep_count(sg_lattice *lat, int64_t t);
 
 /* Choose the sweep kernel and, for SG_KERNEL_FUSED, its tile: tile_x pairs of
- * sites per row (x extent 2*tile_x), tile_y rows, z_chunk planes per workgroup
- * (0 = default).  Invalid shapes return SG_EINVAL and change nothing. */
-int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk);
+ * sites per row (x extent 2*tile_x), tile_y rows, z_chunk planes per workgroup,
+ * band = tile rows per group of the tile order (the workgroups running together
+ * cover a block about band tiles tall); 0 = default for any of the four.  Invalid
+ * shapes return SG_EINVAL and change nothing. */
+int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
 /* Release the handle (never the caller's device buffer). */
 int sg_destroy(sg_lattice *lat);

@@ -23,9 +23,10 @@
 // because a site's random number depends only on (stream, site, sweep).  A z-chunk
 // likewise recomputes the red plane below and above it.
 //
-// Launch.  One workgroup per (tile, z-chunk), tiles numbered x fastest; block ids
-// are spread so that consecutive tiles land on the same XCD (blocks are dealt to
-// the 8 XCDs round robin), where their shared ring columns meet in the same L2.
+// Launch.  One workgroup per (tile, z-chunk); block ids are spread so that
+// consecutive tiles land on the same XCD (blocks are dealt to the 8 XCDs round
+// robin), and tiles are numbered in column-major blocks a few tiles tall, so the
+// workgroups resident on an XCD together cover a compact block of the plane.
 #include <type_traits>
 #include <utility>
 
@@ -44,6 +45,7 @@ struct FusedParams {
     int EX, EY;          // lanes per tile row (TXp + 2), tile rows incl. ring (TY + 4)
     int ntx, nty, nzc;   // tiles along x, y, z
     int WE;              // waves holding the even tile rows
+    int band;            // tile rows per group of the tile order
     uint32_t a;          // MINSTD multiplier of this sweep
     Thresholds T;
 };
@@ -258,12 +260,18 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint6
     const int nb = gridDim.x;
     const int b = blockIdx.x;
     const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-    // x fastest: the workgroups that run together on an XCD read one band of rows
-    // across the whole plane, long contiguous runs of every array
-    const int tx = tile % p.ntx;
-    const int rest = tile / p.ntx;
-    const int ty = rest % p.nty;
-    const int zc = rest / p.nty;
+    // Tile order within a z chunk: groups of `band` tile rows; inside a group the
+    // tiles go down a column of the group, then to the next column.  The workgroups
+    // that run together on one XCD then form a block `band` tiles tall, whose
+    // inner ring rows are read once into that XCD's L2.
+    const int per_chunk = p.ntx * p.nty;
+    const int zc = tile / per_chunk;
+    const int r0 = tile - zc * per_chunk;
+    const int g = r0 / (p.ntx * p.band);
+    const int gh = min(p.band, p.nty - g * p.band);  // tile rows in this group
+    const int q0 = r0 - g * p.ntx * p.band;
+    const int tx = q0 / gh;
+    const int ty = g * p.band + (q0 - tx * gh);
     const int TXe = min(p.TXp, p.P - tx * p.TXp);
     const int TYe = min(p.TY, p.L - ty * p.TY);
     const int z0 = zc * p.ZC;
@@ -476,7 +484,7 @@ static int choose_z_chunk(int L, int64_t tiles, int64_t slots)
     return best_zc;
 }
 
-hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, hipStream_t s)
+hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)
 {
     if (z_chunk == 0) {
         // workgroups resident at once: CUs x workgroups per CU
@@ -484,7 +492,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
         const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess)
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const void *fn = a.nrep == 1 ? (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 1> : (const void *)k_fused<SG_MT19937, 1>)
                                      : (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 2> : (const void *)k_fused<SG_MT19937, 2>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
@@ -513,6 +521,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.a = a.minstd_a;
     p.T = a.T;
     p.WE = fused_waves_even(tile_x, tile_y);
+    p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
     const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
     if (threads > max_threads(a.nrep) || lds > (size_t)max_lds_bytes())

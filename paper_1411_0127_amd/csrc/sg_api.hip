@@ -164,6 +164,8 @@ int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
         return 1;
     }
     fused_default_shape(lat->L, nrep, tx, ty, zc);
+    if (lat->z_chunk > 0)
+        zc = lat->z_chunk;
     if (fused_shape_ok(lat->L, nrep, tx, ty, zc))
         return 1;
     if (lat->kernel == SG_KERNEL_FUSED)
@@ -201,7 +203,7 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
     if (kind < 0)
         return kind;
     if (kind == 1) {
-        e = launch_sweep_fused(a, tx, ty, zc, l0->stream);
+        e = launch_sweep_fused(a, tx, ty, zc, l0->band > 0 ? l0->band : 1, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "fused sweep launch");
         for (int r = 0; r < n; ++r)
@@ -355,6 +357,7 @@ int sg_lattice_create_replica(const sg_lattice *base, uint64_t spin_seed, uint32
     lat->tile_x = base->tile_x;
     lat->tile_y = base->tile_y;
     lat->z_chunk = base->z_chunk;
+    lat->band = base->band;
     rc = init_streams(lat);
     if (rc == SG_OK) {
         hipError_t e = hipStreamSynchronize(lat->stream);
@@ -580,23 +583,29 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
     return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
 }
 
-int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk)
+int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band)
 {
     if (!lat)
         return fail(SG_EINVAL, "NULL lattice");
     if (kind != SG_KERNEL_AUTO && kind != SG_KERNEL_TWOPASS && kind != SG_KERNEL_FUSED)
         return fail(SG_EINVAL, "unknown kernel");
-    if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0 || z_chunk != 0)) {
+    if (band < 0)
+        return fail(SG_EINVAL, "band must be >= 0");
+    if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0)) {
         if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
             return fail(SG_EINVAL, "invalid fused tile shape");
+    } else if (z_chunk < 0 || z_chunk > lat->L) {
+        return fail(SG_EINVAL, "invalid z_chunk");
     }
     lat->kernel = kind;
+    lat->band = band;
     if (kind == SG_KERNEL_FUSED) {
         lat->tile_x = tile_x;
         lat->tile_y = tile_y;
         lat->z_chunk = z_chunk;
     } else {
-        lat->tile_x = lat->tile_y = lat->z_chunk = 0;
+        lat->tile_x = lat->tile_y = 0;
+        lat->z_chunk = z_chunk;
     }
     return SG_OK;
 }

@@ -152,7 +152,7 @@ struct sg_lattice {
     hipStream_t stream = nullptr;
     int64_t t = 0;  // sweeps done
     int kernel = SG_KERNEL_AUTO;
-    int tile_x = 0, tile_y = 0, z_chunk = 0;
+    int tile_x = 0, tile_y = 0, z_chunk = 0, band = 0;
 };
 
 namespace sg {
@@ -189,7 +189,7 @@ struct SweepArgs {
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
-hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, hipStream_t s);
+hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
 
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,
                               hipStream_t s);

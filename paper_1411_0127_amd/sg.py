@@ -53,7 +53,7 @@ SIGNATURES = {
     "sg_thresholds": (_i, [_d, _i, _p]),
     "sg_sweep_count": (_i64, [_p]),
     "sg_set_sweep_count": (_i, [_p, _i64]),
-    "sg_set_kernel": (_i, [_p, _i, _i, _i, _i]),
+    "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
     "sg_destroy": (_i, [_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -154,9 +154,9 @@ class Lattice:
     def sweep(self, n: int, beta: float):
         _check(lib.sg_sweep(self.handle, int(n), float(beta)))
 
-    def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0):
+    def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0, band: int = 0):
         _check(lib.sg_set_kernel(self.handle, KERNELS[kind] if isinstance(kind, str) else int(kind),
-                                 int(tile_x), int(tile_y), int(z_chunk)))
+                                 int(tile_x), int(tile_y), int(z_chunk), int(band)))
 
     @property
     def t(self) -> int:
