@@ -86,7 +86,13 @@ def run_gpu(args, wl):
     def measure(prng):
         base = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
         lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
-        if args.kernel != "auto":
+        shape = None
+        if args.kernel == "auto":
+            # pick the fused tile on these lattices, before the timed region
+            shape, _ = sg.autotune(lats[:2], reps=5)
+            for l in lats[2:]:
+                l.set_kernel("fused", *shape)
+        else:
             for l in lats:
                 l.set_kernel(args.kernel)
 
@@ -121,6 +127,7 @@ def run_gpu(args, wl):
             sweep_ms_per_step=sweep_ms,
             launch_ms=sum(sweep_ms) / (args.steps * nsw),
             energy_per_spin=[float(x) for x in last[0][1][:4]],
+            tile=shape,
         )
         flips = R * 64 * V * nsw
         res["ps_per_flip"] = res["ms_per_step"] * 1e9 / flips
@@ -218,6 +225,7 @@ def main():
             "sweeps_per_step": args.sweeps or wl["sweeps"],
             "prng": wl["prng"],
             "kernel": args.kernel,
+            "tile": main_res["tile"],
             "parallelism": "single GPU",
         },
         "hbm_gbs_algorithmic": round(achieved, 1),

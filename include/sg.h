@@ -147,6 +147,17 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t);
  * shapes return SG_EINVAL and change nothing. */
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
+/* Autotune the fused kernel for n (1 or 2) lattices swept together (n = 2:
+ * replicas sharing couplings, as in sg_sweep_replicas).  Candidate tiles are
+ * timed with `reps` launches each on the lattices' own data without changing
+ * their state (the launches read the current spins and write only the spare
+ * buffer; sweep count and streams do not move).  The fastest shape is set on
+ * every lattice (as sg_set_kernel(SG_KERNEL_FUSED, ...)) and remembered for this
+ * device, L, n and prng; a later call with the same key reuses it without
+ * timing unless reps < 0 forces a new search.  best[4] (may be NULL) receives
+ * tile_x, tile_y, z_chunk, band; ms (may be NULL) the best time per launch. */
+int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *ms);
+
 /* Release the handle (never the caller's device buffer). */
 int sg_destroy(sg_lattice *lat);
 

@@ -77,29 +77,58 @@ __device__ __forceinline__ uint32_t mt_temper(uint32_t y)
 // before the word is output: word i of a new block is computed from word i and
 // i+1 of the previous block and word i+397 (already renewed when i+397 >= 624
 // wraps), which is exactly the order of the sequential in-place twist.
-__global__ void k_mt_fill(uint32_t *__restrict__ st, uint32_t *__restrict__ R, int L, int64_t t)
+//
+// Steps go in groups of U: the words a group reads (i+1 .. i+U and i+397 ..
+// i+397+U-1, mod 624) are loaded first, together.  None of them is renewed inside
+// the group -- word i+1+u is renewed at step u+1, after it is read, and word
+// i+397+u mod 624 is renewed 227 steps before or 397 steps after step u -- so the
+// group sees the same values the sequential twist does, with U loads in flight.
+// blockIdx.y selects one of up to two streams sets (replicas).
+struct MtFillArgs {
+    uint32_t *st[2];
+    uint32_t *R[2];
+};
+
+constexpr int kMtGroup = 8;
+
+__global__ __launch_bounds__(256) void k_mt_fill(MtFillArgs a, int L, int64_t t)
 {
     const int ncols = L * L;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols)
         return;
+    uint32_t *__restrict__ st = a.st[blockIdx.y];
+    uint32_t *__restrict__ R = a.R[blockIdx.y];
     int i = (int)(((int64_t)t * L) % kMtN);
     uint32_t cur = st[(size_t)i * ncols + c];
-    for (int z = 0; z < L; ++z) {
-        const int i1 = (i + 1 == kMtN) ? 0 : i + 1;
-        int im = i + 397;
-        im = (im >= kMtN) ? im - kMtN : im;
-        const uint32_t nxt = st[(size_t)i1 * ncols + c];
-        const uint32_t y = (cur & 0x80000000u) | (nxt & 0x7FFFFFFFu);
-        uint32_t v = st[(size_t)im * ncols + c] ^ (y >> 1);
-        v ^= (y & 1u) ? 0x9908B0DFu : 0u;
-        st[(size_t)i * ncols + c] = v;
-        R[(size_t)z * ncols + c] = mt_temper(v);
-        // word i1 is renewed next, and its value before that renewal is the one
-        // just read (for i1 = 0 that is the word renewed at the start of this
-        // block, which is what the next block's first step reads)
-        cur = nxt;
-        i = i1;
+    for (int z0 = 0; z0 < L; z0 += kMtGroup) {
+        const int n = min(kMtGroup, L - z0);
+        uint32_t nxt[kMtGroup], far[kMtGroup];
+#pragma unroll
+        for (int u = 0; u < kMtGroup; ++u) {
+            if (u < n) {
+                int i1 = i + 1 + u;
+                i1 = i1 >= kMtN ? i1 - kMtN : i1;
+                int im = i + 397 + u;
+                im = im >= kMtN ? im - kMtN : im;
+                im = im >= kMtN ? im - kMtN : im;
+                nxt[u] = st[(size_t)i1 * ncols + c];
+                far[u] = st[(size_t)im * ncols + c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kMtGroup; ++u) {
+            if (u < n) {
+                const uint32_t y = (cur & 0x80000000u) | (nxt[u] & 0x7FFFFFFFu);
+                uint32_t v = far[u] ^ (y >> 1);
+                v ^= (y & 1u) ? 0x9908B0DFu : 0u;
+                st[(size_t)i * ncols + c] = v;
+                R[(size_t)(z0 + u) * ncols + c] = mt_temper(v);
+                // word i+1 is renewed next; its value before that is the one read
+                cur = nxt[u];
+                i = (i + 1 == kMtN) ? 0 : i + 1;
+            }
+        }
     }
 }
 
@@ -140,10 +169,15 @@ hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_mt_fill(uint32_t *state, uint32_t *rbuf, int L, int64_t t, hipStream_t s)
+hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s)
 {
     const int ncols = L * L;
-    hipLaunchKernelGGL(k_mt_fill, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s, state, rbuf, L, t);
+    MtFillArgs a{};
+    for (int r = 0; r < n && r < 2; ++r) {
+        a.st[r] = state[r];
+        a.R[r] = rbuf[r];
+    }
+    hipLaunchKernelGGL(k_mt_fill, dim3((ncols + kBlock - 1) / kBlock, n), dim3(kBlock), 0, s, a, L, t);
     return hipGetLastError();
 }
 

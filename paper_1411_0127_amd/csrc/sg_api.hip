@@ -4,7 +4,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -180,11 +184,14 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
     const int64_t t = l0->t;
     hipError_t e;
     if (l0->prng == SG_MT19937) {
+        uint32_t *st[2], *rb[2];
         for (int r = 0; r < n; ++r) {
-            e = launch_mt_fill(lats[r]->mt_state, lats[r]->rbuf, lats[r]->L, t, l0->stream);
-            if (e != hipSuccess)
-                return hip_fail(e, "MT19937 fill");
+            st[r] = lats[r]->mt_state;
+            rb[r] = lats[r]->rbuf;
         }
+        e = launch_mt_fill(st, rb, n, l0->L, t, l0->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "MT19937 fill");
     }
     SweepArgs a{};
     a.J = l0->J;
@@ -575,7 +582,7 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
     if (t < lat->t || lat->t != 0)
         return fail(SG_EINVAL, "an MT19937 lattice can only be moved forward before its first sweep");
     for (int64_t k = 0; k < t; ++k) {
-        hipError_t e = launch_mt_fill(lat->mt_state, lat->rbuf, lat->L, k, lat->stream);
+        hipError_t e = launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream);
         if (e != hipSuccess)
             return hip_fail(e, "MT19937 fill");
     }
@@ -607,6 +614,130 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
         lat->tile_x = lat->tile_y = 0;
         lat->z_chunk = z_chunk;
     }
+    return SG_OK;
+}
+
+namespace {
+struct TuneKey {
+    int dev, L, n, prng;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(dev, L, n, prng) < std::tie(o.dev, o.L, o.n, o.prng);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, 4>> g_tuned;
+}  // namespace
+
+int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *ms)
+{
+    if (!lats || n < 1 || n > 2)
+        return fail(SG_EINVAL, "autotune takes 1 or 2 lattices");
+    for (int r = 0; r < n; ++r)
+        if (!lats[r] || lats[r]->L != lats[0]->L || lats[r]->prng != lats[0]->prng || lats[r]->J != lats[0]->J ||
+            lats[r]->stream != lats[0]->stream)
+            return fail(SG_EMISMATCH, "autotune: lattices must share L, prng, couplings and stream");
+    sg_lattice *l0 = lats[0];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        dev = 0;
+    const TuneKey key{dev, l0->L, n, l0->prng};
+    std::array<int, 4> pick{0, 0, 0, 1};
+    double pick_ms = -1.0;
+    bool cached = false;
+    if (reps >= 0) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            pick = it->second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        const int nrep_launch = reps > 0 ? reps : 5;
+        uint64_t T[3];
+        sg_thresholds(1.0, l0->prng, T);
+        SweepArgs a{};
+        a.J = l0->J;
+        a.nrep = n;
+        a.L = l0->L;
+        a.prng = l0->prng;
+        a.minstd_a = 16807u;
+        a.T = Thresholds{T[0], T[1], T[2]};
+        for (int r = 0; r < n; ++r) {
+            a.src[r] = lats[r]->spins[lats[r]->cur];
+            a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
+            a.rnd[r] = l0->prng == SG_MINSTD ? lats[r]->seeds : lats[r]->rbuf;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0)
+                (void)hipEventDestroy(e0);
+            return fail(SG_EDEVICE, "autotune: cannot create events");
+        }
+        const int P = l0->L / 2;
+        const int txs[] = {8, 16, 32, 64};
+        const int tys[] = {4, 6, 8, 12, 16, 24};
+        const int bands[] = {1, 2};
+        double best_ms = 1e300;
+        int rc = SG_OK;
+        for (int tx : txs) {
+            if (tx > P)
+                continue;
+            for (int ty : tys) {
+                if (ty > l0->L || !fused_shape_ok(l0->L, n, tx, ty, 0))
+                    continue;
+                for (int band : bands) {
+                    hipError_t e = launch_sweep_fused(a, tx, ty, 0, band, l0->stream);  // warm-up
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e0, l0->stream);
+                    for (int k = 0; e == hipSuccess && k < nrep_launch; ++k)
+                        e = launch_sweep_fused(a, tx, ty, 0, band, l0->stream);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e1, l0->stream);
+                    if (e == hipSuccess)
+                        e = hipEventSynchronize(e1);
+                    float t_ms = 0.f;
+                    if (e == hipSuccess)
+                        e = hipEventElapsedTime(&t_ms, e0, e1);
+                    if (e != hipSuccess) {
+                        rc = hip_fail(e, "autotune launch");
+                        break;
+                    }
+                    const double per = (double)t_ms / nrep_launch;
+                    if (per < best_ms) {
+                        best_ms = per;
+                        pick = {tx, ty, 0, band};
+                    }
+                }
+                if (rc != SG_OK)
+                    break;
+            }
+            if (rc != SG_OK)
+                break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != SG_OK)
+            return rc;
+        if (pick[0] == 0)
+            return fail(SG_EINVAL, "autotune: no fused tile fits this lattice");
+        pick_ms = best_ms;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[key] = pick;
+    }
+    for (int r = 0; r < n; ++r) {
+        lats[r]->kernel = SG_KERNEL_FUSED;
+        lats[r]->tile_x = pick[0];
+        lats[r]->tile_y = pick[1];
+        lats[r]->z_chunk = pick[2];
+        lats[r]->band = pick[3];
+    }
+    if (best)
+        for (int k = 0; k < 4; ++k)
+            best[k] = pick[k];
+    if (ms)
+        *ms = pick_ms;
     return SG_OK;
 }
 

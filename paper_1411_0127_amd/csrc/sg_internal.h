@@ -172,7 +172,8 @@ hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s
 hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_minstd(uint32_t *seeds, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s);
-hipError_t launch_mt_fill(uint32_t *state, uint32_t *rbuf, int L, int64_t t, hipStream_t s);
+// Draws of sweep t for n (1 or 2) stream sets of side L.
+hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
 hipError_t launch_minstd_draws(const uint32_t *seeds, uint32_t *R, int L, uint32_t a, hipStream_t s);
 
 struct SweepArgs {

@@ -54,6 +54,7 @@ SIGNATURES = {
     "sg_sweep_count": (_i64, [_p]),
     "sg_set_sweep_count": (_i, [_p, _i64]),
     "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
+    "sg_autotune": (_i, [ctypes.POINTER(_p), _i, _i, _p, ctypes.POINTER(_d)]),
     "sg_destroy": (_i, [_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -212,6 +213,16 @@ class Lattice:
 def sweep_replicas(lats: Sequence[Lattice], n: int, beta: float):
     arr = (_p * len(lats))(*[l.handle for l in lats])
     _check(lib.sg_sweep_replicas(arr, len(lats), int(n), float(beta)))
+
+
+def autotune(lats: Sequence[Lattice], reps: int = 5):
+    """Pick the fastest fused tile for these lattices (1, or 2 replicas swept together);
+    returns ((tile_x, tile_y, z_chunk, band), ms per launch or -1 if taken from the cache)."""
+    arr = (_p * len(lats))(*[l.handle for l in lats])
+    best = np.zeros(4, dtype=np.int32)
+    ms = _d()
+    _check(lib.sg_autotune(arr, len(lats), int(reps), _ptr(best), ctypes.byref(ms)))
+    return tuple(int(v) for v in best), float(ms.value)
 
 
 def overlap(a: Lattice, b: Lattice):

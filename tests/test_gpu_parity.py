@@ -284,3 +284,29 @@ def test_L256_two_replicas_on_two_bit_planes(sg, prng):
                                        PRNG[prng], seeds)
             one.sweep(nsweeps, beta)
             assert np.array_equal((w >> sh) & np.uint64(1), one.words()), f"replica {r} plane {j}"
+
+
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_autotune_leaves_state_and_parity(sg, prng):
+    say("autotune", prng)
+    L, beta = 32, 0.9
+    a = sg.Lattice(L, 64, prng, coupling_seed=5, spin_seed=6, replica=0)
+    b = sg.Lattice.replica_of(a, spin_seed=6, replica=1)
+    ra = oracle_for(L, 64, prng, 5, 6, 0)
+    rb = oracle_for(L, 64, prng, 5, 6, 1)
+    sg.sweep_replicas([a, b], 2, beta)
+    ra.sweep(2, beta)
+    rb.sweep(2, beta)
+    wa, wb = a.words(), b.words()
+    shape, ms = sg.autotune([a, b], reps=2)
+    assert shape[0] > 0 and shape[1] > 0 and ms > 0
+    assert a.t == 2 and b.t == 2
+    assert np.array_equal(a.words(), wa) and np.array_equal(b.words(), wb)
+    again, ms2 = sg.autotune([a, b], reps=2)
+    assert again == shape and ms2 < 0  # taken from the cache
+    for _ in range(3):
+        sg.sweep_replicas([a, b], 1, beta)
+        ra.sweep(1, beta)
+        rb.sweep(1, beta)
+    assert_same(a.words(), ra, 64, "after autotune, replica 0")
+    assert_same(b.words(), rb, 64, "after autotune, replica 1")
