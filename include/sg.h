@@ -158,6 +158,43 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
  * tile_x, tile_y, z_chunk, band; ms (may be NULL) the best time per launch. */
 int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *ms);
 
+/* ---- Batches: many lattices advanced together --------------------------------
+ * A batch holds lattices of any sizes (one replica each, SG_MINSTD, all on the
+ * batch's stream, which must not be the legacy default stream when graphs are
+ * used), each with its own inverse temperature and sweep count.  A run queues
+ * rounds; a round sweeps every lattice that has sweeps left, all of them in one
+ * launch (one work item per fused tile and z chunk of every lattice).  The spins
+ * of each lattice after n sweeps are bit-identical to n calls of sg_sweep on it
+ * alone.  Lattices join with sg_batch_add and leave when their sweeps are done
+ * (sg_batch_take_finished); both take effect at run boundaries.  A lattice must
+ * not be swept or destroyed while it is in a batch. */
+typedef struct sg_batch sg_batch;
+
+/* Device workspace for a batch of up to max_lattices lattices and max_items work
+ * items (tiles x z chunks, summed over the lattices it holds at once). */
+int sg_batch_footprint(int max_lattices, int max_items, size_t *dev_bytes);
+int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_bytes, void *stream,
+                    sg_batch **out);
+
+/* Queue nsweeps >= 1 sweeps at beta for lat. */
+int sg_batch_add(sg_batch *b, sg_lattice *lat, int64_t nsweeps, double beta);
+
+/* Queue up to max_rounds rounds (fewer if every lattice finishes first).  With
+ * rounds_per_graph > 0 the rounds are captured once into a hipGraph of that many
+ * rounds (re-captured when the set of work items changes) and replayed.  Returns
+ * as soon as the work is queued; lattices whose sweeps are all queued move to the
+ * finished list.  *rounds_done (may be NULL) = rounds queued. */
+int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t *rounds_done);
+
+/* Move up to max finished lattices to out[]; *n = how many. */
+int sg_batch_take_finished(sg_batch *b, sg_lattice **out, int max, int *n);
+
+/* Lattices with sweeps left, finished lattices not yet taken, and the work items
+ * the active lattices need (any output may be NULL). */
+int sg_batch_size(const sg_batch *b, int *active, int *finished, int *items);
+
+int sg_batch_destroy(sg_batch *b);
+
 /* Release the handle (never the caller's device buffer). */
 int sg_destroy(sg_lattice *lat);
 

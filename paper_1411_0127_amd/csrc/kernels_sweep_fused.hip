@@ -235,21 +235,13 @@ struct Ring {
     static constexpr int value = NREP == 1 ? 6 : 5;
 };
 
+// The march of one tile: tile = tile index within the lattice (z chunk major).
 template <int PRNG, int NREP, int... Is>
-__device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint64_t *lds, std::integer_sequence<int, Is...>);
-
-template <int PRNG, int NREP>
-__global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
-{
-    extern __shared__ uint64_t lds[];
-    Lane c;
-    fused_march<PRNG, NREP>(p, c, lds, std::make_integer_sequence<int, Ring<NREP>::value>{});
-}
-
-template <int PRNG, int NREP, int... Is>
-__device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint64_t *lds, std::integer_sequence<int, Is...>)
+__device__ __forceinline__ void fused_march(const FusedParams &p, const int tile, uint64_t *lds,
+                                            std::integer_sequence<int, Is...>)
 {
     constexpr int NS = sizeof...(Is);
+    Lane c;
     // one LDS set: blue_old[NREP], red_new[NREP], jx_hi, jy_lo, jy_hi, each with a slot
     // per tile lane plus one that threads outside the tile write, so that every
     // thread publishes without a branch
@@ -257,9 +249,6 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint6
     c.set_words = c.nl * (2 * NREP + 3);
 
     // ---- tile of this workgroup ---------------------------------------------
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int tile = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     // Tile order within a z chunk: groups of `band` tile rows; inside a group the
     // tiles go down a column of the group, then to the next column.  The workgroups
     // that run together on one XCD then form a block `band` tiles tall, whose
@@ -385,6 +374,94 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, Lane &c, uint6
 #undef SG_FUSED_STEP
 }
 
+// Block b -> work item: blocks are dealt to the 8 XCDs round robin, so consecutive
+// items go to the same XCD when the grid is a multiple of 8.
+__device__ __forceinline__ int xcd_item(int b, int nb) { return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b; }
+
+template <int PRNG, int NREP>
+__global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
+{
+    extern __shared__ uint64_t lds[];
+    fused_march<PRNG, NREP>(p, xcd_item(blockIdx.x, gridDim.x), lds,
+                            std::make_integer_sequence<int, Ring<NREP>::value>{});
+}
+
+// 16807^(t+1) mod (2^31 - 1), by square and multiply (uniform, scalar unit).
+__device__ __forceinline__ uint32_t minstd_power(int64_t t)
+{
+    uint64_t result = 1, base = 16807;
+    uint64_t e = (uint64_t)t + 1;
+    while (e) {
+        if (e & 1) {
+            const uint64_t q = result * base;
+            result = (q & 0x7FFFFFFFull) + (q >> 31);
+            result = result >= 0x7FFFFFFFull ? result - 0x7FFFFFFFull : result;
+        }
+        const uint64_t q = base * base;
+        base = (q & 0x7FFFFFFFull) + (q >> 31);
+        base = base >= 0x7FFFFFFFull ? base - 0x7FFFFFFFull : base;
+        e >>= 1;
+    }
+    return (uint32_t)result;
+}
+
+// Many lattices, one sweep each per launch ("round").  Work items of all lattices
+// are numbered consecutively; item_lat maps an item to its lattice.  A lattice
+// takes part in round r while r < its sweep count for this run; its sweep index is
+// t0 + r, its current spins are buffer c0 ^ (r & 1).  The round number is read
+// from device memory, so a captured graph of rounds replays without new
+// arguments.
+__global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *__restrict__ E,
+                                                             const uint32_t *__restrict__ item_lat, int nitems,
+                                                             const int64_t *__restrict__ round_ctr)
+{
+    extern __shared__ uint64_t lds[];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nitems)
+        return;
+    const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
+    const BatchEntry &e = E[li];
+    const int64_t r = *round_ctr;
+    if (r >= e.nsweeps)
+        return;
+    FusedParams p;
+    p.J = e.J;
+    const int c = e.c0 ^ (int)(r & 1);
+    p.src[0] = e.spins[c];
+    p.dst[0] = e.spins[c ^ 1];
+    p.rnd[0] = e.seeds;
+    p.src[1] = p.src[0];
+    p.dst[1] = p.dst[0];
+    p.rnd[1] = p.rnd[0];
+    p.L = e.L;
+    p.P = e.L / 2;
+    p.TXp = e.TXp;
+    p.TY = e.TY;
+    p.ZC = e.ZC;
+    p.EX = e.TXp + 2;
+    p.EY = e.TY + 4;
+    p.ntx = e.ntx;
+    p.nty = e.nty;
+    p.nzc = e.nzc;
+    p.WE = e.WE;
+    p.band = e.band;
+    p.a = minstd_power(e.t0 + r);
+    p.T = Thresholds{e.t4, e.t8, e.t12};
+    fused_march<SG_MINSTD, 1>(p, item - e.item0, lds, std::make_integer_sequence<int, Ring<1>::value>{});
+}
+
+__global__ void k_round_advance(int64_t *round_ctr)
+{
+    if (threadIdx.x == 0)
+        round_ctr[threadIdx.x] += 1;
+}
+
+__global__ void k_round_reset(int64_t *round_ctr)
+{
+    if (threadIdx.x == 0)
+        round_ctr[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 static size_t fused_lds_bytes(int nrep, int tile_x, int tile_y)
@@ -482,6 +559,49 @@ static int choose_z_chunk(int L, int64_t tiles, int64_t slots)
         }
     }
     return best_zc;
+}
+
+bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band)
+{
+    if (!fused_shape_ok(L, 1, tile_x, tile_y, z_chunk) || z_chunk < 1)
+        return false;
+    const int P = L / 2;
+    e.L = L;
+    e.TXp = tile_x;
+    e.TY = tile_y;
+    e.ZC = z_chunk;
+    e.ntx = (P + tile_x - 1) / tile_x;
+    e.nty = (L + tile_y - 1) / tile_y;
+    e.nzc = (L + z_chunk - 1) / z_chunk;
+    e.WE = fused_waves_even(tile_x, tile_y);
+    e.band = band < 1 ? 1 : (band > e.nty ? e.nty : band);
+    e.nitems = e.ntx * e.nty * e.nzc;
+    return true;
+}
+
+size_t fused_batch_lds_bytes(int tile_x, int tile_y) { return fused_lds_bytes(1, tile_x, tile_y); }
+
+hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
+                              size_t lds, hipStream_t s)
+{
+    if (nitems < 1)
+        return hipSuccess;
+    if (lds > (size_t)max_lds_bytes())
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_fused_batch, dim3((unsigned)nitems), dim3(kMaxThreads), lds, s, E, item_lat, nitems, round_ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_advance, dim3(1), dim3(64), 0, s, round_ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(64), 0, s, round_ctr);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)

@@ -1,0 +1,323 @@
+// Batch runtime of libsg: many lattices of different sizes, temperatures and
+// sweep counts advanced together.  Each round sweeps every lattice that still has
+// sweeps to do, all of them in one launch of k_fused_batch (one work item per
+// tile and z chunk of every lattice).  Rounds run eagerly or replay a captured
+// hipGraph of `rounds_per_graph` rounds; the round number lives in device memory
+// so the graph needs no new arguments.  Lattices join and leave between runs: a
+// serving loop admits and retires at those boundaries.
+//
+// Every site update is the same arithmetic as a sweep of the lattice alone, with
+// the same keyed streams, so a lattice's spins after n sweeps do not depend on
+// what else was in the batch.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+struct sg_batch {
+    struct Job {
+        sg_lattice *lat;
+        int64_t left;  // sweeps still to do
+        double beta;
+    };
+    hipStream_t stream = nullptr;
+    int max_lat = 0, max_items = 0;
+    sg::BatchEntry *d_entries = nullptr;
+    uint32_t *d_item_lat = nullptr;
+    int64_t *d_round = nullptr;
+    std::vector<Job> jobs;
+    std::vector<sg_lattice *> finished;
+    std::vector<sg::BatchEntry> h_entries;
+    std::vector<uint32_t> h_item_lat;
+    int nitems = 0;
+    size_t lds = 0;
+    bool layout_dirty = true;
+    // captured graph of G rounds for (nitems, lds)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_rounds = 0, graph_items = -1;
+    size_t graph_lds = 0;
+};
+
+namespace sg {
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void drop_graph(sg_batch *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_rounds = 0;
+    b->graph_items = -1;
+}
+
+// Tile of a lattice inside a batch: the autotuned or default fused tile, z chunks
+// of up to 128 planes so that work items of big lattices stay comparable.
+int batch_tile(const sg_lattice *lat, BatchEntry &e)
+{
+    int tx = lat->tile_x, ty = lat->tile_y, zc = 0;
+    if (tx <= 0 || ty <= 0)
+        fused_default_shape(lat->L, 1, tx, ty, zc);
+    zc = lat->L <= 128 ? lat->L : std::max(64, std::min(128, lat->L / 4));
+    if (!fill_batch_entry(e, lat->L, tx, ty, zc, lat->band > 0 ? lat->band : 1))
+        return fail(SG_EINVAL, "no fused tile fits a lattice of side " + std::to_string(lat->L));
+    return SG_OK;
+}
+
+// Lay out the work items of the current jobs (after jobs joined or left).
+int build_layout(sg_batch *b)
+{
+    b->h_entries.assign(b->jobs.size(), BatchEntry{});
+    b->h_item_lat.clear();
+    size_t lds = 0;
+    int items = 0;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        BatchEntry &e = b->h_entries[j];
+        const int rc = batch_tile(b->jobs[j].lat, e);
+        if (rc != SG_OK)
+            return rc;
+        e.item0 = items;
+        if ((int64_t)items + e.nitems > b->max_items)
+            return fail(SG_EINVAL, "batch work items exceed max_items");
+        items += e.nitems;
+        b->h_item_lat.insert(b->h_item_lat.end(), (size_t)e.nitems, (uint32_t)j);
+        lds = std::max(lds, fused_batch_lds_bytes(e.TXp, e.TY));
+    }
+    b->nitems = items;
+    b->lds = lds;
+    b->layout_dirty = false;
+    return SG_OK;
+}
+
+int record_round(sg_batch *b)
+{
+    hipError_t e = launch_fused_batch(b->d_entries, b->d_item_lat, b->nitems, b->d_round, b->lds, b->stream);
+    if (e == hipSuccess)
+        e = launch_round_advance(b->d_round, b->stream);
+    return e == hipSuccess ? SG_OK : hip_fail(e, "batch round");
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sg_batch_footprint(int max_lattices, int max_items, size_t *dev_bytes)
+{
+    if (max_lattices < 1 || max_items < 1 || !dev_bytes)
+        return fail(SG_EINVAL, "bad batch size");
+    *dev_bytes = align256(sizeof(BatchEntry) * (size_t)max_lattices) + align256(4 * (size_t)max_items) + 256;
+    return SG_OK;
+}
+
+int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_bytes, void *stream, sg_batch **out)
+{
+    if (!out)
+        return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    if (sg_batch_footprint(max_lattices, max_items, &need) != SG_OK)
+        return SG_EINVAL;
+    if (!dev_buf || dev_bytes < need)
+        return fail(SG_EINVAL, "batch device buffer too small: need " + std::to_string(need) + " bytes");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
+        return fail(SG_EINVAL, "batch device buffer must be 256-byte aligned");
+    sg_batch *b = new (std::nothrow) sg_batch();
+    if (!b)
+        return fail(SG_ENOMEM, "out of host memory");
+    uint8_t *p = static_cast<uint8_t *>(dev_buf);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->max_lat = max_lattices;
+    b->max_items = max_items;
+    b->d_entries = reinterpret_cast<BatchEntry *>(p);
+    p += align256(sizeof(BatchEntry) * (size_t)max_lattices);
+    b->d_item_lat = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * (size_t)max_items);
+    b->d_round = reinterpret_cast<int64_t *>(p);
+    *out = b;
+    return SG_OK;
+}
+
+int sg_batch_add(sg_batch *b, sg_lattice *lat, int64_t nsweeps, double beta)
+{
+    if (!b || !lat)
+        return fail(SG_EINVAL, "NULL argument");
+    if (nsweeps < 1)
+        return fail(SG_EINVAL, "nsweeps must be >= 1");
+    if (std::isnan(beta) || beta < 0)
+        return fail(SG_EINVAL, "beta must be >= 0");
+    if (lat->prng != SG_MINSTD)
+        return fail(SG_EINVAL, "batched sweeps take MINSTD lattices");
+    if (lat->stream != b->stream)
+        return fail(SG_EMISMATCH, "a batched lattice must use the batch's stream");
+    if ((int)b->jobs.size() >= b->max_lat)
+        return fail(SG_EINVAL, "batch is full (max_lattices)");
+    for (const auto &j : b->jobs)
+        if (j.lat == lat)
+            return fail(SG_EINVAL, "lattice already in the batch");
+    b->jobs.push_back({lat, nsweeps, beta});
+    b->layout_dirty = true;
+    return SG_OK;
+}
+
+int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t *rounds_done)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    if (rounds_done)
+        *rounds_done = 0;
+    if (max_rounds < 0 || rounds_per_graph < 0)
+        return fail(SG_EINVAL, "negative round count");
+    if (b->jobs.empty() || max_rounds == 0)
+        return SG_OK;
+    int rc = SG_OK;
+    if (b->layout_dirty) {
+        rc = build_layout(b);
+        if (rc != SG_OK)
+            return rc;
+    }
+    int64_t R = 0;
+    for (const auto &j : b->jobs)
+        R = std::max(R, j.left);
+    R = std::min(R, max_rounds);
+    // per-run lattice state: sweep count, current buffer, sweeps in this run
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        BatchEntry &e = b->h_entries[j];
+        const sg_batch::Job &job = b->jobs[j];
+        e.J = job.lat->J;
+        e.spins[0] = job.lat->spins[0];
+        e.spins[1] = job.lat->spins[1];
+        e.seeds = job.lat->seeds;
+        e.c0 = job.lat->cur;
+        e.t0 = job.lat->t;
+        e.nsweeps = std::min(job.left, R);
+        uint64_t T[3];
+        sg_thresholds(job.beta, SG_MINSTD, T);
+        e.t4 = T[0];
+        e.t8 = T[1];
+        e.t12 = T[2];
+    }
+    // pageable sources: the runtime stages them before these calls return, so the
+    // host vectors may change for the next run right away
+    hipError_t e = hipMemcpyAsync(b->d_entries, b->h_entries.data(), sizeof(BatchEntry) * b->h_entries.size(),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_item_lat, b->h_item_lat.data(), 4 * b->h_item_lat.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = launch_round_reset(b->d_round, b->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch setup");
+
+    int64_t done = 0;
+    const int G = rounds_per_graph;
+    if (G > 0 && R >= G) {
+        if (!b->exec || b->graph_rounds != G || b->graph_items != b->nitems || b->graph_lds != b->lds) {
+            drop_graph(b);
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess)
+                return hip_fail(e, "begin capture");
+            for (int g = 0; g < G && rc == SG_OK; ++g)
+                rc = record_round(b);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(b->stream, &graph);
+            if (rc != SG_OK) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return hip_fail(e, "end capture");
+            b->graph = graph;
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return hip_fail(e, "graph instantiate");
+            }
+            b->graph_rounds = G;
+            b->graph_items = b->nitems;
+            b->graph_lds = b->lds;
+        }
+        for (; done + G <= R; done += G) {
+            e = hipGraphLaunch(b->exec, b->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "graph launch");
+        }
+    }
+    for (; done < R; ++done) {
+        rc = record_round(b);
+        if (rc != SG_OK)
+            return rc;
+    }
+    // the host view of every lattice moves with the queued rounds
+    std::vector<sg_batch::Job> keep;
+    for (auto &job : b->jobs) {
+        const int64_t d = std::min(job.left, R);
+        job.lat->t += d;
+        job.lat->cur ^= (int)(d & 1);
+        job.left -= d;
+        if (job.left == 0)
+            b->finished.push_back(job.lat);
+        else
+            keep.push_back(job);
+    }
+    if (keep.size() != b->jobs.size())
+        b->layout_dirty = true;
+    b->jobs.swap(keep);
+    if (rounds_done)
+        *rounds_done = done;
+    return SG_OK;
+}
+
+int sg_batch_take_finished(sg_batch *b, sg_lattice **out, int max, int *n)
+{
+    if (!b || !n || (max > 0 && !out))
+        return fail(SG_EINVAL, "NULL argument");
+    int k = 0;
+    while (k < max && !b->finished.empty()) {
+        out[k++] = b->finished.front();
+        b->finished.erase(b->finished.begin());
+    }
+    *n = k;
+    return SG_OK;
+}
+
+int sg_batch_size(const sg_batch *b, int *active, int *finished, int *items)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    if (active)
+        *active = (int)b->jobs.size();
+    if (finished)
+        *finished = (int)b->finished.size();
+    if (items) {
+        int n = 0;
+        for (const auto &job : b->jobs) {
+            BatchEntry e{};
+            if (batch_tile(job.lat, e) == SG_OK)
+                n += e.nitems;
+        }
+        *items = n;
+    }
+    return SG_OK;
+}
+
+int sg_batch_destroy(sg_batch *b)
+{
+    if (!b)
+        return SG_OK;
+    drop_graph(b);
+    delete b;
+    return SG_OK;
+}
+
+}  // extern "C"

@@ -192,6 +192,26 @@ bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
 
+// One lattice of a batched launch (device copy; see k_fused_batch).
+struct BatchEntry {
+    const uint64_t *J;
+    uint64_t *spins[2];
+    const uint32_t *seeds;
+    int L, TXp, TY, ZC, ntx, nty, nzc, WE, band;
+    int c0;          // current spin buffer when the run starts
+    int item0;       // first work item
+    int nitems;      // work items: tiles x z chunks
+    int64_t t0;      // sweeps done when the run starts
+    int64_t nsweeps; // sweeps to do in this run
+    uint64_t t4, t8, t12;
+};
+bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band);
+size_t fused_batch_lds_bytes(int tile_x, int tile_y);
+hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
+                              size_t lds, hipStream_t s);
+hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
+hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
+
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,
                               hipStream_t s);
 hipError_t launch_count_diff(const uint64_t *A, const uint64_t *B, int64_t V, uint64_t *partials, int &nblocks,

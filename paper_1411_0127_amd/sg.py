@@ -55,6 +55,13 @@ SIGNATURES = {
     "sg_set_sweep_count": (_i, [_p, _i64]),
     "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
     "sg_autotune": (_i, [ctypes.POINTER(_p), _i, _i, _p, ctypes.POINTER(_d)]),
+    "sg_batch_footprint": (_i, [_i, _i, ctypes.POINTER(_sz)]),
+    "sg_batch_create": (_i, [_i, _i, _p, _sz, _p, ctypes.POINTER(_p)]),
+    "sg_batch_add": (_i, [_p, _p, _i64, _d]),
+    "sg_batch_run": (_i, [_p, _i64, _i, ctypes.POINTER(_i64)]),
+    "sg_batch_take_finished": (_i, [_p, ctypes.POINTER(_p), _i, ctypes.POINTER(_i)]),
+    "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "sg_batch_destroy": (_i, [_p]),
     "sg_destroy": (_i, [_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -230,3 +237,59 @@ def overlap(a: Lattice, b: Lattice):
     q = np.zeros(a.nsamples, dtype=np.float64)
     _check(lib.sg_overlap(a.handle, b.handle, _ptr(nd), _ptr(q)))
     return nd, q
+
+
+class Batch:
+    """Lattices of mixed sizes advanced together, one launch per round (sg_batch_*).
+
+    The lattices must be MINSTD single replicas created on ``stream``; use a
+    non-default stream when rounds are replayed from graphs."""
+
+    def __init__(self, max_lattices: int, max_items: int, stream, device=None):
+        torch = _torch()
+        n = _sz()
+        _check(lib.sg_batch_footprint(int(max_lattices), int(max_items), ctypes.byref(n)))
+        self.device = torch.device(device if device is not None else "cuda")
+        self.buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        h = _p()
+        _check(lib.sg_batch_create(int(max_lattices), int(max_items), _p(self.buf.data_ptr()), int(n.value),
+                                   _p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self._members = {}  # handle value -> Lattice, keeps them alive while queued
+
+    def add(self, lat: Lattice, nsweeps: int, beta: float):
+        _check(lib.sg_batch_add(self.handle, lat.handle, int(nsweeps), float(beta)))
+        self._members[lat.handle.value] = lat
+
+    def run(self, max_rounds: int, rounds_per_graph: int = 0) -> int:
+        done = _i64()
+        _check(lib.sg_batch_run(self.handle, int(max_rounds), int(rounds_per_graph), ctypes.byref(done)))
+        return int(done.value)
+
+    def take_finished(self):
+        out = []
+        while True:
+            arr = (_p * 64)()
+            n = _i()
+            _check(lib.sg_batch_take_finished(self.handle, arr, 64, ctypes.byref(n)))
+            for k in range(n.value):
+                out.append(self._members.pop(arr[k]))
+            if n.value < 64:
+                return out
+
+    def size(self):
+        a, f, it = _i(), _i(), _i()
+        _check(lib.sg_batch_size(self.handle, ctypes.byref(a), ctypes.byref(f), ctypes.byref(it)))
+        return int(a.value), int(f.value), int(it.value)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib.sg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
