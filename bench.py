@@ -35,6 +35,16 @@ WORKLOADS = {
     "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd", variant=None,
                desc="L=1024 periodic cube, 64 samples multispin-coded per uint64, J=+-1 (p=1/2), "
                     "random start, T=1.1, 100 sweeps per step, MINSTD per-site streams"),
+    # 256 lattices in one batch: L from {32,...,512}, T in [0.5, 1.5], 100-2000 sweeps
+    "c3": dict(L=0, replicas=1, beta=0, sweeps=0, prng="minstd", variant=None,
+               desc="batch of 256 lattices, L uniform over {32,64,128,256,512}, 64 samples each, T uniform "
+                    "[0.5,1.5], sweeps uniform 100-2000 (times sweep_scale), all present at t=0, admitted by "
+                    "HBM budget, one launch per round, MINSTD"),
+    # Poisson job stream at 50 jobs/s: L from {64,...,512}, T in [0.6, 1.4], 10^U(2,4) sweeps
+    "c4": dict(L=0, replicas=1, beta=0, sweeps=0, prng="minstd", variant=None,
+               desc="served Poisson job stream (mean 50 jobs/s), L uniform over {64,128,256,512}, 64 samples, "
+                    "T uniform [0.6,1.4], sweeps 10^U(2,4) (times sweep_scale), admitted by HBM budget, "
+                    "continuous batching, MINSTD"),
     # L=16 cube, 1 sample, energy after every sweep
     "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=None,
                desc="L=16 periodic cube, 1 sample, T=0.7, 1000 sweeps per step, MINSTD"),
@@ -143,6 +153,73 @@ def run_gpu(args, wl):
     return main, variant
 
 
+def _budget_bytes(torch, frac=0.8):
+    return int(torch.cuda.get_device_properties(0).total_memory * frac)
+
+
+def solo_sweep_ms(sg, torch, L, nsw=5):
+    """ms per sweep of one lattice alone (autotuned fused kernel), on its own stream."""
+    stream = torch.cuda.Stream(torch.device("cuda:0"))
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)
+    if L >= 64:
+        sg.autotune([lat], reps=3)
+    lat.sweep(2, 1.0)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    lat.sweep(nsw, 1.0)
+    b.record(stream)
+    torch.cuda.synchronize()
+    lat.close()
+    return a.elapsed_time(b) / nsw
+
+
+def run_mix(args, wl):
+    """Batched (c3) or served (c4) mix through the continuous-batching server."""
+    import torch
+
+    from paper_1411_0127_amd import sg
+    from paper_1411_0127_amd.serve import GpuBackend, Server, trace_batch, trace_served
+
+    scale = args.sweep_scale
+    budget = _budget_bytes(torch)
+    out = {}
+    if args.workload == "c3":
+        jobs = trace_batch(args.jobs or 256, seed=args.seed, sweep_scale=scale)
+        be = GpuBackend(rounds_per_graph=8)
+        be.pretune(j.L for j in jobs)  # one-time per side, outside the measured span
+        rep = Server(be, budget, chunk_rounds=200, min_rounds=8).serve(jobs)
+        s = rep.summary()
+        sizes = sorted({j.L for j in jobs})
+        t_solo = {L: solo_sweep_ms(sg, torch, L) for L in sizes}
+        plain_s = sum(j.nsweeps * t_solo[j.L] for j in jobs) / 1e3
+        out["ps_per_flip"] = s["ps_per_flip_makespan"]
+        out["plain_ps_per_flip"] = plain_s * 1e12 / s["flips"]
+        out["batched_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
+        out["solo_ms_per_sweep"] = {str(L): round(v, 4) for L, v in t_solo.items()}
+        out["summary"] = s
+        out["bytes"] = sum(44 * j.L**3 * j.nsweeps for j in jobs)
+        out["seconds"] = s["makespan_s"]
+    else:
+        jobs = trace_served(args.jobs or 64, rate=50.0, seed=args.seed, sweep_scale=scale)
+        be = GpuBackend(rounds_per_graph=8)
+        be.pretune(j.L for j in jobs)
+        rep = Server(be, budget, chunk_rounds=100).serve(jobs)
+        s = rep.summary()
+        mean_job_s = s["busy_s"] / max(1, s["jobs"])
+        rate = 0.7 / max(mean_job_s, 1e-6)
+        jobs2 = trace_served(max(8, (args.jobs or 64) // 2), rate=rate, seed=args.seed + 1, sweep_scale=scale)
+        rep2 = Server(be, budget, chunk_rounds=100).serve(jobs2)
+        s2 = rep2.summary()
+        out["ps_per_flip"] = s["ps_per_flip_busy"]
+        out["summary"] = s
+        out["sub_saturating"] = dict(rate_jobs_per_s=rate, **s2)
+        out["bytes"] = sum(44 * j.L**3 * j.nsweeps for j in jobs)
+        out["seconds"] = s["busy_s"]
+    return out
+
+
 def cpu_baseline(wl, budget_s: float):
     """The oracle as it stands, single-threaded, on one sample of one replica."""
     import numpy as np
@@ -178,6 +255,10 @@ def main():
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep-scale", type=float, default=0.1,
+                    help="c3/c4: multiply every job's sweep count (the full mixes take minutes)")
+    ap.add_argument("--jobs", type=int, default=0, help="c3/c4: number of jobs (default 256 / 64)")
+    ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also make 3 device copies of BYTES bytes, for counter calibration")
     args = ap.parse_args()
@@ -189,6 +270,36 @@ def main():
         sys.exit(2)
 
     wl = WORKLOADS[args.workload]
+    if args.workload in ("c3", "c4"):
+        res = run_mix(args, wl)
+        gbs = res["bytes"] / res["seconds"] / 1e9
+        line = {
+            "metric": METRIC,
+            "value": round(res["ps_per_flip"], 6),
+            "unit": "ps/flip",
+            "n_gpus": 1,
+            "steps": 1,
+            "warmup": 0,
+            "ms_per_step": round(res["seconds"] * 1e3, 3),
+            "higher_is_better": False,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": wl["desc"], "sweep_scale": args.sweep_scale, "jobs": res["summary"]["jobs"],
+                       "seed": args.seed, "parallelism": "single GPU"},
+            "hbm_gbs_algorithmic": round(gbs, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "sg::k_fused_batch (all resident lattices, one launch per round)",
+                         "bytes_per_site": 44},
+        }
+        for k in ("plain_ps_per_flip", "batched_over_plain", "solo_ms_per_sweep", "sub_saturating"):
+            if k in res:
+                line[k] = res[k]
+        line["summary"] = res["summary"]
+        print(json.dumps(line), flush=True)
+        return
     main_res, variant = run_gpu(args, wl)
     if args.calibrate_copy:
         import torch

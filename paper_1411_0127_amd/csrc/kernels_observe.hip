@@ -95,15 +95,26 @@ __global__ __launch_bounds__(kThreads) void k_count_diff(const uint64_t *__restr
     block_flush(vc, partials);
 }
 
-__global__ void k_reduce_partials(const uint64_t *__restrict__ partials, int nblocks, uint64_t *__restrict__ out)
+// Sum the per-block rows: 16 threads per sample each add every 16th row, then
+// the 16 partial sums of a sample are added in LDS.
+__global__ __launch_bounds__(1024) void k_reduce_partials(const uint64_t *__restrict__ partials, int nblocks,
+                                                          uint64_t *__restrict__ out)
 {
-    const int j = threadIdx.x;
-    if (j >= 64)
-        return;
+    __shared__ uint64_t part[16][64];
+    const int j = threadIdx.x & 63;
+    const int q = threadIdx.x >> 6;
     uint64_t s = 0;
-    for (int b = 0; b < nblocks; ++b)
+    for (int b = q; b < nblocks; b += 16)
         s += partials[(size_t)b * 64 + j];
-    out[j] = s;
+    part[q][j] = s;
+    __syncthreads();
+    if (q == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            t += part[k][j];
+        out[j] = t;
+    }
 }
 
 int blocks_for(int64_t words_per_site, int64_t V)
@@ -146,7 +157,7 @@ hipError_t launch_count_diff(const uint64_t *A, const uint64_t *B, int64_t V, ui
 
 hipError_t launch_reduce_partials(const uint64_t *partials, int nblocks, uint64_t *out64, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partials, nblocks, out64);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, partials, nblocks, out64);
     return hipGetLastError();
 }
 

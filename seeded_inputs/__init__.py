@@ -115,6 +115,30 @@ def mt_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
     return (out(k, c) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
 
 
+def coupling_words_at(L: int, coupling_seed: int, sites: np.ndarray) -> np.ndarray:
+    """Coupling words J[3][len(sites)] of the given site indices (same values as
+    coupling_words(L, coupling_seed)[:, sites])."""
+    k = key(coupling_seed, TAG_J, 0)
+    i = np.asarray(sites, dtype=np.uint64)
+    return np.stack([out(k, np.uint64(1 + d) + np.uint64(3) * i) for d in range(3)])
+
+
+def spin_words_at(L: int, spin_seed: int, replica: int, sites: np.ndarray) -> np.ndarray:
+    k = key(spin_seed, TAG_SPIN, replica)
+    return out(k, np.asarray(sites, dtype=np.uint64) + np.uint64(1))
+
+
+def minstd_seeds_at(L: int, spin_seed: int, replica: int, sites: np.ndarray) -> np.ndarray:
+    k = key(spin_seed, TAG_MINSTD, replica)
+    h = out(k, np.asarray(sites, dtype=np.uint64) + np.uint64(1)) >> np.uint64(33)
+    return (np.uint64(1) + h % np.uint64(MINSTD_MODULUS - 1)).astype(np.uint32)
+
+
+def mt_seeds_at(L: int, spin_seed: int, replica: int, columns: np.ndarray) -> np.ndarray:
+    k = key(spin_seed, TAG_MT, replica)
+    return (out(k, np.asarray(columns, dtype=np.uint64) + np.uint64(1)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
 def gauge_words(L: int, gauge_seed: int) -> np.ndarray:
     """Random per-site gauge words g_i for the gauge-symmetry checks."""
     k = key(gauge_seed, 7, 0)

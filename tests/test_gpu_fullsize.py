@@ -1,0 +1,104 @@
+"""Parity at the full benchmark sizes, on sampled sites.
+
+After n sweeps a site's spin depends only on the old spins within Manhattan
+distance 2n (a red site reads its neighbours, a blue site reads new red
+neighbours).  The oracle therefore reproduces any sampled site exactly from a
+window of the global lattice of side 2h+2, h = 2n+1, around it: the wrap of the
+window corrupts only sites within 2n of its faces.  The window keeps the global
+colour parity, and every site in it gets its global couplings, spins and random
+numbers.  All 64 samples of each sampled site are compared bit for bit, in the
+launch configuration the benchmark times (autotuned fused tile)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def window_check(L, prng, cseed, sseed, replica, words, nsweeps, beta, centers):
+    h = 2 * nsweeps + 1
+    W = 2 * h + 2
+    bad = []
+    for (cx, cy, cz) in centers:
+        o = [cx - h, cy - h, cz - h]
+        if (o[0] + o[1] + o[2]) % 2:
+            o[0] -= 1  # keep the global colour of every window site
+        lz, ly, lx = np.meshgrid(np.arange(W), np.arange(W), np.arange(W), indexing="ij")
+        gx = (o[0] + lx.ravel()) % L
+        gy = (o[1] + ly.ravel()) % L
+        gz = (o[2] + lz.ravel()) % L
+        gsite = gx + L * (gy + L * gz)
+        J = si.coupling_words_at(L, cseed, gsite)
+        # local bond (i, i+d) must be the global bond (g, g+d): identical inside the window
+        S0 = si.spin_words_at(L, sseed, replica, gsite)
+        if prng == "minstd":
+            ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.MINSTD,
+                                       si.minstd_seeds_at(L, sseed, replica, gsite))
+            ref.sweep(nsweeps, beta)
+        else:
+            cols = (gx + L * gy).reshape(W, W, W)[0].ravel()  # window column -> global column
+            seeds = si.mt_seeds_at(L, sseed, replica, cols)
+            outs = np.stack([oracle.mt19937_outputs(int(s), nsweeps * L) for s in seeds])  # [W*W, n*L]
+            ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.MT19937, seeds)
+            zg = gz.reshape(W, W, W)
+            for t in range(nsweeps):
+                R = outs[np.tile(np.arange(W * W), W), (t * L + zg.ravel())].astype(np.uint32)
+                ref.sweep_with(R, beta)
+        lc = (cx - o[0]) + W * ((cy - o[1]) + W * (cz - o[2]))
+        want = ref.words()[lc]
+        got = words[cx + L * (cy + L * cz)]
+        if got != want:
+            bad.append(((cx, cy, cz), hex(int(got)), hex(int(want))))
+    assert not bad, f"{len(bad)} of {len(centers)} sampled sites differ, first {bad[:3]}"
+
+
+def centers_for(L, rng, n_random, tile=(32, 8)):
+    tx, ty = 2 * tile[0], tile[1]
+    xs = sorted({0, 1, L - 1, L - 2} | {v % L for k in (1, 2, 3) for v in (k * tx - 1, k * tx, k * tx + 1)})
+    ys = sorted({0, 1, L - 1} | {v % L for k in (1, 2) for v in (k * ty - 1, k * ty)})
+    zs = sorted({0, 1, L // 2 - 1, L // 2, L - 1})
+    pts = [(x, y, z) for x in xs[::2] for y in ys for z in zs]
+    pts += [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(n_random)]
+    return pts
+
+
+def test_L1024_sampled_sites_after_two_sweeps():
+    import torch
+
+    from paper_1411_0127_amd import sg
+
+    say("L1024 window parity")
+    L, beta, n = 1024, 1 / 1.1, 2
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=1, spin_seed=2)
+    shape, _ = sg.autotune([lat], reps=2)
+    lat.sweep(n, beta)
+    words = lat.words()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    window_check(L, "minstd", 1, 2, 0, words, n, beta, centers_for(L, np.random.default_rng(5), 120, shape[:2]))
+
+
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_L256_two_replicas_sampled_sites(prng):
+    from paper_1411_0127_amd import sg
+
+    say("L256 window parity", prng)
+    L, beta, n = 256, 1 / 0.7, 3
+    a = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0)
+    b = sg.Lattice.replica_of(a, spin_seed=2, replica=1)
+    shape, _ = sg.autotune([a, b], reps=2)
+    sg.sweep_replicas([a, b], n, beta)
+    wa, wb = a.words(), b.words()
+    rng = np.random.default_rng(9)
+    window_check(L, prng, 1, 2, 0, wa, n, beta, centers_for(L, rng, 60, shape[:2]))
+    window_check(L, prng, 1, 2, 1, wb, n, beta, centers_for(L, rng, 30, shape[:2]))
