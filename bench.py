@@ -55,11 +55,12 @@ def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
     """Bytes one fused sweep launch must move per lattice site.
 
     Couplings: 3 words read once for all replicas (24 B).  Per replica: the spin
-    word read and written (16 B) and the stream word read: the MINSTD seed (4 B)
-    or the MT19937 draw (4 B) -- the MT19937 fill kernel's state traffic is not
-    part of the sweep kernel.
+    word read and written (16 B); with MT19937 also the draw read from the
+    buffer the fill kernel wrote (4 B).  MINSTD draws are computed from the site
+    and the sweep, nothing is read for them.  The MT19937 fill kernel's own state
+    traffic is not part of the sweep kernel.
     """
-    return 24 + replicas * (16 + 4)
+    return 24 + replicas * (16 + (4 if prng == "mt19937" else 0))
 
 
 def kernel_source_sha() -> str:
@@ -199,7 +200,7 @@ def run_mix(args, wl):
         out["batched_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
         out["solo_ms_per_sweep"] = {str(L): round(v, 4) for L, v in t_solo.items()}
         out["summary"] = s
-        out["bytes"] = sum(44 * j.L**3 * j.nsweeps for j in jobs)
+        out["bytes"] = sum(40 * j.L**3 * j.nsweeps for j in jobs)
         out["seconds"] = s["makespan_s"]
     else:
         jobs = trace_served(args.jobs or 64, rate=50.0, seed=args.seed, sweep_scale=scale)
@@ -215,7 +216,7 @@ def run_mix(args, wl):
         out["ps_per_flip"] = s["ps_per_flip_busy"]
         out["summary"] = s
         out["sub_saturating"] = dict(rate_jobs_per_s=rate, **s2)
-        out["bytes"] = sum(44 * j.L**3 * j.nsweeps for j in jobs)
+        out["bytes"] = sum(40 * j.L**3 * j.nsweeps for j in jobs)
         out["seconds"] = s["busy_s"]
     return out
 
@@ -292,7 +293,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                          "kernel": "sg::k_fused_batch (all resident lattices, one launch per round)",
-                         "bytes_per_site": 44},
+                         "bytes_per_site": 40},
         }
         for k in ("plain_ps_per_flip", "batched_over_plain", "solo_ms_per_sweep", "sub_saturating"):
             if k in res:

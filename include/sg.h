@@ -23,13 +23,16 @@
  * Random streams (this library's convention; all keyed, so results do not depend
  * on the kernel, tile shape or launch split):
  *   SG_MINSTD  one MINSTD stream per site and replica; in sweep t (t = 0, 1, ...)
- *              site i draws 16807^(t+1) * seed_i mod (2^31 - 1);
+ *              site i draws 16807^(t+1) * seed_i mod (2^31 - 1), with
+ *              seed_i = 1 + ((fmix32((x + L*y) ^ fmix32(z ^ k)) >> 1) mod (2^31 - 2)),
+ *              fmix32 the MurmurHash3 finalizer, k the low 32 bits of the
+ *              replica's keyed word; no per-site state is stored;
  *   SG_MT19937 one MT19937 stream per x-y column and replica, seeded with
  *              init_genrand; in sweep t the site at height z draws the column's
  *              output number t*L + z.
- * The seeds, the initial spins and (unless given) the couplings come from the
- * SplitMix64 keyed generator documented with the seeded-input module
- * (Steele, Lea, Flood 2014), evaluated on the device.
+ * The keys, the MT19937 seeds, the initial spins and (unless given) the
+ * couplings come from the SplitMix64 keyed generator documented with the
+ * seeded-input module (Steele, Lea, Flood 2014), evaluated on the device.
  *
  * Acceptance: a proposal with dE > 0 is accepted iff R < T(dE) with
  * T(dE) = ceil(R_range * exp(-beta * dE)), R_range = 2^31 - 1 (MINSTD) or 2^32

@@ -1,5 +1,6 @@
 // Initialisation and random-stream kernels of libsg (gfx950).
-//  - couplings, spins and MINSTD seeds from the SplitMix64 keyed generator;
+//  - couplings and spins from the SplitMix64 keyed generator (MINSTD seeds are
+//    a keyed hash of the site, evaluated where they are used);
 //  - MT19937 (Matsumoto-Nishimura 1998) per-column streams: init_genrand, and a
 //    per-sweep fill of the L draws every column needs (Sec. 3 of the paper: a
 //    per-stream MT19937 whose state is laid out so that consecutive streams are
@@ -35,18 +36,6 @@ __global__ void k_init_spins(uint64_t *__restrict__ S, int64_t V, uint64_t key)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
         S[i] = sm_out(key, 1ull + (uint64_t)i);
-}
-
-__global__ void k_init_minstd(uint32_t *__restrict__ seeds, int64_t V, uint64_t key)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
-        seeds[i] = minstd_seed_from(sm_out(key, 1ull + (uint64_t)i));
-}
-
-__global__ void k_minstd_draws(const uint32_t *__restrict__ seeds, uint32_t *__restrict__ R, int64_t V, uint32_t a)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x)
-        R[i] = minstd_jump(a, seeds[i]);
 }
 
 // init_genrand of column c's stream with seed = low 32 bits of its keyed word.
@@ -145,20 +134,6 @@ hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
     hipLaunchKernelGGL(k_init_spins, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, S, V, key);
-    return hipGetLastError();
-}
-
-hipError_t launch_init_minstd(uint32_t *seeds, int L, uint64_t key, hipStream_t s)
-{
-    const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_init_minstd, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, seeds, V, key);
-    return hipGetLastError();
-}
-
-hipError_t launch_minstd_draws(const uint32_t *seeds, uint32_t *R, int L, uint32_t a, hipStream_t s)
-{
-    const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_minstd_draws, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, seeds, R, V, a);
     return hipGetLastError();
 }
 

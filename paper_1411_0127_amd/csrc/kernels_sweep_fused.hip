@@ -47,6 +47,7 @@ struct FusedParams {
     int WE;              // waves holding the even tile rows
     int band;            // tile rows per group of the tile order
     uint32_t a;          // MINSTD multiplier of this sweep
+    uint32_t mk[2];      // MINSTD key per replica
     Thresholds T;
 };
 
@@ -99,7 +100,7 @@ struct Offsets {
     uint32_t r;   // random-stream words (4 bytes per site)
 };
 
-template <int NREP>
+template <int PRNG, int NREP>
 __device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Offsets &o, Plane<NREP> &d)
 {
     const int64_t LL = (int64_t)p.L * p.L;
@@ -114,10 +115,14 @@ __device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Of
     ld_pair(plane_rsrc(p.J, 2 * V * 8 + qo, pb), o.f, d.jzlo, d.jzhi);
 #pragma unroll
     for (int r = 0; r < NREP; ++r) {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[r], (int64_t)q * LL * 4, pb / 2), o.r,
-                                                            0, 0);
-        d.rlo[r] = v.x;
-        d.rhi[r] = v.y;
+        if (PRNG == SG_MT19937) {  // MINSTD draws are computed from the site, nothing to load
+            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[r], (int64_t)q * LL * 4, pb / 2),
+                                                                o.r, 0, 0);
+            d.rlo[r] = v.x;
+            d.rhi[r] = v.y;
+        } else {
+            d.rlo[r] = d.rhi[r] = 0;
+        }
     }
 }
 
@@ -130,6 +135,7 @@ struct Lane {
     int nl, set_words;
     int me, ixm, ixp, iym, iyp;
     bool lane;
+    uint32_t col;  // in-plane index of the lane's even site, x + L*y
 };
 
 // Values carried from one step to the next.
@@ -138,6 +144,7 @@ struct Carry {
     uint64_t jzm2lo, jzm2hi;                 // jz of plane k-2
     uint64_t jxl, jyulo, jyuhi;              // neighbour couplings of plane k-1 (read at step k-1)
     uint64_t rn1[NREP], rn2[NREP];           // new red words of planes k-1, k-2
+    uint32_t zk1[NREP];                      // MINSTD plane key of plane k-1
 };
 
 // Step k of the march with the lane's half H = (y + k) & 1 known at compile time:
@@ -146,9 +153,9 @@ struct Carry {
 template <int PRNG, int NREP, int H>
 __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_blue,
                                            bool do_publish, const Plane<NREP> &A, const Plane<NREP> &B,
-                                           const Plane<NREP> &C, Carry<NREP> &cy, uint64_t (&rn)[NREP],
-                                           uint64_t (&wlo)[NREP], uint64_t (&whi)[NREP], uint64_t &jxl,
-                                           uint64_t &jyulo, uint64_t &jyuhi)
+                                           const Plane<NREP> &C, Carry<NREP> &cy, const uint32_t (&zk)[NREP],
+                                           uint64_t (&rn)[NREP], uint64_t (&wlo)[NREP], uint64_t (&whi)[NREP],
+                                           uint64_t &jxl, uint64_t &jyulo, uint64_t &jyuhi)
 {
     const uint64_t *S = lds + ((k + 2) & 1) * c.set_words;
     const int ixn = H ? c.ixp : c.ixm;  // lane holding the x-neighbour outside the pair
@@ -173,9 +180,8 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t other = sp<1 - H>(B, r);
             const uint64_t nxp = H ? nbx : other;
             const uint64_t nxm = H ? other : nbx;
-            uint32_t R = H ? B.rhi[r] : B.rlo[r];
-            if (PRNG == SG_MINSTD)
-                R = minstd_jump(p.a, R);
+            const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, zk[r]))
+                                                   : (H ? B.rhi[r] : B.rlo[r]);
             rn[r] = s ^ flip_mask(s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r), jxp, jyp, jzp, jxm, jym, jzm, R,
                                   p.T);
         }
@@ -197,9 +203,8 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t s = sp<H>(A, r);
             const uint64_t nxp = H ? nbx : cy.rn1[r];
             const uint64_t nxm = H ? cy.rn1[r] : nbx;
-            uint32_t R = H ? A.rhi[r] : A.rlo[r];
-            if (PRNG == SG_MINSTD)
-                R = minstd_jump(p.a, R);
+            const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, cy.zk1[r]))
+                                                   : (H ? A.rhi[r] : A.rlo[r]);
             const uint64_t bn =
                 s ^ flip_mask(s, nxp, nyp, rn[r], nxm, nym, cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
             wlo[r] = H ? cy.rn1[r] : bn;
@@ -290,6 +295,7 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
     const int L = p.L;
     const int64_t LL = (int64_t)L * L;
     const uint32_t col = (uint32_t)y * (uint32_t)L + 2u * (uint32_t)m;  // site index within a plane
+    c.col = col;
     Offsets o;
     o.s = c.lane ? col * 8u : kOOB;
     o.f = full ? col * 8u : kOOB;
@@ -305,13 +311,15 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
     const int kfirst = z0 - 1;
     const int klast = z0 + ZCe;
     Plane<NREP> ring[NS];  // ring[j] starts with plane kfirst - 1 + j
-    ((load_plane<NREP>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
+    ((load_plane<PRNG, NREP>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
 
     Carry<NREP> cy;
     cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
 #pragma unroll
-    for (int r = 0; r < NREP; ++r)
+    for (int r = 0; r < NREP; ++r) {
         cy.rn1[r] = cy.rn2[r] = 0;
+        cy.zk1[r] = 0;
+    }
 
     {
         // publish plane kfirst: its old blue words (half 1-H) and its couplings
@@ -337,11 +345,13 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
         uint64_t jxl, jyulo, jyuhi;                                                                               \
         const bool do_blue = k >= z0 + 1;                                                                         \
         const bool do_pub = k < klast;                                                                            \
+        uint32_t zk[NREP];                                                                                        \
+        _Pragma("unroll") for (int r = 0; r < NREP; ++r) zk[r] = minstd_plane_key((uint32_t)wrap(k), p.mk[r]);   \
         if ((ypar + k + L) & 1)                                                                                   \
-            fused_step<PRNG, NREP, 1>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, rn, wlo, whi, jxl, jyulo,     \
+            fused_step<PRNG, NREP, 1>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, rn, wlo, whi, jxl, jyulo, \
                                       jyuhi);                                                                     \
         else                                                                                                      \
-            fused_step<PRNG, NREP, 0>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, rn, wlo, whi, jxl, jyulo,     \
+            fused_step<PRNG, NREP, 0>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, rn, wlo, whi, jxl, jyulo, \
                                       jyuhi);                                                                     \
         {                                                                                                         \
             const int64_t qo = (int64_t)wrap(k - 1) * LL * 8;                                                     \
@@ -360,8 +370,9 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
         {                                                                                                         \
             cy.rn2[r] = cy.rn1[r];                                                                                \
             cy.rn1[r] = rn[r];                                                                                    \
+            cy.zk1[r] = zk[r];                                                                                    \
         }                                                                                                         \
-        load_plane<NREP>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);                       \
+        load_plane<PRNG, NREP>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);                 \
     }
 
     auto step = [&](auto I) -> bool {
@@ -429,10 +440,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
     const int c = e.c0 ^ (int)(r & 1);
     p.src[0] = e.spins[c];
     p.dst[0] = e.spins[c ^ 1];
-    p.rnd[0] = e.seeds;
+    p.rnd[0] = nullptr;
+    p.mk[0] = e.mk;
     p.src[1] = p.src[0];
     p.dst[1] = p.dst[0];
-    p.rnd[1] = p.rnd[0];
+    p.rnd[1] = nullptr;
+    p.mk[1] = e.mk;
     p.L = e.L;
     p.P = e.L / 2;
     p.TXp = e.TXp;
@@ -627,6 +640,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
         p.src[r] = a.src[r];
         p.dst[r] = a.dst[r];
         p.rnd[r] = a.rnd[r];
+        p.mk[r] = a.mk[r];
     }
     p.L = a.L;
     p.P = a.L / 2;

@@ -13,8 +13,8 @@ constexpr int kBlock = 256;
 
 template <int PRNG>
 __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, const uint64_t *__restrict__ J,
-                                                    const uint32_t *__restrict__ rnd, int L, int colour,
-                                                    uint32_t a, Thresholds T)
+                                                    const uint32_t *__restrict__ rnd, uint32_t mk, int L,
+                                                    int colour, uint32_t a, Thresholds T)
 {
     const int64_t LL = (int64_t)L * L;
     const int64_t V = LL * L;
@@ -34,7 +34,9 @@ __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, co
         const int64_t izp = (z + 1 == L) ? i - (V - LL) : i + LL;
         const int64_t izm = (z == 0) ? i + (V - LL) : i - LL;
         const uint64_t s = S[i];
-        const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(a, rnd[i]) : rnd[i];
+        const uint32_t R = (PRNG == SG_MINSTD)
+                               ? minstd_jump(a, minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk)))
+                               : rnd[i];
         const uint64_t m = flip_mask(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i],
                                      J[2 * V + i], J[ixm], J[V + iym], J[2 * V + izm], R, T);
         S[i] = s ^ m;
@@ -55,10 +57,10 @@ hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s)
         for (int colour = 0; colour < 2; ++colour) {
             if (a.prng == SG_MINSTD)
                 hipLaunchKernelGGL(k_twopass<SG_MINSTD>, dim3((unsigned)g), dim3(kBlock), 0, s, a.src[r], a.J,
-                                   a.rnd[r], a.L, colour, a.minstd_a, a.T);
+                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.T);
             else
                 hipLaunchKernelGGL(k_twopass<SG_MT19937>, dim3((unsigned)g), dim3(kBlock), 0, s, a.src[r], a.J,
-                                   a.rnd[r], a.L, colour, a.minstd_a, a.T);
+                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.T);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;

@@ -76,9 +76,6 @@ Carve carve(int L, int prng, bool own_J)
     c.J = off;
     if (own_J)
         off = align_up(off + 24 * V);
-    c.seeds = off;
-    if (prng == SG_MINSTD)
-        off = align_up(off + 4 * V);
     c.mt_state = off;
     if (prng == SG_MT19937)
         off = align_up(off + (size_t)4 * kMtN * L * L);
@@ -111,12 +108,11 @@ int init_streams(sg_lattice *lat)
     hipError_t e = launch_init_spins(lat->spins[0], lat->L, lat->key_spin, lat->stream);
     if (e != hipSuccess)
         return hip_fail(e, "init spins");
-    if (lat->prng == SG_MINSTD)
-        e = launch_init_minstd(lat->seeds, lat->L, lat->key_minstd, lat->stream);
-    else
+    if (lat->prng == SG_MT19937) {
         e = launch_init_mt(lat->mt_state, lat->L, lat->key_mt, lat->stream);
-    if (e != hipSuccess)
-        return hip_fail(e, "init streams");
+        if (e != hipSuccess)
+            return hip_fail(e, "init streams");
+    }
     return SG_OK;
 }
 
@@ -136,6 +132,7 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     lat->replica = replica;
     lat->key_spin = derive_key(spin_seed, kTagSpin, replica);
     lat->key_minstd = derive_key(spin_seed, kTagMinstd, replica);
+    lat->minstd_k = (uint32_t)lat->key_minstd;
     lat->key_mt = derive_key(spin_seed, kTagMt, replica);
     lat->base = static_cast<uint8_t *>(dev_buf);
     lat->bytes = dev_bytes;
@@ -143,7 +140,6 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     lat->spins[1] = reinterpret_cast<uint64_t *>(lat->base + c.spins1);
     if (own_J)
         lat->J = reinterpret_cast<uint64_t *>(lat->base + c.J);
-    lat->seeds = prng == SG_MINSTD ? reinterpret_cast<uint32_t *>(lat->base + c.seeds) : nullptr;
     lat->mt_state = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.mt_state) : nullptr;
     lat->rbuf = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.rbuf) : nullptr;
     lat->scratch = reinterpret_cast<uint64_t *>(lat->base + c.scratch);
@@ -203,7 +199,8 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
     for (int r = 0; r < n; ++r) {
         a.src[r] = lats[r]->spins[lats[r]->cur];
         a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
-        a.rnd[r] = l0->prng == SG_MINSTD ? lats[r]->seeds : lats[r]->rbuf;
+        a.rnd[r] = lats[r]->rbuf;
+        a.mk[r] = lats[r]->minstd_k;
     }
     int tx = 0, ty = 0, zc = 0;
     const int kind = pick_kernel(l0, n, tx, ty, zc);
@@ -551,17 +548,16 @@ int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
     if (lat->prng == SG_MT19937) {
         e = hipMemcpyAsync(out, lat->rbuf, 4 * n, hipMemcpyDeviceToHost, lat->stream);
     } else {
-        // MINSTD draws are a function of (seed, sweep): evaluate the last sweep's on
-        // the host from the device's seeds, with the device's own jump function.
-        std::vector<uint32_t> seeds(n);
-        e = hipMemcpyAsync(seeds.data(), lat->seeds, 4 * n, hipMemcpyDeviceToHost, lat->stream);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(lat->stream);
-        if (e == hipSuccess) {
-            const uint32_t a = minstd_multiplier(lat->t - 1);
-            for (size_t i = 0; i < n; ++i)
-                out[i] = minstd_jump(a, seeds[i]);
+        // MINSTD draws are a function of (site, sweep): evaluate the last sweep's on
+        // the host with the device's own seed and jump functions
+        const uint32_t a = minstd_multiplier(lat->t - 1);
+        const uint32_t LL = (uint32_t)lat->L * (uint32_t)lat->L;
+        for (int z = 0; z < lat->L; ++z) {
+            const uint32_t zk = minstd_plane_key((uint32_t)z, lat->minstd_k);
+            for (uint32_t xy = 0; xy < LL; ++xy)
+                out[(size_t)z * LL + xy] = minstd_jump(a, minstd_seed(xy, zk));
         }
+        e = hipSuccess;
         return check_hip(e, "get randoms");
     }
     if (e == hipSuccess)
@@ -667,7 +663,8 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *m
         for (int r = 0; r < n; ++r) {
             a.src[r] = lats[r]->spins[lats[r]->cur];
             a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
-            a.rnd[r] = l0->prng == SG_MINSTD ? lats[r]->seeds : lats[r]->rbuf;
+            a.rnd[r] = lats[r]->rbuf;
+            a.mk[r] = lats[r]->minstd_k;
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

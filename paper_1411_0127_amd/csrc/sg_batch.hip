@@ -196,7 +196,7 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
         e.J = job.lat->J;
         e.spins[0] = job.lat->spins[0];
         e.spins[1] = job.lat->spins[1];
-        e.seeds = job.lat->seeds;
+        e.mk = job.lat->minstd_k;
         e.c0 = job.lat->cur;
         e.t0 = job.lat->t;
         e.nsweeps = std::min(job.left, R);

@@ -38,10 +38,25 @@ inline uint64_t derive_key(uint64_t seed, uint32_t tag, uint32_t replica)
     return sm_out(sm_out(seed, 1ull + tag), 1ull + replica);
 }
 
-// MINSTD seed of a site from its keyed word: 1 + ((h >> 33) mod (2^31 - 2)).
-__host__ __device__ __forceinline__ uint32_t minstd_seed_from(uint64_t h)
+// MurmurHash3's 32-bit finalizer (A. Appleby): a bijection of 32-bit words.
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
 {
-    uint32_t v = (uint32_t)(h >> 33);              // < 2^31
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// MINSTD seed of site (x, y, z): 1 + ((fmix32((x + L*y) ^ zkey) >> 1) mod (2^31 - 2)),
+// zkey = fmix32(z ^ k), k = low 32 bits of key(spin_seed, TAG_MINSTD, replica).
+// The per-plane part zkey is the same for a whole plane.
+__host__ __device__ __forceinline__ uint32_t minstd_plane_key(uint32_t z, uint32_t k) { return fmix32(z ^ k); }
+
+__host__ __device__ __forceinline__ uint32_t minstd_seed(uint32_t xy, uint32_t zkey)
+{
+    uint32_t v = fmix32(xy ^ zkey) >> 1;           // < 2^31
     v = (v >= 0x7FFFFFFEu) ? v - 0x7FFFFFFEu : v;  // mod 2^31 - 2
     return v + 1u;
 }
@@ -139,13 +154,13 @@ struct sg_lattice {
     uint64_t coupling_seed = 0, spin_seed = 0;
     uint32_t replica = 0;
     uint64_t key_spin = 0, key_minstd = 0, key_mt = 0, key_j = 0;
+    uint32_t minstd_k = 0;  // low 32 bits of key_minstd
     uint8_t *base = nullptr;
     size_t bytes = 0;
     uint64_t *spins[2] = {nullptr, nullptr};
     int cur = 0;  // spins[cur] holds the current configuration
     uint64_t *J = nullptr;
     const sg_lattice *J_owner = nullptr;  // nullptr: this lattice owns J
-    uint32_t *seeds = nullptr;            // MINSTD per-site seeds [V]
     uint32_t *mt_state = nullptr;         // MT19937 state, word k of column c at k*L*L + c
     uint32_t *rbuf = nullptr;             // MT19937 draws of the sweep being done [V]
     uint64_t *scratch = nullptr;          // reduction partials
@@ -163,24 +178,23 @@ int hip_fail(hipError_t e, const char *what);
 
 // Memory carve of one lattice buffer.
 struct Carve {
-    size_t spins0, spins1, J, seeds, mt_state, rbuf, scratch, total;
+    size_t spins0, spins1, J, mt_state, rbuf, scratch, total;
 };
 Carve carve(int L, int prng, bool own_J);
 
 // Kernels (launchers return hipError_t of the launch).
 hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s);
-hipError_t launch_init_minstd(uint32_t *seeds, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s);
 // Draws of sweep t for n (1 or 2) stream sets of side L.
 hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
-hipError_t launch_minstd_draws(const uint32_t *seeds, uint32_t *R, int L, uint32_t a, hipStream_t s);
 
 struct SweepArgs {
     const uint64_t *J;
     uint64_t *src[2];      // per replica: current spins
     uint64_t *dst[2];      // per replica: next spins (fused) -- unused by two-pass
-    const uint32_t *rnd[2];  // per replica: MINSTD seeds or MT19937 draws
+    const uint32_t *rnd[2];  // per replica: MT19937 draws (unused for MINSTD)
+    uint32_t mk[2];          // per replica: MINSTD key (low 32 bits of its keyed word)
     int nrep;
     int L;
     int prng;
@@ -196,7 +210,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
 struct BatchEntry {
     const uint64_t *J;
     uint64_t *spins[2];
-    const uint32_t *seeds;
+    uint32_t mk;     // MINSTD key
     int L, TXp, TY, ZC, ntx, nty, nzc, WE, band;
     int c0;          // current spin buffer when the run starts
     int item0;       // first work item

@@ -23,9 +23,11 @@ Conventions (this project's, stated once here):
   sample j (bit mapping of Sec. 4);
 * initial spin word of site i, replica r: ``out(key(spin_seed, TAG_SPIN, r), 1 + i)``;
   bit j set <=> sigma = +1 for sample j;
-* MINSTD seed of site i, replica r:
-  ``1 + ((out(key(spin_seed, TAG_MINSTD, r), 1 + i) >> 33) mod (2**31 - 2))``,
-  a value in [1, 2**31 - 2], i.e. a valid non-zero MINSTD state;
+* MINSTD seed of site (x, y, z), replica r, with k = low 32 bits of
+  ``key(spin_seed, TAG_MINSTD, r)``:
+  ``1 + ((fmix32((x + L*y) ^ fmix32(z ^ k)) >> 1) mod (2**31 - 2))``, a value in
+  [1, 2**31 - 2], i.e. a valid non-zero MINSTD state; fmix32 is the 32-bit
+  finalizer of MurmurHash3 (A. Appleby), a bijection of 32-bit words;
 * MT19937 seed of column c = x + L*y, replica r:
   ``out(key(spin_seed, TAG_MT, r), 1 + c) & 0xffffffff``.
 """
@@ -43,6 +45,17 @@ TAG_MINSTD = 3
 TAG_MT = 4
 
 MINSTD_MODULUS = 2**31 - 1
+
+
+def fmix32(h) -> np.ndarray:
+    """MurmurHash3 32-bit finalizer (wrapping uint32 arithmetic)."""
+    h = np.asarray(h, dtype=np.uint32)
+    with np.errstate(over="ignore"):
+        h = h ^ (h >> np.uint32(16))
+        h = h * np.uint32(0x85EBCA6B)
+        h = h ^ (h >> np.uint32(13))
+        h = h * np.uint32(0xC2B2AE35)
+        return h ^ (h >> np.uint32(16))
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -97,14 +110,23 @@ def spin_words(L: int, spin_seed: int, replica: int) -> np.ndarray:
     return S
 
 
+def _minstd_seed(L: int, k: int, sites) -> np.ndarray:
+    i = np.asarray(sites, dtype=np.uint64)
+    LL = np.uint64(L * L)
+    xy = (i % LL).astype(np.uint32)
+    z = (i // LL).astype(np.uint32)
+    h = fmix32(xy ^ fmix32(z ^ np.uint32(k))) >> np.uint32(1)
+    h = np.where(h >= np.uint32(MINSTD_MODULUS - 1), h - np.uint32(MINSTD_MODULUS - 1), h)
+    return (h + np.uint32(1)).astype(np.uint32)
+
+
 def minstd_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
     """uint32 array of per-site MINSTD seeds in [1, 2^31 - 2]."""
     V = L**3
-    k = key(spin_seed, TAG_MINSTD, replica)
+    k = key(spin_seed, TAG_MINSTD, replica) & 0xFFFFFFFF
     s = np.empty(V, dtype=np.uint32)
     for a, b in _chunks(V):
-        h = out(k, np.arange(a + 1, b + 1, dtype=np.uint64)) >> np.uint64(33)
-        s[a:b] = (np.uint64(1) + h % np.uint64(MINSTD_MODULUS - 1)).astype(np.uint32)
+        s[a:b] = _minstd_seed(L, k, np.arange(a, b, dtype=np.uint64))
     return s
 
 
@@ -129,9 +151,7 @@ def spin_words_at(L: int, spin_seed: int, replica: int, sites: np.ndarray) -> np
 
 
 def minstd_seeds_at(L: int, spin_seed: int, replica: int, sites: np.ndarray) -> np.ndarray:
-    k = key(spin_seed, TAG_MINSTD, replica)
-    h = out(k, np.asarray(sites, dtype=np.uint64) + np.uint64(1)) >> np.uint64(33)
-    return (np.uint64(1) + h % np.uint64(MINSTD_MODULUS - 1)).astype(np.uint32)
+    return _minstd_seed(L, key(spin_seed, TAG_MINSTD, replica) & 0xFFFFFFFF, sites)
 
 
 def mt_seeds_at(L: int, spin_seed: int, replica: int, columns: np.ndarray) -> np.ndarray:
