@@ -98,7 +98,11 @@ def run_gpu(args, wl):
         base = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
         lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
         shape = None
-        if args.kernel == "auto":
+        if args.tile:
+            shape = tuple(int(v) for v in args.tile.split(","))
+            for l in lats:
+                l.set_kernel("fused", *shape)
+        elif args.kernel == "auto":
             # pick the fused tile on these lattices, before the timed region
             shape, _ = sg.autotune(lats[:2], reps=5)
             for l in lats[2:]:
@@ -253,6 +257,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "twopass"])
+    ap.add_argument("--tile", default="", help="fused tile tile_x,tile_y,z_chunk,band (skips the autotuner)")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")

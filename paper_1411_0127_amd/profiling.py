@@ -42,10 +42,9 @@ def stats(csv_path: str, out_md: str, command: str) -> str:
         "|---|---|---|---|---|---|",
     ]
     for r in rows:
-        name = r.get("Name") or r.get("KernelName") or ""
-        short = name.split("(")[0].replace("sg::(anonymous namespace)::", "sg::")
-        if "<" in name and "k_fused" in name:
-            short = name[: name.index(">") + 1].replace("void ", "").replace("sg::(anonymous namespace)::", "sg::")
+        name = (r.get("Name") or r.get("KernelName") or "").replace("(anonymous namespace)::", "")
+        short = name.replace("void ", "")
+        short = short[: short.index(">") + 1] if "<" in short.split("(")[0] else short.split("(")[0]
         calls = int(float(r.get("Calls", 0)))
         avg = float(r.get("AverageNs", 0)) / 1e3
         mn = float(r.get("MinNs", 0)) / 1e3
