@@ -182,8 +182,7 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t nxm = H ? other : nbx;
             const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, zk[r]))
                                                    : (H ? B.rhi[r] : B.rlo[r]);
-            rn[r] = s ^ flip_mask(s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r), jxp, jyp, jzp, jxm, jym, jzm, R,
-                                  p.T);
+            rn[r] = flip_site(s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r), jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
         }
     }
 
@@ -205,8 +204,7 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t nxm = H ? cy.rn1[r] : nbx;
             const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, cy.zk1[r]))
                                                    : (H ? A.rhi[r] : A.rlo[r]);
-            const uint64_t bn =
-                s ^ flip_mask(s, nxp, nyp, rn[r], nxm, nym, cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+            const uint64_t bn = flip_site(s, nxp, nyp, rn[r], nxm, nym, cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
             wlo[r] = H ? cy.rn1[r] : bn;
             whi[r] = H ? bn : cy.rn1[r];
         }

@@ -37,9 +37,8 @@ __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, co
         const uint32_t R = (PRNG == SG_MINSTD)
                                ? minstd_jump(a, minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk)))
                                : rnd[i];
-        const uint64_t m = flip_mask(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i],
-                                     J[2 * V + i], J[ixm], J[V + iym], J[2 * V + izm], R, T);
-        S[i] = s ^ m;
+        S[i] = flip_site(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i], J[ixm],
+                         J[V + iym], J[2 * V + izm], R, T);
     }
 }
 

@@ -80,47 +80,60 @@ __host__ __device__ __forceinline__ uint32_t minstd_jump(uint32_t a, uint32_t s)
 // full adders into a 3-bit count v = 0..6 per sample, dE = 4v - 12, and the flip
 // mask keeps every sample with v <= 3, those with v = 4 if R < T4, v = 5 if
 // R < T8 and v = 6 if R < T12.  One R per word (asynchronous multispin coding).
-// flip_mask returns the mask; the new spin word is s ^ mask.
 // ---------------------------------------------------------------------------
 struct Thresholds {
     uint64_t t4, t8, t12;
 };
 
-// v_bfi_b32: bits of a where m is 1, bits of b where m is 0.
-__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t a, uint32_t b)
+// v_bitop3_b32 (gfx950): any bitwise function of three words in one instruction.
+// Its 8-bit table is the function evaluated on the bit patterns 0xF0, 0xCC, 0xAA
+// standing for the first, second and third operand.
+namespace bop {
+constexpr uint32_t A = 0xF0, B = 0xCC, C = 0xAA;
+constexpr int table(uint32_t v) { return (int)(v & 0xFFu); }
+constexpr int kXor3 = table(A ^ B ^ C);                          // a ^ b ^ c
+constexpr int kMaj = table((A & B) | (A & C) | (B & C));         // majority
+constexpr int kBothEq = table(~(A ^ C) & ~(B ^ C));              // bitwise a == c and b == c
+constexpr int kOrAnd = table(A | (B & C));                       // a | (b & c)
+constexpr int kSel = table((A & B) | (~A & C));                  // a ? b : c
+constexpr int kXorOrNot = table(A ^ (~B | C));                   // a ^ (b ? c : 1)
+}  // namespace bop
+
+template <int T>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c)
 {
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
-    return r;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, T);
 }
 
-// 32 samples of the update.  x[k] = J_k ^ n_k; the bond bit is b_k = x[k] ^ ~s.
-// The complement of s is carried through the adder instead of being applied to
-// all six inputs: a three-input sum of (x ^ c) is sum(x) ^ c, a majority of
-// (x ^ c) is maj(x) ^ c, and c cancels in the XOR of two such terms.
-// a4, a8, a12 are all-ones when R < T4, T8, T12.
+// 32 samples of the update; returns the new spin word.  x[k] = J_k ^ n_k, and the
+// bond bit is b_k = x[k] ^ ~s.  The complement of s is carried through the adder
+// instead of being applied to all six inputs: a three-input sum of (x ^ c) is
+// sum(x) ^ c, a majority of (x ^ c) is maj(x) ^ c, and c cancels in the XOR of two
+// such terms.  v = b0 + ... + b5 = (B1 + B2) + 2 (K1 + K2) with B, K the sums and
+// carries of the two triples.  a4, a8, a12 are all-ones when R < T4, T8, T12; since
+// T12 <= T8 <= T4 they are nested, and the accepted set is
+// v <= 3, or v = 4 with a4, v = 5 with a8, v = 6 with a12.
 __device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                               uint32_t x4, uint32_t x5, uint32_t a4, uint32_t a8, uint32_t a12)
 {
-    const uint32_t ns = ~s;
-    const uint32_t t1 = x0 ^ x1, t2 = x3 ^ x4;
-    const uint32_t s1 = t1 ^ x2, s2 = t2 ^ x5;   // sums of x: sums of b are s1^ns, s2^ns
-    const uint32_t k1 = bfi(t1, x2, x0);         // majority of x0, x1, x2
-    const uint32_t k2 = bfi(t2, x5, x3);
-    const uint32_t c0 = s1 ^ s2;                 // bit 0 of v
-    const uint32_t k3 = bfi(c0, 0u, s1 ^ ns);    // carry of (s1^ns) + (s2^ns)
-    const uint32_t t3 = k1 ^ k2;
-    const uint32_t c1 = t3 ^ k3;                 // bit 1 of v
-    const uint32_t c2 = bfi(t3, k3, k1 ^ ns);    // bit 2 of v
-    // flip if v <= 3, or v = 4 and R < T4, v = 5 and R < T8, v = 6 and R < T12
-    const uint32_t mid = bfi(c0, a8, a4);        // v in {4, 5}
-    const uint32_t hi = bfi(c1, 0u, mid) | a12;  // v >= 4 and accepted
-    return bfi(c2, hi, ~0u);
+    const uint32_t s1 = bop3<bop::kXor3>(x0, x1, x2);    // B1 = s1 ^ ~s
+    const uint32_t k1 = bop3<bop::kMaj>(x0, x1, x2);     // K1 = k1 ^ ~s
+    const uint32_t s2 = bop3<bop::kXor3>(x3, x4, x5);
+    const uint32_t k2 = bop3<bop::kMaj>(x3, x4, x5);
+    const uint32_t c0 = s1 ^ s2;                         // bit 0 of v
+    const uint32_t k3 = bop3<bop::kBothEq>(s1, s2, s);   // carry of B1 + B2: B1 & B2, B = (s1 == s)
+    const uint32_t t = k1 ^ k2;                          // K1 ^ K2
+    const uint32_t c1 = t ^ k3;                          // bit 1 of v
+    const uint32_t kk = bop3<bop::kBothEq>(k1, k2, s);   // K1 & K2, K = (k == s)
+    const uint32_t c2 = bop3<bop::kOrAnd>(kk, k3, t);    // bit 2 of v: majority of K1, K2, k3
+    const uint32_t mid = bop3<bop::kSel>(c0, a8, a4);    // v = 4 or 5: accepted
+    const uint32_t hi = bop3<bop::kSel>(c1, a12, mid);   // v >= 4: accepted (a12 lies in mid)
+    return bop3<bop::kXorOrNot>(s, c2, hi);              // s ^ (v <= 3 or accepted)
 }
 
-// Flip mask of a 64-sample word: s the spin word, n0..n5 the neighbour words and
-// j0..j5 the coupling words of the same six bonds, one R for the word.
-__device__ __forceinline__ uint64_t flip_mask(uint64_t s, uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
+// New spin word of a 64-sample site: s the spin word, n0..n5 the neighbour words
+// and j0..j5 the coupling words of the same six bonds, one R for the word.
+__device__ __forceinline__ uint64_t flip_site(uint64_t s, uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
                                               uint64_t n4, uint64_t n5, uint64_t j0, uint64_t j1, uint64_t j2,
                                               uint64_t j3, uint64_t j4, uint64_t j5, uint32_t R,
                                               const Thresholds &T)
