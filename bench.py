@@ -58,7 +58,8 @@ def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
     word read and written (16 B); with MT19937 also the draw read from the
     buffer the fill kernel wrote (4 B).  MINSTD draws are computed from the site
     and the sweep, nothing is read for them.  The MT19937 fill kernel's own state
-    traffic is not part of the sweep kernel.
+    traffic is not part of the sweep kernel.  A two-sweep launch must move the
+    same bytes: it reads and writes every word once for both sweeps.
     """
     return 24 + replicas * (16 + (4 if prng == "mt19937" else 0))
 
@@ -99,17 +100,24 @@ def run_gpu(args, wl):
         lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
         shape = None
         if args.tile:
-            shape = tuple(int(v) for v in args.tile.split(","))
+            parts = args.tile.split(",")
+            kind = parts[0] if not parts[0].isdigit() else "fused"
+            nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
+            if kind == "fused2" and prng != "minstd":
+                kind = "fused"  # the two-sweep kernel takes MINSTD lattices only
+            shape = (kind,) + nums
             for l in lats:
-                l.set_kernel("fused", *shape)
+                l.set_kernel(kind, *nums)
         elif args.kernel == "auto":
-            # pick the fused tile on these lattices, before the timed region
+            # pick the fused kernel and tile on these lattices, before the timed region
             shape, _ = sg.autotune(lats[:2], reps=5)
             for l in lats[2:]:
-                l.set_kernel("fused", *shape)
+                l.set_kernel(shape[0], *shape[1:])
         else:
             for l in lats:
                 l.set_kernel(args.kernel)
+        kind = shape[0] if shape else args.kernel
+        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng == "minstd")) and nsw % 2 == 0 else 1
 
         def step(ev=None):
             if ev is not None:
@@ -140,7 +148,9 @@ def run_gpu(args, wl):
             wall_s=wall,
             ms_per_step=wall * 1e3 / args.steps,
             sweep_ms_per_step=sweep_ms,
-            launch_ms=sum(sweep_ms) / (args.steps * nsw),
+            launch_ms=sum(sweep_ms) / (args.steps * nsw / per_launch),
+            sweeps_per_launch=per_launch,
+            kind=kind,
             energy_per_spin=[float(x) for x in last[0][1][:4]],
             tile=shape,
         )
@@ -256,8 +266,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "twopass"])
-    ap.add_argument("--tile", default="", help="fused tile tile_x,tile_y,z_chunk,band (skips the autotuner)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
+    ap.add_argument("--tile", default="",
+                    help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band (skips the autotuner)")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
@@ -353,8 +364,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "sg::k_fused (one launch per sweep, all replicas)",
+            "kernel": ("sg::k_fused2 (two sweeps per launch, replicas interleaved)"
+                       if main_res["sweeps_per_launch"] == 2 else "sg::k_fused (one launch per sweep, all replicas)"),
             "bytes_per_site": bps,
+            "sweeps_per_launch": main_res["sweeps_per_launch"],
             "launch_ms": round(main_res["launch_ms"], 5),
         },
     }

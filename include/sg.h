@@ -79,8 +79,14 @@ enum {
  * SG_KERNEL_FUSED:   one launch per sweep; each workgroup marches a tile of x-y
  *                    columns along z, red plane k then blue plane k-1, in-plane
  *                    neighbours exchanged through LDS, old/new spins in two
- *                    buffers and tile-edge red sites recomputed by both tiles. */
-enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2 };
+ *                    buffers and tile-edge red sites recomputed by both tiles.
+ * SG_KERNEL_FUSED2:  two sweeps per launch (SG_MINSTD only): the same march
+ *                    carries sweep t+1 two planes behind sweep t, so spins and
+ *                    couplings cross HBM once per two sweeps; an odd last sweep
+ *                    of a call runs on SG_KERNEL_FUSED.
+ * SG_KERNEL_AUTO picks SG_KERNEL_FUSED2 for SG_MINSTD lattices and
+ * SG_KERNEL_FUSED otherwise, with default tiles (sg_autotune picks by timing). */
+enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2, SG_KERNEL_FUSED2 = 3 };
 
 /* Bytes of device memory a lattice needs.  own_couplings = 1 for a lattice that
  * holds its couplings (sg_lattice_create), 0 for a replica that reads another
@@ -143,23 +149,25 @@ int sg_thresholds(double beta, int prng, uint64_t T[3]);
 int64_t sg_sweep_count(const sg_lattice *lat);
 int sg_set_sweep_count(sg_lattice *lat, int64_t t);
 
-/* Choose the sweep kernel and, for SG_KERNEL_FUSED, its tile: tile_x pairs of
+/* Choose the sweep kernel and, for SG_KERNEL_FUSED(2), its tile: tile_x pairs of
  * sites per row (x extent 2*tile_x), tile_y rows, z_chunk planes per workgroup,
  * band = tile rows per group of the tile order (the workgroups running together
  * cover a block about band tiles tall); 0 = default for any of the four.  Invalid
  * shapes return SG_EINVAL and change nothing. */
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
-/* Autotune the fused kernel for n (1 or 2) lattices swept together (n = 2:
- * replicas sharing couplings, as in sg_sweep_replicas).  Candidate tiles are
- * timed with `reps` launches each on the lattices' own data without changing
- * their state (the launches read the current spins and write only the spare
- * buffer; sweep count and streams do not move).  The fastest shape is set on
- * every lattice (as sg_set_kernel(SG_KERNEL_FUSED, ...)) and remembered for this
- * device, L, n and prng; a later call with the same key reuses it without
- * timing unless reps < 0 forces a new search.  best[4] (may be NULL) receives
- * tile_x, tile_y, z_chunk, band; ms (may be NULL) the best time per launch. */
-int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *ms);
+/* Autotune the fused kernels for n (1 or 2) lattices swept together (n = 2:
+ * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
+ * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 for SG_MINSTD) and tiles are timed with
+ * `reps` launches each on the lattices' own data without changing their state
+ * (the launches read the current spins and write only the spare buffer; sweep
+ * count and streams do not move), and compared by time per sweep.  The fastest
+ * is set on every lattice (as sg_set_kernel) and remembered for this device, L,
+ * n and prng; a later call with the same key reuses it without timing unless
+ * reps < 0 forces a new search.  best[5] (may be NULL) receives kind, tile_x,
+ * tile_y, z_chunk, band; ms (may be NULL) the best time per sweep, or -1 when the
+ * choice came from the cache. */
+int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *ms);
 
 /* ---- Batches: many lattices advanced together --------------------------------
  * A batch holds lattices of any sizes (one replica each, SG_MINSTD, all on the

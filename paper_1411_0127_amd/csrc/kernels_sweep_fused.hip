@@ -47,6 +47,8 @@ struct FusedParams {
     int WE;              // waves holding the even tile rows
     int band;            // tile rows per group of the tile order
     uint32_t a;          // MINSTD multiplier of this sweep
+    uint32_t a2;         // two sweeps per launch: multiplier of the second sweep
+    int nrep;            // two sweeps per launch: replicas, one per workgroup (interleaved items)
     uint32_t mk[2];      // MINSTD key per replica
     Thresholds T;
 };
@@ -457,6 +459,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
     p.WE = e.WE;
     p.band = e.band;
     p.a = minstd_power(e.t0 + r);
+    p.a2 = 0;
+    p.nrep = 1;
     p.T = Thresholds{e.t4, e.t8, e.t12};
     fused_march<SG_MINSTD, 1>(p, item - e.item0, lds, std::make_integer_sequence<int, Ring<1>::value>{});
 }
@@ -471,6 +475,271 @@ __global__ void k_round_reset(int64_t *round_ctr)
 {
     if (threadIdx.x == 0)
         round_ctr[threadIdx.x] = 0;
+}
+
+// ===========================================================================
+// Two sweeps per launch (MINSTD).
+//
+// The same z-march carries a second sweep two planes behind the first.  At step k
+// a lane does, on its pair half H = (y + k) & 1:
+//   first sweep:  red of plane k, blue of plane k-1        (as above)
+//   second sweep: red of plane k-2, blue of plane k-3
+// The second sweep's red at k-2 needs the first sweep's blue at k-3 .. k-1, done
+// by then (blue k-1 a moment earlier in the same step); its blue at k-3 needs its
+// own red at k-4 .. k-2.  Every site therefore sees exactly the neighbours of two
+// consecutive sweeps, and only the second sweep's words are stored: spins and
+// couplings cross HBM once per two sweeps.  The second sweep updates the same
+// sites as the first did two steps earlier, so the coupling operands and the
+// stream seed of those updates are kept for two steps instead of reloaded.
+//
+// The ring around the tile doubles: the second sweep's blue on the tile needs its
+// red one step out, which needs the first sweep's blue two out, its red three out
+// and the old spins four out.  Lanes cover the tile plus two pairs each side in x
+// and four rows each side in y; a z chunk recomputes three planes below and above.
+// ===========================================================================
+constexpr int kF2OldBlue = 0, kF2Red = 1, kF2Jx = 2, kF2JyLo = 3, kF2JyHi = 4, kF2Blue = 5, kF2Red2 = 6;
+constexpr int kF2Words = 7;  // LDS words per lane and buffer set
+
+// Coupling operands and stream seed of one site update.
+struct SiteOps {
+    uint64_t jxp, jyp, jzp, jxm, jym, jzm;
+    uint32_t seed;
+};
+
+struct Carry2 {
+    uint64_t jzm2lo, jzm2hi;     // jz of plane k-2
+    uint64_t jxl, jyulo, jyuhi;  // neighbour couplings of plane k-1
+    uint64_t ar1, ar2;           // first sweep: new red of planes k-1, k-2
+    uint64_t ab1, ab2;           // first sweep: new blue of planes k-2, k-3
+    uint64_t br1, br2;           // second sweep: new red of planes k-3, k-4
+    SiteOps r1, b1, r2, b2;      // first sweep's red / blue operands of steps k-1, k-2
+};
+
+template <int H>
+__device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_ab,
+                                            bool do_br, bool do_bb, bool do_pub, const Plane<1> &A,
+                                            const Plane<1> &B, const Plane<1> &C, const Carry2 &cy, uint32_t zk,
+                                            uint32_t zk1, uint64_t &ar0, uint64_t &ab0, uint64_t &br0,
+                                            uint64_t &bb0, SiteOps &r0, SiteOps &b0, uint64_t &jxl,
+                                            uint64_t &jyulo, uint64_t &jyuhi)
+{
+    const uint64_t *S = lds + ((k + 2) & 1) * c.set_words;
+    const int ixn = H ? c.ixp : c.ixm;  // lane holding the x-neighbour outside the pair
+    const int nl = c.nl;
+    jxl = S[kF2Jx * nl + c.ixm];
+    jyulo = S[kF2JyLo * nl + c.iym];
+    jyuhi = S[kF2JyHi * nl + c.iym];
+
+    // ---- first sweep, red of plane k -----------------------------------------
+    r0.jxp = H ? B.jxhi : B.jxlo;
+    r0.jxm = H ? B.jxlo : jxl;
+    r0.jyp = H ? B.jyhi : B.jylo;
+    r0.jym = H ? jyuhi : jyulo;
+    r0.jzp = H ? B.jzhi : B.jzlo;
+    r0.jzm = H ? A.jzhi : A.jzlo;
+    r0.seed = minstd_seed(c.col + H, zk);
+    {
+        const uint64_t nbx = S[kF2OldBlue * nl + ixn];
+        const uint64_t nym = S[kF2OldBlue * nl + c.iym];
+        const uint64_t nyp = S[kF2OldBlue * nl + c.iyp];
+        const uint64_t s = sp<H>(B, 0), other = sp<1 - H>(B, 0);
+        ar0 = flip_site(s, H ? nbx : other, nyp, sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp,
+                        r0.jzp, r0.jxm, r0.jym, r0.jzm, minstd_jump(p.a, r0.seed), p.T);
+    }
+
+    // ---- first sweep, blue of plane k-1: neighbours are new red ----------------
+    b0.jxp = H ? A.jxhi : A.jxlo;
+    b0.jxm = H ? A.jxlo : cy.jxl;
+    b0.jyp = H ? A.jyhi : A.jylo;
+    b0.jym = H ? cy.jyuhi : cy.jyulo;
+    b0.jzp = H ? A.jzhi : A.jzlo;
+    b0.jzm = H ? cy.jzm2hi : cy.jzm2lo;
+    b0.seed = minstd_seed(c.col + H, zk1);
+    if (do_ab) {
+        const uint64_t nbx = S[kF2Red * nl + ixn];
+        const uint64_t nym = S[kF2Red * nl + c.iym];
+        const uint64_t nyp = S[kF2Red * nl + c.iyp];
+        ab0 = flip_site(sp<H>(A, 0), H ? nbx : cy.ar1, nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp,
+                        b0.jzp, b0.jxm, b0.jym, b0.jzm, minstd_jump(p.a, b0.seed), p.T);
+    }
+
+    // ---- second sweep, red of plane k-2: neighbours are the first sweep's blue --
+    if (do_br) {
+        const uint64_t nbx = S[kF2Blue * nl + ixn];
+        const uint64_t nym = S[kF2Blue * nl + c.iym];
+        const uint64_t nyp = S[kF2Blue * nl + c.iyp];
+        const SiteOps &o = cy.r2;
+        br0 = flip_site(cy.ar2, H ? nbx : cy.ab1, nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp,
+                        o.jxm, o.jym, o.jzm, minstd_jump(p.a2, o.seed), p.T);
+    }
+
+    // ---- second sweep, blue of plane k-3: neighbours are its own new red --------
+    if (do_bb) {
+        const uint64_t nbx = S[kF2Red2 * nl + ixn];
+        const uint64_t nym = S[kF2Red2 * nl + c.iym];
+        const uint64_t nyp = S[kF2Red2 * nl + c.iyp];
+        const SiteOps &o = cy.b2;
+        bb0 = flip_site(cy.ab2, H ? nbx : cy.br1, nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp,
+                        o.jxm, o.jym, o.jzm, minstd_jump(p.a2, o.seed), p.T);
+    }
+
+    // ---- publish for step k+1 ----------------------------------------------------
+    if (do_pub) {
+        uint64_t *W = lds + ((k + 3) & 1) * c.set_words;
+        W[kF2OldBlue * nl + c.me] = sp<H>(C, 0);
+        W[kF2Red * nl + c.me] = ar0;
+        W[kF2Jx * nl + c.me] = C.jxhi;
+        W[kF2JyLo * nl + c.me] = C.jylo;
+        W[kF2JyHi * nl + c.me] = C.jyhi;
+        W[kF2Blue * nl + c.me] = ab0;
+        W[kF2Red2 * nl + c.me] = br0;
+    }
+}
+
+// Planes in flight for the two-sweep march.
+constexpr int kRing2 = 4;
+
+template <int... Is>
+__device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
+                                             std::integer_sequence<int, Is...>)
+{
+    constexpr int NS = sizeof...(Is);
+    // replicas are interleaved: consecutive items are the same tile of each replica
+    const int rep = item % pp.nrep;
+    const int tile = item / pp.nrep;
+    FusedParams p = pp;
+    p.src[0] = pp.src[rep];
+    p.dst[0] = pp.dst[rep];
+    p.mk[0] = pp.mk[rep];
+
+    Lane c;
+    c.nl = p.EX * p.EY + 1;
+    c.set_words = c.nl * kF2Words;
+
+    const int per_chunk = p.ntx * p.nty;
+    const int zc = tile / per_chunk;
+    const int r0 = tile - zc * per_chunk;
+    const int g = r0 / (p.ntx * p.band);
+    const int gh = min(p.band, p.nty - g * p.band);
+    const int q0 = r0 - g * p.ntx * p.band;
+    const int tx = q0 / gh;
+    const int ty = g * p.band + (q0 - tx * gh);
+    const int TXe = min(p.TXp, p.P - tx * p.TXp);
+    const int TYe = min(p.TY, p.L - ty * p.TY);
+    const int z0 = zc * p.ZC;
+    const int ZCe = min(p.ZC, p.L - z0);
+
+    const int lid = threadIdx.x;
+    const int cls = lid < 64 * p.WE ? 0 : 1;
+    const int idx = cls ? lid - 64 * p.WE : lid;
+    const int rows_cls = cls ? p.EY / 2 : (p.EY + 1) / 2;
+    c.lane = idx < p.EX * rows_cls;
+    const int ex = c.lane ? idx % p.EX : 0;
+    const int ey = c.lane ? 2 * (idx / p.EX) + cls : cls;
+    const bool full = c.lane && ey >= 1 && ey <= TYe + 6;  // rows whose red sites are computed
+    const bool inter = c.lane && ex >= 2 && ex <= TXe + 1 && ey >= 4 && ey <= TYe + 3;
+    const int m = (tx * p.TXp + ex - 2 + 2 * p.P) % p.P;
+    const int y = (ty * p.TY + ey - 4 + 4 * p.L) % p.L;
+    c.me = c.lane ? ey * p.EX + ex : c.nl - 1;
+    c.ixm = ey * p.EX + max(ex - 1, 0);
+    c.ixp = ey * p.EX + min(ex + 1, p.EX - 1);
+    c.iym = max(ey - 1, 0) * p.EX + ex;
+    c.iyp = min(ey + 1, p.EY - 1) * p.EX + ex;
+    const int ypar = __builtin_amdgcn_readfirstlane((ty * p.TY + ey) & 1);
+
+    const int L = p.L;
+    const int64_t LL = (int64_t)L * L;
+    const uint32_t col = (uint32_t)y * (uint32_t)L + 2u * (uint32_t)m;
+    c.col = col;
+    Offsets o;
+    o.s = c.lane ? col * 8u : kOOB;
+    o.f = full ? col * 8u : kOOB;
+    o.r = kOOB;
+    const uint32_t o_st = inter ? col * 8u : kOOB;
+    Offsets o_none;
+    o_none.s = o_none.f = o_none.r = kOOB;
+    auto wrap = [&](int q) -> int {  // q lies in [-6, L+6), inside [-L, 2L) as L >= 8
+        return q < 0 ? q + L : (q >= L ? q - L : q);
+    };
+
+    // first sweep's red runs over planes z0-3 .. z0+ZCe+2, reading old planes one beyond
+    const int kfirst = z0 - 3;
+    const int klast = z0 + ZCe + 2;
+    Plane<1> ring[NS];
+    ((load_plane<SG_MINSTD, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
+
+    Carry2 cy;
+    cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
+    cy.ar1 = cy.ar2 = cy.ab1 = cy.ab2 = cy.br1 = cy.br2 = 0;
+    cy.r1 = cy.b1 = cy.r2 = cy.b2 = SiteOps{0, 0, 0, 0, 0, 0, 0};
+
+    {
+        uint64_t *S = lds + ((kfirst + 2) & 1) * c.set_words;
+        const bool hred = ((ypar + kfirst + L) & 1) != 0;
+        S[kF2OldBlue * c.nl + c.me] = hred ? ring[1].slo[0] : ring[1].shi[0];
+        S[kF2Jx * c.nl + c.me] = ring[1].jxhi;
+        S[kF2JyLo * c.nl + c.me] = ring[1].jylo;
+        S[kF2JyHi * c.nl + c.me] = ring[1].jyhi;
+    }
+    __syncthreads();
+
+    int k = kfirst;
+#define SG_FUSED2_STEP(A, B, C)                                                                                  \
+    {                                                                                                             \
+        uint64_t ar0 = 0, ab0 = 0, br0 = 0, bb0 = 0, jxl, jyulo, jyuhi;                                          \
+        SiteOps r0, b0;                                                                                           \
+        const bool do_ab = k >= z0 - 1;                                                                           \
+        const bool do_br = k >= z0 + 1;                                                                           \
+        const bool do_bb = k >= z0 + 3;                                                                           \
+        const bool do_pub = k < klast;                                                                            \
+        const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);                                        \
+        const uint32_t zk1 = minstd_plane_key((uint32_t)wrap(k - 1), p.mk[0]);                                   \
+        if ((ypar + k + L) & 1)                                                                                   \
+            fused2_step<1>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0,  \
+                           r0, b0, jxl, jyulo, jyuhi);                                                            \
+        else                                                                                                      \
+            fused2_step<0>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0,  \
+                           r0, b0, jxl, jyulo, jyuhi);                                                            \
+        {                                                                                                         \
+            const bool h = ((ypar + k + L) & 1) != 0;                                                             \
+            const uint64_t wlo = h ? cy.br1 : bb0, whi = h ? bb0 : cy.br1;                                        \
+            const int64_t qo = (int64_t)wrap(k - 3) * LL * 8;                                                     \
+            st_pair(plane_rsrc(p.dst[0], qo, (uint32_t)(LL * 8)), do_bb ? o_st : kOOB, wlo, whi);                 \
+        }                                                                                                         \
+        if (do_pub)                                                                                               \
+            __syncthreads();                                                                                      \
+        cy.jzm2lo = A.jzlo;                                                                                       \
+        cy.jzm2hi = A.jzhi;                                                                                       \
+        cy.jxl = jxl;                                                                                             \
+        cy.jyulo = jyulo;                                                                                         \
+        cy.jyuhi = jyuhi;                                                                                         \
+        cy.ar2 = cy.ar1;                                                                                          \
+        cy.ar1 = ar0;                                                                                             \
+        cy.ab2 = cy.ab1;                                                                                          \
+        cy.ab1 = ab0;                                                                                             \
+        cy.br2 = cy.br1;                                                                                          \
+        cy.br1 = br0;                                                                                             \
+        cy.r2 = cy.r1;                                                                                            \
+        cy.r1 = r0;                                                                                               \
+        cy.b2 = cy.b1;                                                                                            \
+        cy.b1 = b0;                                                                                               \
+        load_plane<SG_MINSTD, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);                \
+    }
+
+    auto step = [&](auto I) -> bool {
+        constexpr int i = decltype(I)::value;
+        SG_FUSED2_STEP(ring[i], ring[(i + 1) % NS], ring[(i + 2) % NS])
+        return ++k <= klast;
+    };
+    while ((step(IC<Is>{}) && ...)) {
+    }
+#undef SG_FUSED2_STEP
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
+{
+    extern __shared__ uint64_t lds[];
+    fused2_march(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2>{});
 }
 
 }  // namespace
@@ -552,10 +821,11 @@ void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk
         }
 }
 
-// z chunk length for a grid of `tiles` tiles: each workgroup marches ZC + 2
-// steps, workgroups run in rounds of `slots`; take the chunk count with the
-// shortest rounds * (ZC + 4) (four extra planes are loaded per chunk).
-static int choose_z_chunk(int L, int64_t tiles, int64_t slots)
+// z chunk length for a grid of `tiles` work items per chunk: workgroups run in
+// rounds of `slots`; take the chunk count with the shortest rounds * (ZC + extra)
+// (`extra` planes are loaded per chunk beyond its own: 4 for one sweep per launch,
+// 8 for two).
+static int choose_z_chunk(int L, int64_t tiles, int64_t slots, int extra)
 {
     int best_zc = L;
     double best = 1e300;
@@ -563,7 +833,7 @@ static int choose_z_chunk(int L, int64_t tiles, int64_t slots)
         const int zc = (L + nzc - 1) / nzc;
         const int64_t n = (L + zc - 1) / zc;
         const int64_t rounds = (tiles * n + slots - 1) / slots;
-        const double cost = (double)rounds * (zc + 4);
+        const double cost = (double)rounds * (zc + extra);
         if (cost < best - 1e-9) {
             best = cost;
             best_zc = zc;
@@ -630,7 +900,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
             per_cu = 1;
         const int P = a.L / 2;
         const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((a.L + tile_y - 1) / tile_y);
-        z_chunk = choose_z_chunk(a.L, tiles, (int64_t)cus * per_cu);
+        z_chunk = choose_z_chunk(a.L, tiles, (int64_t)cus * per_cu, 4);
     }
     FusedParams p;
     p.J = a.J;
@@ -651,6 +921,8 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.nty = (p.L + tile_y - 1) / tile_y;
     p.nzc = (p.L + z_chunk - 1) / z_chunk;
     p.a = a.minstd_a;
+    p.a2 = a.minstd_a2;
+    p.nrep = a.nrep;
     p.T = a.T;
     p.WE = fused_waves_even(tile_x, tile_y);
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
@@ -673,6 +945,107 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
         else
             hipLaunchKernelGGL((k_fused<SG_MT19937, 2>), grid, block, lds, s, p);
     }
+    return hipGetLastError();
+}
+
+
+// ---- two sweeps per launch ---------------------------------------------------
+static size_t fused2_lds_bytes(int tile_x, int tile_y)
+{
+    return (size_t)2 * ((tile_x + 4) * (tile_y + 8) + 1) * kF2Words * sizeof(uint64_t);
+}
+static int fused2_waves_even(int tile_x, int tile_y) { return ((tile_x + 4) * ((tile_y + 9) / 2) + 63) / 64; }
+static int fused2_threads(int tile_x, int tile_y)
+{
+    return 64 * (fused2_waves_even(tile_x, tile_y) + ((tile_x + 4) * ((tile_y + 8) / 2) + 63) / 64);
+}
+
+bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk)
+{
+    // the march touches planes z0-6 .. z0+ZC+5, which the one-step wrap maps
+    // into [0, L) only for L >= 6
+    if (L < 8 || (L & 1))
+        return false;
+    const int P = L / 2;
+    if (tile_x < 1 || tile_x > P || tile_y < 1 || tile_y > L || z_chunk < 0 || z_chunk > L)
+        return false;
+    return fused2_threads(tile_x, tile_y) <= kMaxThreads && fused2_lds_bytes(tile_x, tile_y) <= (size_t)max_lds_bytes();
+}
+
+void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk)
+{
+    const int P = L / 2;
+    z_chunk = 0;
+    const int pref[][2] = {{16, 16}, {16, 12}, {8, 24}, {8, 16}};
+    for (const auto &c : pref)
+        if (P % c[0] == 0 && L >= c[1] && fused2_shape_ok(L, c[0], c[1], 0)) {
+            tile_x = c[0];
+            tile_y = c[1];
+            return;
+        }
+    double best = 1e30;
+    tile_x = 1;
+    tile_y = 1;
+    for (int tx = 1; tx <= P && tx <= 124; ++tx)
+        for (int ty = 1; ty <= L && ty <= 248; ++ty) {
+            if (!fused2_shape_ok(L, tx, ty, 0))
+                continue;
+            const int64_t ntx = (P + tx - 1) / tx, nty = (L + ty - 1) / ty;
+            const double cost = (double)(ntx * nty * fused2_threads(tx, ty)) / ((double)P * L);
+            if (cost < best - 1e-9) {
+                best = cost;
+                tile_x = tx;
+                tile_y = ty;
+            }
+        }
+}
+
+hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)
+{
+    if (a.prng != SG_MINSTD || a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
+        return hipErrorInvalidConfiguration;
+    const int threads = fused2_threads(tile_x, tile_y);
+    const size_t lds = fused2_lds_bytes(tile_x, tile_y);
+    const int P = a.L / 2;
+    const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((a.L + tile_y - 1) / tile_y);
+    if (z_chunk == 0) {
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fused2, threads, lds) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        z_chunk = choose_z_chunk(a.L, tiles * a.nrep, (int64_t)cus * per_cu, 8);
+    }
+    FusedParams p;
+    p.J = a.J;
+    for (int r = 0; r < 2; ++r) {
+        p.src[r] = a.src[r];
+        p.dst[r] = a.dst[r];
+        p.rnd[r] = nullptr;
+        p.mk[r] = a.mk[r];
+    }
+    p.L = a.L;
+    p.P = P;
+    p.TXp = tile_x;
+    p.TY = tile_y;
+    p.ZC = z_chunk;
+    p.EX = tile_x + 4;
+    p.EY = tile_y + 8;
+    p.ntx = (P + tile_x - 1) / tile_x;
+    p.nty = (a.L + tile_y - 1) / tile_y;
+    p.nzc = (a.L + z_chunk - 1) / z_chunk;
+    p.a = a.minstd_a;
+    p.a2 = a.minstd_a2;
+    p.nrep = a.nrep;
+    p.T = a.T;
+    p.WE = fused2_waves_even(tile_x, tile_y);
+    p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
+    const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
+    if (blocks < 1 || blocks > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_fused2, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
     return hipGetLastError();
 }
 

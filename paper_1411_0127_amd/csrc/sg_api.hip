@@ -149,13 +149,31 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     return SG_OK;
 }
 
-// Kernel for a sweep of nrep lattices: 1 = fused (shape in tx, ty, zc), 0 = two-pass,
-// negative = error (an explicitly chosen fused shape that does not fit nrep).
+// Kernel for sweeps of nrep lattices: 2 = two sweeps per launch, 1 = fused, 0 =
+// two-pass (shape in tx, ty, zc); negative = error (an explicitly chosen tile
+// that does not fit).
 int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
 {
     if (lat->kernel == SG_KERNEL_TWOPASS)
         return 0;
-    if (lat->tile_x > 0) {
+    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && lat->prng == SG_MINSTD)) {
+        if (lat->kernel == SG_KERNEL_FUSED2 && lat->tile_x > 0) {
+            tx = lat->tile_x;
+            ty = lat->tile_y;
+            zc = lat->z_chunk;
+            if (!fused2_shape_ok(lat->L, tx, ty, zc))
+                return fail(SG_EINVAL, "the chosen two-sweep tile does not fit this lattice");
+            return 2;
+        }
+        fused2_default_shape(lat->L, tx, ty, zc);
+        if (lat->z_chunk > 0)
+            zc = lat->z_chunk;
+        if (fused2_shape_ok(lat->L, tx, ty, zc))
+            return 2;
+        if (lat->kernel == SG_KERNEL_FUSED2)
+            return fail(SG_EINVAL, "no two-sweep tile fits this lattice");
+    }
+    if (lat->kernel == SG_KERNEL_FUSED && lat->tile_x > 0) {
         tx = lat->tile_x;
         ty = lat->tile_y;
         zc = lat->z_chunk;
@@ -173,8 +191,9 @@ int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
     return 0;
 }
 
-// One sweep of n (1 or 2) lattices that share couplings, stream and sweep count.
-int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
+// One launch of `kind` (see pick_kernel) for n (1 or 2) lattices that share
+// couplings, stream and sweep count: two sweeps for kind 2, one otherwise.
+int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, int tx, int ty, int zc)
 {
     sg_lattice *l0 = lats[0];
     const int64_t t = l0->t;
@@ -195,6 +214,7 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
     a.L = l0->L;
     a.prng = l0->prng;
     a.minstd_a = minstd_multiplier(t);
+    a.minstd_a2 = minstd_multiplier(t + 1);
     a.T = T;
     for (int r = 0; r < n; ++r) {
         a.src[r] = lats[r]->spins[lats[r]->cur];
@@ -202,23 +222,53 @@ int sweep_once(sg_lattice *const *lats, int n, const Thresholds &T)
         a.rnd[r] = lats[r]->rbuf;
         a.mk[r] = lats[r]->minstd_k;
     }
-    int tx = 0, ty = 0, zc = 0;
-    const int kind = pick_kernel(l0, n, tx, ty, zc);
-    if (kind < 0)
-        return kind;
-    if (kind == 1) {
-        e = launch_sweep_fused(a, tx, ty, zc, l0->band > 0 ? l0->band : 1, l0->stream);
+    const int band = l0->band > 0 ? l0->band : 1;
+    int done = 1;
+    if (kind == 2) {
+        e = launch_sweep_fused2(a, tx, ty, zc, band, l0->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "two-sweep launch");
+        done = 2;
+    } else if (kind == 1) {
+        e = launch_sweep_fused(a, tx, ty, zc, band, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "fused sweep launch");
-        for (int r = 0; r < n; ++r)
-            lats[r]->cur ^= 1;
     } else {
         e = launch_sweep_twopass(a, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "two-pass sweep launch");
     }
-    for (int r = 0; r < n; ++r)
-        lats[r]->t += 1;
+    for (int r = 0; r < n; ++r) {
+        if (kind != 0)
+            lats[r]->cur ^= 1;
+        lats[r]->t += done;
+    }
+    return SG_OK;
+}
+
+// nsweeps sweeps of n (1 or 2) lattices as above.  With the two-sweep kernel an
+// odd last sweep runs on the one-sweep fused kernel (same tile when it fits).
+int sweep_n(sg_lattice *const *lats, int n, int64_t nsweeps, const Thresholds &T)
+{
+    int tx = 0, ty = 0, zc = 0;
+    const int kind = pick_kernel(lats[0], n, tx, ty, zc);
+    if (kind < 0)
+        return kind;
+    while (nsweeps > 0) {
+        int k = kind, x = tx, y = ty, z = zc;
+        if (k == 2 && nsweeps < 2) {
+            k = 1;
+            if (!fused_shape_ok(lats[0]->L, n, x, y, z)) {
+                fused_default_shape(lats[0]->L, n, x, y, z);
+                if (!fused_shape_ok(lats[0]->L, n, x, y, z))
+                    k = 0;
+            }
+        }
+        const int rc = sweep_launch(lats, n, T, k, x, y, z);
+        if (rc != SG_OK)
+            return rc;
+        nsweeps -= (k == 2) ? 2 : 1;
+    }
     return SG_OK;
 }
 
@@ -387,12 +437,7 @@ int sg_sweep(sg_lattice *lat, int64_t nsweeps, double beta)
     uint64_t T[3];
     sg_thresholds(beta, lat->prng, T);
     const Thresholds th{T[0], T[1], T[2]};
-    for (int64_t i = 0; i < nsweeps; ++i) {
-        int rc = sweep_once(&lat, 1, th);
-        if (rc != SG_OK)
-            return rc;
-    }
-    return SG_OK;
+    return sweep_n(&lat, 1, nsweeps, th);
 }
 
 int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double beta)
@@ -416,13 +461,12 @@ int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double be
     uint64_t T[3];
     sg_thresholds(beta, lats[0]->prng, T);
     const Thresholds th{T[0], T[1], T[2]};
-    for (int64_t i = 0; i < nsweeps; ++i)
-        for (int r = 0; r < n; r += 2) {
-            const int m = (n - r) >= 2 ? 2 : 1;
-            int rc = sweep_once(lats + r, m, th);
-            if (rc != SG_OK)
-                return rc;
-        }
+    for (int r = 0; r < n; r += 2) {
+        const int m = (n - r) >= 2 ? 2 : 1;
+        const int rc = sweep_n(lats + r, m, nsweeps, th);
+        if (rc != SG_OK)
+            return rc;
+    }
     return SG_OK;
 }
 
@@ -590,19 +634,24 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
 {
     if (!lat)
         return fail(SG_EINVAL, "NULL lattice");
-    if (kind != SG_KERNEL_AUTO && kind != SG_KERNEL_TWOPASS && kind != SG_KERNEL_FUSED)
+    if (kind != SG_KERNEL_AUTO && kind != SG_KERNEL_TWOPASS && kind != SG_KERNEL_FUSED && kind != SG_KERNEL_FUSED2)
         return fail(SG_EINVAL, "unknown kernel");
     if (band < 0)
         return fail(SG_EINVAL, "band must be >= 0");
+    if (kind == SG_KERNEL_FUSED2 && lat->prng != SG_MINSTD)
+        return fail(SG_EINVAL, "the two-sweep kernel takes MINSTD lattices only");
     if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0)) {
         if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
             return fail(SG_EINVAL, "invalid fused tile shape");
+    } else if (kind == SG_KERNEL_FUSED2 && (tile_x != 0 || tile_y != 0)) {
+        if (!fused2_shape_ok(lat->L, tile_x, tile_y, z_chunk))
+            return fail(SG_EINVAL, "invalid two-sweep tile shape");
     } else if (z_chunk < 0 || z_chunk > lat->L) {
         return fail(SG_EINVAL, "invalid z_chunk");
     }
     lat->kernel = kind;
     lat->band = band;
-    if (kind == SG_KERNEL_FUSED) {
+    if (kind == SG_KERNEL_FUSED || kind == SG_KERNEL_FUSED2) {
         lat->tile_x = tile_x;
         lat->tile_y = tile_y;
         lat->z_chunk = z_chunk;
@@ -622,10 +671,10 @@ struct TuneKey {
     }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<int, 4>> g_tuned;
+std::map<TuneKey, std::array<int, 5>> g_tuned;  // kind, tile_x, tile_y, z_chunk, band
 }  // namespace
 
-int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *ms)
+int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *ms)
 {
     if (!lats || n < 1 || n > 2)
         return fail(SG_EINVAL, "autotune takes 1 or 2 lattices");
@@ -633,12 +682,15 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *m
         if (!lats[r] || lats[r]->L != lats[0]->L || lats[r]->prng != lats[0]->prng || lats[r]->J != lats[0]->J ||
             lats[r]->stream != lats[0]->stream)
             return fail(SG_EMISMATCH, "autotune: lattices must share L, prng, couplings and stream");
+    for (int r = 1; r < n; ++r)
+        if (lats[r] == lats[0])
+            return fail(SG_EINVAL, "a lattice appears twice");
     sg_lattice *l0 = lats[0];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         dev = 0;
     const TuneKey key{dev, l0->L, n, l0->prng};
-    std::array<int, 4> pick{0, 0, 0, 1};
+    std::array<int, 5> pick{0, 0, 0, 0, 1};
     double pick_ms = -1.0;
     bool cached = false;
     if (reps >= 0) {
@@ -659,6 +711,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *m
         a.L = l0->L;
         a.prng = l0->prng;
         a.minstd_a = 16807u;
+        a.minstd_a2 = 282475249u;
         a.T = Thresholds{T[0], T[1], T[2]};
         for (int r = 0; r < n; ++r) {
             a.src[r] = lats[r]->spins[lats[r]->cur];
@@ -678,40 +731,51 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *m
         const int bands[] = {1, 2};
         double best_ms = 1e300;
         int rc = SG_OK;
-        for (int tx : txs) {
-            if (tx > P)
-                continue;
-            for (int ty : tys) {
-                if (ty > l0->L || !fused_shape_ok(l0->L, n, tx, ty, 0))
+        // kind 1: one sweep per launch; kind 2: two (MINSTD); compared per sweep
+        for (int kind = 1; kind <= 2 && rc == SG_OK; ++kind) {
+            if (kind == 2 && l0->prng != SG_MINSTD)
+                break;
+            for (int tx : txs) {
+                if (tx > P)
                     continue;
-                for (int band : bands) {
-                    hipError_t e = launch_sweep_fused(a, tx, ty, 0, band, l0->stream);  // warm-up
-                    if (e == hipSuccess)
-                        e = hipEventRecord(e0, l0->stream);
-                    for (int k = 0; e == hipSuccess && k < nrep_launch; ++k)
-                        e = launch_sweep_fused(a, tx, ty, 0, band, l0->stream);
-                    if (e == hipSuccess)
-                        e = hipEventRecord(e1, l0->stream);
-                    if (e == hipSuccess)
-                        e = hipEventSynchronize(e1);
-                    float t_ms = 0.f;
-                    if (e == hipSuccess)
-                        e = hipEventElapsedTime(&t_ms, e0, e1);
-                    if (e != hipSuccess) {
-                        rc = hip_fail(e, "autotune launch");
+                for (int ty : tys) {
+                    if (ty > l0->L)
+                        continue;
+                    if (kind == 1 ? !fused_shape_ok(l0->L, n, tx, ty, 0) : !fused2_shape_ok(l0->L, tx, ty, 0))
+                        continue;
+                    for (int band : bands) {
+                        auto launch = [&]() {
+                            return kind == 1 ? launch_sweep_fused(a, tx, ty, 0, band, l0->stream)
+                                             : launch_sweep_fused2(a, tx, ty, 0, band, l0->stream);
+                        };
+                        hipError_t e = launch();  // warm-up
+                        if (e == hipSuccess)
+                            e = hipEventRecord(e0, l0->stream);
+                        for (int k = 0; e == hipSuccess && k < nrep_launch; ++k)
+                            e = launch();
+                        if (e == hipSuccess)
+                            e = hipEventRecord(e1, l0->stream);
+                        if (e == hipSuccess)
+                            e = hipEventSynchronize(e1);
+                        float t_ms = 0.f;
+                        if (e == hipSuccess)
+                            e = hipEventElapsedTime(&t_ms, e0, e1);
+                        if (e != hipSuccess) {
+                            rc = hip_fail(e, "autotune launch");
+                            break;
+                        }
+                        const double per_sweep = (double)t_ms / nrep_launch / kind;
+                        if (per_sweep < best_ms) {
+                            best_ms = per_sweep;
+                            pick = {kind == 1 ? SG_KERNEL_FUSED : SG_KERNEL_FUSED2, tx, ty, 0, band};
+                        }
+                    }
+                    if (rc != SG_OK)
                         break;
-                    }
-                    const double per = (double)t_ms / nrep_launch;
-                    if (per < best_ms) {
-                        best_ms = per;
-                        pick = {tx, ty, 0, band};
-                    }
                 }
                 if (rc != SG_OK)
                     break;
             }
-            if (rc != SG_OK)
-                break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -724,14 +788,14 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[4], double *m
         g_tuned[key] = pick;
     }
     for (int r = 0; r < n; ++r) {
-        lats[r]->kernel = SG_KERNEL_FUSED;
-        lats[r]->tile_x = pick[0];
-        lats[r]->tile_y = pick[1];
-        lats[r]->z_chunk = pick[2];
-        lats[r]->band = pick[3];
+        lats[r]->kernel = pick[0];
+        lats[r]->tile_x = pick[1];
+        lats[r]->tile_y = pick[2];
+        lats[r]->z_chunk = pick[3];
+        lats[r]->band = pick[4];
     }
     if (best)
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 5; ++k)
             best[k] = pick[k];
     if (ms)
         *ms = pick_ms;

@@ -212,12 +212,17 @@ struct SweepArgs {
     int L;
     int prng;
     uint32_t minstd_a;     // 16807^(t+1) mod (2^31 - 1)
+    uint32_t minstd_a2;    // 16807^(t+2) mod (2^31 - 1): second sweep of a two-sweep launch
     Thresholds T;
 };
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
+// Two sweeps (t and t+1) per launch, MINSTD only; replicas share one launch.
+bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk);
+void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk);
+hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
 
 // One lattice of a batched launch (device copy; see k_fused_batch).
 struct BatchEntry {

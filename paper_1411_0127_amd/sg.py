@@ -25,9 +25,11 @@ SG_EMISMATCH = -4
 SG_KERNEL_AUTO = 0
 SG_KERNEL_TWOPASS = 1
 SG_KERNEL_FUSED = 2
+SG_KERNEL_FUSED2 = 3
 
 PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937}
-KERNELS = {"auto": SG_KERNEL_AUTO, "twopass": SG_KERNEL_TWOPASS, "fused": SG_KERNEL_FUSED}
+KERNELS = {"auto": SG_KERNEL_AUTO, "twopass": SG_KERNEL_TWOPASS, "fused": SG_KERNEL_FUSED, "fused2": SG_KERNEL_FUSED2}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 # Every function the header declares, with its ctypes signature.
 _p = ctypes.c_void_p
@@ -223,13 +225,14 @@ def sweep_replicas(lats: Sequence[Lattice], n: int, beta: float):
 
 
 def autotune(lats: Sequence[Lattice], reps: int = 5):
-    """Pick the fastest fused tile for these lattices (1, or 2 replicas swept together);
-    returns ((tile_x, tile_y, z_chunk, band), ms per launch or -1 if taken from the cache)."""
+    """Pick the fastest fused kernel and tile for these lattices (1, or 2 replicas swept
+    together); returns ((kind, tile_x, tile_y, z_chunk, band), ms per sweep or -1 if taken
+    from the cache), kind being "fused" or "fused2"."""
     arr = (_p * len(lats))(*[l.handle for l in lats])
-    best = np.zeros(4, dtype=np.int32)
+    best = np.zeros(5, dtype=np.int32)
     ms = _d()
     _check(lib.sg_autotune(arr, len(lats), int(reps), _ptr(best), ctypes.byref(ms)))
-    return tuple(int(v) for v in best), float(ms.value)
+    return (KERNEL_NAMES[int(best[0])],) + tuple(int(v) for v in best[1:]), float(ms.value)
 
 
 def overlap(a: Lattice, b: Lattice):

@@ -85,7 +85,7 @@ def test_L1024_sampled_sites_after_two_sweeps():
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    window_check(L, "minstd", 1, 2, 0, words, n, beta, centers_for(L, np.random.default_rng(5), 120, shape[:2]))
+    window_check(L, "minstd", 1, 2, 0, words, n, beta, centers_for(L, np.random.default_rng(5), 120, shape[1:3]))
 
 
 @pytest.mark.parametrize("prng", ["minstd", "mt19937"])
@@ -100,5 +100,5 @@ def test_L256_two_replicas_sampled_sites(prng):
     sg.sweep_replicas([a, b], n, beta)
     wa, wb = a.words(), b.words()
     rng = np.random.default_rng(9)
-    window_check(L, prng, 1, 2, 0, wa, n, beta, centers_for(L, rng, 60, shape[:2]))
-    window_check(L, prng, 1, 2, 1, wb, n, beta, centers_for(L, rng, 30, shape[:2]))
+    window_check(L, prng, 1, 2, 0, wa, n, beta, centers_for(L, rng, 60, shape[1:3]))
+    window_check(L, prng, 1, 2, 1, wb, n, beta, centers_for(L, rng, 30, shape[1:3]))

@@ -139,6 +139,108 @@ def test_fused_tile_shapes_and_ragged_edges(sg, L, tiles, prng):
 
 
 # ---------------------------------------------------------------------------
+# two sweeps per launch (MINSTD): calls of 2, 3 and 4 sweeps run two-sweep
+# launches and, for an odd count, one one-sweep launch
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [8, 10, 16, 18, 32, 34])
+def test_two_sweeps_per_launch_every_call(sg, L):
+    say("fused2 64 samples", L)
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4)
+    lat.set_kernel("fused2")
+    ref = oracle_for(L, 64, "minstd", 3, 4)
+    t = 0
+    for n, beta in [(2, 0.9), (3, 0.3), (4, 2.0), (2, 1 / 1.1), (1, 0.9), (2, 0.7)]:
+        lat.sweep(n, beta)
+        ref.sweep(n, beta)
+        t += n
+        assert lat.t == t
+        assert_same(lat.words(), ref, 64, f"L={L} fused2 after {t} sweeps")
+    assert np.array_equal(lat.energy()[0], ref.unsatisfied())
+
+
+@pytest.mark.parametrize("L,tiles", [
+    (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 16, 11)),
+    (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)), (40, (20, 6, 0)), (16, (8, 16, 5)),
+])
+def test_two_sweep_tile_shapes_and_ragged_edges(sg, L, tiles):
+    say("fused2 tiles", L, tiles)
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=8, spin_seed=21)
+    lat.set_kernel("fused2", *tiles)
+    ref = oracle_for(L, 64, "minstd", 8, 21)
+    for k in range(3):
+        lat.sweep(2, 0.75)
+        ref.sweep(2, 0.75)
+        assert_same(lat.words(), ref, 64, f"L={L} fused2 tiles={tiles} after {2 * k + 2} sweeps")
+
+
+@pytest.mark.parametrize("L", [8, 16, 30])
+def test_two_sweeps_two_replicas(sg, L):
+    say("fused2 replicas", L)
+    a = sg.Lattice(L, 64, "minstd", coupling_seed=7, spin_seed=100, replica=0)
+    a.set_kernel("fused2")
+    b = sg.Lattice.replica_of(a, spin_seed=100, replica=1)
+    b.set_kernel("fused2")
+    ra = oracle_for(L, 64, "minstd", 7, 100, 0)
+    rb = oracle_for(L, 64, "minstd", 7, 100, 1)
+    for n in (2, 3, 2):
+        sg.sweep_replicas([a, b], n, 1 / 0.7)
+        ra.sweep(n, 1 / 0.7)
+        rb.sweep(n, 1 / 0.7)
+        assert_same(a.words(), ra, 64, f"replica 0 after {a.t}")
+        assert_same(b.words(), rb, 64, f"replica 1 after {b.t}")
+    nd, _ = sg.overlap(a, b)
+    assert np.array_equal(nd, oracle.ndiff(ra, rb))
+
+
+def test_two_sweeps_L16_single_sample_every_second_sweep(sg):
+    say("fused2 L16 1 sample 1000 sweeps")
+    L, beta = 16, 1 / 0.7
+    lat = sg.Lattice(L, 1, "minstd", coupling_seed=1, spin_seed=2)
+    lat.set_kernel("fused2")
+    ref = oracle_for(L, 1, "minstd", 1, 2)
+    for t in range(500):
+        lat.sweep(2, beta)
+        ref.sweep(2, beta)
+        assert lat.energy()[0][0] == ref.unsatisfied()[0], f"energy differs after sweep {2 * t + 2}"
+    assert_same(lat.words(), ref, 1, "after 1000 sweeps")
+
+
+def test_two_sweeps_beta_zero_and_infinite(sg):
+    say("fused2 beta 0 and inf")
+    lat = sg.Lattice(20, 64, "minstd", coupling_seed=1, spin_seed=2)
+    lat.set_kernel("fused2")
+    w0 = lat.words()
+    lat.sweep(2, 0.0)
+    assert np.array_equal(lat.words(), w0)  # every spin flipped twice
+    lat.sweep(3, 0.0)
+    assert np.array_equal(lat.words(), ~w0)
+    prev = lat.energy()[0]
+    for _ in range(3):
+        lat.sweep(2, math.inf)
+        U = lat.energy()[0]
+        assert np.all(U <= prev)
+        prev = U
+
+
+def test_two_sweep_kernel_argument_checks(sg):
+    mt = sg.Lattice(16, 64, "mt19937", coupling_seed=1, spin_seed=2)
+    with pytest.raises(sg.SGError) as e:
+        mt.set_kernel("fused2")
+    assert e.value.code == sg.SG_EINVAL
+    small = sg.Lattice(6, 64, "minstd", coupling_seed=1, spin_seed=2)
+    with pytest.raises(sg.SGError):
+        small.set_kernel("fused2", 3, 3, 0)
+    small.set_kernel("auto")  # falls back to the one-sweep kernel below L = 8
+    ref = oracle_for(6, 64, "minstd", 1, 2)
+    small.sweep(4, 0.8)
+    ref.sweep(4, 0.8)
+    assert_same(small.words(), ref, 64, "L=6 auto")
+    lat = sg.Lattice(16, 64, "minstd", coupling_seed=1, spin_seed=2)
+    with pytest.raises(sg.SGError):
+        lat.set_kernel("fused2", 9, 40, 0)  # more lanes than a workgroup holds
+
+
+# ---------------------------------------------------------------------------
 # replicas, overlap, energies
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [8, 16, 30])
@@ -299,7 +401,8 @@ def test_autotune_leaves_state_and_parity(sg, prng):
     rb.sweep(2, beta)
     wa, wb = a.words(), b.words()
     shape, ms = sg.autotune([a, b], reps=2)
-    assert shape[0] > 0 and shape[1] > 0 and ms > 0
+    assert shape[0] in (("fused", "fused2") if prng == "minstd" else ("fused",))
+    assert shape[1] > 0 and shape[2] > 0 and ms > 0
     assert a.t == 2 and b.t == 2
     assert np.array_equal(a.words(), wa) and np.array_equal(b.words(), wb)
     again, ms2 = sg.autotune([a, b], reps=2)
