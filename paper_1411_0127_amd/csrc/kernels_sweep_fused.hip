@@ -45,6 +45,7 @@ struct FusedParams {
     int EX, EY;          // lanes per tile row (TXp + 2), tile rows incl. ring (TY + 4)
     int ntx, nty, nzc;   // tiles along x, y, z
     int WE;              // waves holding the even tile rows
+    int WO[2];           // two sweeps per launch: waves of outer ring rows, even and odd class
     int band;            // tile rows per group of the tile order
     uint32_t a;          // MINSTD multiplier of this sweep
     uint32_t a2;         // two sweeps per launch: multiplier of the second sweep
@@ -457,6 +458,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
     p.nty = e.nty;
     p.nzc = e.nzc;
     p.WE = e.WE;
+    p.WO[0] = p.WO[1] = 0;
     p.band = e.band;
     p.a = minstd_power(e.t0 + r);
     p.a2 = 0;
@@ -599,11 +601,98 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
 // Planes in flight for the two-sweep march.
 constexpr int kRing2 = 4;
 
-template <int... Is>
-__device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
-                                             std::integer_sequence<int, Is...>)
+// The march of one work item after its lanes are set up.  P0 = (row parity +
+// first step) & 1 is the same for a whole wave; with an even ring the pair half
+// of ring slot i is then (P0 + i) & 1, known at compile time, so the steps of a
+// turn of the ring are straight-line code.
+template <int P0, int... Is>
+__device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, uint64_t *lds, const int z0,
+                                           const int ZCe, const Offsets &o, const uint32_t o_st,
+                                           const bool second, std::integer_sequence<int, Is...>)
 {
     constexpr int NS = sizeof...(Is);
+    static_assert(NS % 2 == 0, "an odd ring would change the pair half of a slot from turn to turn");
+    const int L = p.L;
+    const int64_t LL = (int64_t)L * L;
+    Offsets o_none;
+    o_none.s = o_none.f = o_none.r = kOOB;
+    auto wrap = [&](int q) -> int {  // q lies in [-6, L+6), inside [-L, 2L) as L >= 8
+        return q < 0 ? q + L : (q >= L ? q - L : q);
+    };
+
+    // first sweep's red runs over planes z0-3 .. z0+ZCe+2, reading old planes one beyond
+    const int kfirst = z0 - 3;
+    const int klast = z0 + ZCe + 2;
+    Plane<1> ring[NS];
+    ((load_plane<SG_MINSTD, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
+
+    Carry2 cy;
+    cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
+    cy.ar1 = cy.ar2 = cy.ab1 = cy.ab2 = cy.br1 = cy.br2 = 0;
+    cy.r1 = cy.b1 = cy.r2 = cy.b2 = SiteOps{0, 0, 0, 0, 0, 0, 0};
+
+    {
+        // publish plane kfirst: its old blue words (half 1-P0) and its couplings
+        uint64_t *S = lds + ((kfirst + 2) & 1) * c.set_words;
+        S[kF2OldBlue * c.nl + c.me] = P0 ? ring[1].slo[0] : ring[1].shi[0];
+        S[kF2Jx * c.nl + c.me] = ring[1].jxhi;
+        S[kF2JyLo * c.nl + c.me] = ring[1].jylo;
+        S[kF2JyHi * c.nl + c.me] = ring[1].jyhi;
+    }
+    __syncthreads();
+
+    int k = kfirst;
+    // One step with ring slots (A, B, C) = planes (k-1, k, k+1); A's slot receives
+    // plane k+NS-1 at the end.
+    auto step = [&](auto I) -> bool {
+        constexpr int i = decltype(I)::value;
+        constexpr int H = (P0 + i) & 1;
+        Plane<1> &A = ring[i];
+        const Plane<1> &B = ring[(i + 1) % NS];
+        const Plane<1> &C = ring[(i + 2) % NS];
+        uint64_t ar0 = 0, ab0 = 0, br0 = 0, bb0 = 0, jxl, jyulo, jyuhi;
+        SiteOps r0, b0;
+        const bool do_ab = k >= z0 - 1;
+        const bool do_br = second && k >= z0 + 1;
+        const bool do_bb = second && k >= z0 + 3;
+        const bool do_pub = k < klast;
+        const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);
+        const uint32_t zk1 = minstd_plane_key((uint32_t)wrap(k - 1), p.mk[0]);
+        fused2_step<H>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0, r0, b0,
+                       jxl, jyulo, jyuhi);
+        {
+            const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
+            const int64_t qo = (int64_t)wrap(k - 3) * LL * 8;
+            st_pair(plane_rsrc(p.dst[0], qo, (uint32_t)(LL * 8)), do_bb ? o_st : kOOB, wlo, whi);
+        }
+        if (do_pub)
+            __syncthreads();
+        cy.jzm2lo = A.jzlo;
+        cy.jzm2hi = A.jzhi;
+        cy.jxl = jxl;
+        cy.jyulo = jyulo;
+        cy.jyuhi = jyuhi;
+        cy.ar2 = cy.ar1;
+        cy.ar1 = ar0;
+        cy.ab2 = cy.ab1;
+        cy.ab1 = ab0;
+        cy.br2 = cy.br1;
+        cy.br1 = br0;
+        cy.r2 = cy.r1;
+        cy.r1 = r0;
+        cy.b2 = cy.b1;
+        cy.b1 = b0;
+        load_plane<SG_MINSTD, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);
+        return ++k <= klast;
+    };
+    while ((step(IC<Is>{}) && ...)) {
+    }
+}
+
+template <int... Is>
+__device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
+                                             std::integer_sequence<int, Is...> seq)
+{
     // replicas are interleaved: consecutive items are the same tile of each replica
     const int rep = item % pp.nrep;
     const int tile = item / pp.nrep;
@@ -629,13 +718,25 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     const int z0 = zc * p.ZC;
     const int ZCe = min(p.ZC, p.L - z0);
 
+    // ---- lanes: waves hold tile rows of one parity (the even class first); within a
+    // class the outer ring rows (two or more rows from the tile: 0..2 and EY-3..EY-1)
+    // come first, in waves of their own, which skip the second sweep: it is needed
+    // only up to one row from the tile.
     const int lid = threadIdx.x;
-    const int cls = lid < 64 * p.WE ? 0 : 1;
-    const int idx = cls ? lid - 64 * p.WE : lid;
-    const int rows_cls = cls ? p.EY / 2 : (p.EY + 1) / 2;
-    c.lane = idx < p.EX * rows_cls;
-    const int ex = c.lane ? idx % p.EX : 0;
-    const int ey = c.lane ? 2 * (idx / p.EX) + cls : cls;
+    const int wave = __builtin_amdgcn_readfirstlane(lid >> 6);
+    const int cls = wave < p.WE ? 0 : 1;
+    const int w = cls ? wave - p.WE : wave;
+    const bool outer = w < p.WO[cls];
+    const int idx = (outer ? w : w - p.WO[cls]) * 64 + (lid & 63);
+    const int nbot = cls ? 1 : 2;                              // rows 0..2 of this parity
+    const int t0 = ((p.EY - 3) & 1) == cls ? p.EY - 3 : p.EY - 2;  // first top outer row of this parity
+    const int ntop = ((p.EY - 3) & 1) == cls ? 2 : 1;
+    const int ifirst = cls ? 3 : 4;                            // first inner row of this parity
+    const int nin = ifirst <= p.EY - 4 ? (p.EY - 4 - ifirst) / 2 + 1 : 0;
+    const int rrow = idx / p.EX;
+    c.lane = idx < p.EX * (outer ? nbot + ntop : nin);
+    const int ex = c.lane ? idx - rrow * p.EX : 0;
+    const int ey = !c.lane ? cls : (outer ? (rrow < nbot ? cls + 2 * rrow : t0 + 2 * (rrow - nbot)) : ifirst + 2 * rrow);
     const bool full = c.lane && ey >= 1 && ey <= TYe + 6;  // rows whose red sites are computed
     const bool inter = c.lane && ex >= 2 && ex <= TXe + 1 && ey >= 4 && ey <= TYe + 3;
     const int m = (tx * p.TXp + ex - 2 + 2 * p.P) % p.P;
@@ -647,93 +748,17 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     c.iyp = min(ey + 1, p.EY - 1) * p.EX + ex;
     const int ypar = __builtin_amdgcn_readfirstlane((ty * p.TY + ey) & 1);
 
-    const int L = p.L;
-    const int64_t LL = (int64_t)L * L;
-    const uint32_t col = (uint32_t)y * (uint32_t)L + 2u * (uint32_t)m;
+    const uint32_t col = (uint32_t)y * (uint32_t)p.L + 2u * (uint32_t)m;
     c.col = col;
     Offsets o;
     o.s = c.lane ? col * 8u : kOOB;
     o.f = full ? col * 8u : kOOB;
     o.r = kOOB;
     const uint32_t o_st = inter ? col * 8u : kOOB;
-    Offsets o_none;
-    o_none.s = o_none.f = o_none.r = kOOB;
-    auto wrap = [&](int q) -> int {  // q lies in [-6, L+6), inside [-L, 2L) as L >= 8
-        return q < 0 ? q + L : (q >= L ? q - L : q);
-    };
-
-    // first sweep's red runs over planes z0-3 .. z0+ZCe+2, reading old planes one beyond
-    const int kfirst = z0 - 3;
-    const int klast = z0 + ZCe + 2;
-    Plane<1> ring[NS];
-    ((load_plane<SG_MINSTD, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
-
-    Carry2 cy;
-    cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
-    cy.ar1 = cy.ar2 = cy.ab1 = cy.ab2 = cy.br1 = cy.br2 = 0;
-    cy.r1 = cy.b1 = cy.r2 = cy.b2 = SiteOps{0, 0, 0, 0, 0, 0, 0};
-
-    {
-        uint64_t *S = lds + ((kfirst + 2) & 1) * c.set_words;
-        const bool hred = ((ypar + kfirst + L) & 1) != 0;
-        S[kF2OldBlue * c.nl + c.me] = hred ? ring[1].slo[0] : ring[1].shi[0];
-        S[kF2Jx * c.nl + c.me] = ring[1].jxhi;
-        S[kF2JyLo * c.nl + c.me] = ring[1].jylo;
-        S[kF2JyHi * c.nl + c.me] = ring[1].jyhi;
-    }
-    __syncthreads();
-
-    int k = kfirst;
-#define SG_FUSED2_STEP(A, B, C)                                                                                  \
-    {                                                                                                             \
-        uint64_t ar0 = 0, ab0 = 0, br0 = 0, bb0 = 0, jxl, jyulo, jyuhi;                                          \
-        SiteOps r0, b0;                                                                                           \
-        const bool do_ab = k >= z0 - 1;                                                                           \
-        const bool do_br = k >= z0 + 1;                                                                           \
-        const bool do_bb = k >= z0 + 3;                                                                           \
-        const bool do_pub = k < klast;                                                                            \
-        const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);                                        \
-        const uint32_t zk1 = minstd_plane_key((uint32_t)wrap(k - 1), p.mk[0]);                                   \
-        if ((ypar + k + L) & 1)                                                                                   \
-            fused2_step<1>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0,  \
-                           r0, b0, jxl, jyulo, jyuhi);                                                            \
-        else                                                                                                      \
-            fused2_step<0>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0,  \
-                           r0, b0, jxl, jyulo, jyuhi);                                                            \
-        {                                                                                                         \
-            const bool h = ((ypar + k + L) & 1) != 0;                                                             \
-            const uint64_t wlo = h ? cy.br1 : bb0, whi = h ? bb0 : cy.br1;                                        \
-            const int64_t qo = (int64_t)wrap(k - 3) * LL * 8;                                                     \
-            st_pair(plane_rsrc(p.dst[0], qo, (uint32_t)(LL * 8)), do_bb ? o_st : kOOB, wlo, whi);                 \
-        }                                                                                                         \
-        if (do_pub)                                                                                               \
-            __syncthreads();                                                                                      \
-        cy.jzm2lo = A.jzlo;                                                                                       \
-        cy.jzm2hi = A.jzhi;                                                                                       \
-        cy.jxl = jxl;                                                                                             \
-        cy.jyulo = jyulo;                                                                                         \
-        cy.jyuhi = jyuhi;                                                                                         \
-        cy.ar2 = cy.ar1;                                                                                          \
-        cy.ar1 = ar0;                                                                                             \
-        cy.ab2 = cy.ab1;                                                                                          \
-        cy.ab1 = ab0;                                                                                             \
-        cy.br2 = cy.br1;                                                                                          \
-        cy.br1 = br0;                                                                                             \
-        cy.r2 = cy.r1;                                                                                            \
-        cy.r1 = r0;                                                                                               \
-        cy.b2 = cy.b1;                                                                                            \
-        cy.b1 = b0;                                                                                               \
-        load_plane<SG_MINSTD, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);                \
-    }
-
-    auto step = [&](auto I) -> bool {
-        constexpr int i = decltype(I)::value;
-        SG_FUSED2_STEP(ring[i], ring[(i + 1) % NS], ring[(i + 2) % NS])
-        return ++k <= klast;
-    };
-    while ((step(IC<Is>{}) && ...)) {
-    }
-#undef SG_FUSED2_STEP
+    if ((ypar + z0 - 3 + p.L) & 1)
+        fused2_run<1>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+    else
+        fused2_run<0>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
@@ -925,6 +950,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.nrep = a.nrep;
     p.T = a.T;
     p.WE = fused_waves_even(tile_x, tile_y);
+    p.WO[0] = p.WO[1] = 0;
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
     const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
@@ -954,10 +980,28 @@ static size_t fused2_lds_bytes(int tile_x, int tile_y)
 {
     return (size_t)2 * ((tile_x + 4) * (tile_y + 8) + 1) * kF2Words * sizeof(uint64_t);
 }
-static int fused2_waves_even(int tile_x, int tile_y) { return ((tile_x + 4) * ((tile_y + 9) / 2) + 63) / 64; }
+// Waves of the two-sweep workgroup: per row parity class, the outer ring rows
+// (0..2 and EY-3..EY-1) and the inner rows (3..EY-4), each in whole waves.
+struct F2Waves {
+    int outer[2], inner[2];
+};
+static F2Waves fused2_waves(int tile_x, int tile_y)
+{
+    const int EX = tile_x + 4, EY = tile_y + 8;
+    F2Waves w;
+    for (int cls = 0; cls < 2; ++cls) {
+        const int nout = (cls ? 1 : 2) + (((EY - 3) & 1) == cls ? 2 : 1);
+        const int ifirst = cls ? 3 : 4;
+        const int nin = ifirst <= EY - 4 ? (EY - 4 - ifirst) / 2 + 1 : 0;
+        w.outer[cls] = (nout * EX + 63) / 64;
+        w.inner[cls] = (nin * EX + 63) / 64;
+    }
+    return w;
+}
 static int fused2_threads(int tile_x, int tile_y)
 {
-    return 64 * (fused2_waves_even(tile_x, tile_y) + ((tile_x + 4) * ((tile_y + 8) / 2) + 63) / 64);
+    const F2Waves w = fused2_waves(tile_x, tile_y);
+    return 64 * (w.outer[0] + w.inner[0] + w.outer[1] + w.inner[1]);
 }
 
 bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk)
@@ -1040,7 +1084,10 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     p.a2 = a.minstd_a2;
     p.nrep = a.nrep;
     p.T = a.T;
-    p.WE = fused2_waves_even(tile_x, tile_y);
+    const F2Waves fw = fused2_waves(tile_x, tile_y);
+    p.WE = fw.outer[0] + fw.inner[0];
+    p.WO[0] = fw.outer[0];
+    p.WO[1] = fw.outer[1];
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)

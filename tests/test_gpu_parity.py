@@ -159,7 +159,7 @@ def test_two_sweeps_per_launch_every_call(sg, L):
 
 
 @pytest.mark.parametrize("L,tiles", [
-    (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 16, 11)),
+    (24, (12, 20, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 16, 11)),
     (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)), (40, (20, 6, 0)), (16, (8, 16, 5)),
 ])
 def test_two_sweep_tile_shapes_and_ragged_edges(sg, L, tiles):
