@@ -172,7 +172,7 @@ def _budget_bytes(torch, frac=0.8):
     return int(torch.cuda.get_device_properties(0).total_memory * frac)
 
 
-def solo_sweep_ms(sg, torch, L, nsw=5):
+def solo_sweep_ms(sg, torch, L, nsw=6):
     """ms per sweep of one lattice alone (autotuned fused kernel), on its own stream."""
     stream = torch.cuda.Stream(torch.device("cuda:0"))
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)

@@ -173,9 +173,11 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
  * A batch holds lattices of any sizes (one replica each, SG_MINSTD, all on the
  * batch's stream, which must not be the legacy default stream when graphs are
  * used), each with its own inverse temperature and sweep count.  A run queues
- * rounds; a round sweeps every lattice that has sweeps left, all of them in one
- * launch (one work item per fused tile and z chunk of every lattice).  The spins
- * of each lattice after n sweeps are bit-identical to n calls of sg_sweep on it
+ * rounds; a round advances every lattice that has sweeps left, all of them in one
+ * launch (one work item per fused tile and z chunk of every lattice): by two
+ * sweeps for a lattice on SG_KERNEL_AUTO or SG_KERNEL_FUSED2 whose tile allows
+ * the two-sweep march (one for its odd last sweep), else by one.  The spins of
+ * each lattice after n sweeps are bit-identical to n calls of sg_sweep on it
  * alone.  Lattices join with sg_batch_add and leave when their sweeps are done
  * (sg_batch_take_finished); both take effect at run boundaries.  A lattice must
  * not be swept or destroyed while it is in a batch. */
@@ -203,6 +205,10 @@ int sg_batch_take_finished(sg_batch *b, sg_lattice **out, int max, int *n);
 /* Lattices with sweeps left, finished lattices not yet taken, and the work items
  * the active lattices need (any output may be NULL). */
 int sg_batch_size(const sg_batch *b, int *active, int *finished, int *items);
+
+/* Rounds until the first and until the last active lattice finishes (0 and 0
+ * when none is active); either output may be NULL. */
+int sg_batch_rounds_left(const sg_batch *b, int64_t *first, int64_t *last);
 
 int sg_batch_destroy(sg_batch *b);
 

@@ -16,6 +16,9 @@ What it computes (Lulli, Bernaschi, Parisi, arXiv:1411.0127):
   spin, with the shared number;
 * MINSTD and MT19937 generators (Sec. 3), one MINSTD stream per site and one
   MT19937 stream per x-y column;
+* a per-sample variant of the acceptance step: every coded sample draws its own
+  32-bit number per site and sweep (Philox4x32-10, Salmon et al., SC'11), instead
+  of sharing the site's;
 * observables: unsatisfied-bond count / energy per spin, and the two-replica
   overlap q (textbook definition; the paper simulates replicas, Sec. 2).
 
@@ -39,8 +42,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MINSTD = 0
 MT19937 = 1
+PHILOX = 2  # one number per sample, per site and sweep
 MINSTD_RANGE = 2**31 - 1
 MT19937_RANGE = 2**32
+PHILOX_RANGE = 2**32
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -82,6 +87,9 @@ def lib() -> ctypes.CDLL:
         L.oc_gibbs.restype = ci
         L.oc_run.argtypes = [ci, ci, ci, ci, p, p, ci, p, i64, p, p]
         L.oc_run.restype = ci
+        L.oc_philox4x32_10.argtypes = [p, p, p]
+        L.oc_sample_draws.argtypes = [ctypes.c_uint64, i64, i64, p]
+        L.oc_sample_draws_all.argtypes = [i64, ci, ctypes.c_uint64, i64, p]
         _lib = L
     return _lib
 
@@ -104,8 +112,24 @@ def mt19937_outputs(seed: int, n: int) -> np.ndarray:
     return out
 
 
+def philox4x32_10(counter, key) -> np.ndarray:
+    """Philox4x32-10 of a 4-word counter under a 2-word key (uint32 words)."""
+    c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.empty(4, dtype=np.uint32)
+    lib().oc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sample_draws(key: int, site: int, t: int) -> np.ndarray:
+    """The 64 per-sample numbers of one site in sweep t (uint32[64])."""
+    out = np.empty(64, dtype=np.uint32)
+    lib().oc_sample_draws(int(key) & 0xFFFFFFFFFFFFFFFF, int(site), int(t), _ptr(out))
+    return out
+
+
 def thresholds(beta: float, prng: int) -> np.ndarray:
-    rng = MINSTD_RANGE if prng == MINSTD else MT19937_RANGE
+    rng = MINSTD_RANGE if prng == MINSTD else (MT19937_RANGE if prng == MT19937 else PHILOX_RANGE)
     T = np.zeros(3, dtype=np.uint64)
     lib().oc_thresholds(float(beta), rng, _ptr(T))
     return T
@@ -146,8 +170,9 @@ class OracleLattice:
 
     ``J_words``: uint64 [3][V]; ``spin_words``: uint64 [V];
     ``stream_seeds``: uint32 per-site MINSTD seeds [V], or per-column MT19937
-    seeds [Lx*Ly].  Samples j < S are simulated, each with its own couplings
-    (bit j of every coupling word) and the site's shared random number.
+    seeds [Lx*Ly], or the 64-bit Philox key of the per-sample numbers.  Samples
+    j < S are simulated, each with its own couplings (bit j of every coupling
+    word) and the site's shared random number -- or, with PHILOX, its own.
     """
 
     def __init__(self, extents, nsamples, J_words, spin_words, prng, stream_seeds):
@@ -166,6 +191,8 @@ class OracleLattice:
             self.state = np.ascontiguousarray(np.asarray(stream_seeds, dtype=np.uint32).copy())
             assert self.state.shape == (self.V,)
             assert int(self.state.min()) >= 1 and int(self.state.max()) <= MINSTD_RANGE - 1
+        elif self.prng == PHILOX:
+            self.state = np.array([int(stream_seeds) & 0xFFFFFFFFFFFFFFFF, 0], dtype=np.uint64)  # key, next sweep
         else:
             seeds = np.ascontiguousarray(np.asarray(stream_seeds, dtype=np.uint32))
             assert seeds.shape == (self.Lx * self.Ly,)
@@ -175,7 +202,13 @@ class OracleLattice:
         self.last_R = np.zeros(self.V, dtype=np.uint32)
 
     def draws(self) -> np.ndarray:
-        """Random numbers of the next sweep (advances the streams)."""
+        """Random numbers of the next sweep (advances the streams): uint32 [V], or
+        [S][V] with PHILOX."""
+        if self.prng == PHILOX:
+            R = np.empty((self.S, self.V), dtype=np.uint32)
+            lib().oc_sample_draws_all(self.V, self.S, int(self.state[0]), int(self.state[1]), _ptr(R))
+            self.state[1] += np.uint64(1)
+            return R
         R = np.empty(self.V, dtype=np.uint32)
         if self.prng == MINSTD:
             lib().oc_minstd_draws(self.V, _ptr(self.state), _ptr(R))
@@ -184,10 +217,12 @@ class OracleLattice:
         return R
 
     def sweep_with(self, R: np.ndarray, beta: float, samples=None):
+        """One sweep with given numbers: R [V] shared by the samples, or R [S][V]."""
         T = thresholds(beta, self.prng)
         R = np.ascontiguousarray(np.asarray(R, dtype=np.uint32))
         for j in range(self.S) if samples is None else samples:
-            lib().oc_sweep(self.Lx, self.Ly, self.Lz, _ptr(self.s[j]), _ptr(self.J[j]), _ptr(R), _ptr(T))
+            Rj = np.ascontiguousarray(R[j]) if R.ndim == 2 else R
+            lib().oc_sweep(self.Lx, self.Ly, self.Lz, _ptr(self.s[j]), _ptr(self.J[j]), _ptr(Rj), _ptr(T))
 
     def sweep(self, n: int, beta: float, samples=None):
         for _ in range(int(n)):

@@ -120,11 +120,74 @@ void oc_mt_draws(int Lx, int Ly, int Lz, oc_mt *cols, uint32_t *R)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Per-sample draws (a variant of Sec. 4 with one random number per coded     */
+/* sample instead of one per site word): Philox4x32-10 (J. K. Salmon, M. A.  */
+/* Moraes, R. O. Dror, D. E. Shaw, "Parallel random numbers: as easy as 1, 2, */
+/* 3", SC'11), a counter-based generator: ten rounds of a multiply-and-xor    */
+/* bijection of a 128-bit counter, the 64-bit key bumped by two Weyl constants */
+/* between rounds.                                                             */
+/* ------------------------------------------------------------------------- */
+void oc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n[4] = {(uint32_t)(p1 >> 32) ^ c[1] ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c[3] ^ k1,
+                               (uint32_t)p0};
+        memcpy(c, n, sizeof(c));
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+/* The 32-bit numbers of the 64 samples at site i in sweep t (this project's
+ * convention): 32 bit-planes W[0..31] of 64 bits, bit j of W[b] being bit 31-b
+ * of sample j's number; planes 2q and 2q+1 are the outputs (o0 | o1 << 32) and
+ * (o2 | o3 << 32) of Philox4x32-10 at counter (lo32(i), hi32(i) << 8 | q,
+ * lo32(t), hi32(t)) under key (lo32(key), hi32(key)). */
+void oc_sample_draws(uint64_t key, int64_t i, int64_t t, uint32_t R[64])
+{
+    uint64_t W[32];
+    const uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t ctr[4] = {(uint32_t)i, ((uint32_t)((uint64_t)i >> 32) << 8) | (uint32_t)q, (uint32_t)t,
+                                 (uint32_t)((uint64_t)t >> 32)};
+        uint32_t o[4];
+        oc_philox4x32_10(ctr, k, o);
+        W[2 * q] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+        W[2 * q + 1] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+    }
+    for (int j = 0; j < 64; ++j) {
+        uint32_t r = 0;
+        for (int b = 0; b < 32; ++b)
+            r |= (uint32_t)((W[b] >> j) & 1u) << (31 - b);
+        R[j] = r;
+    }
+}
+
+/* Numbers of every site for samples 0..S-1 in sweep t: R[j*V + i]. */
+void oc_sample_draws_all(int64_t V, int S, uint64_t key, int64_t t, uint32_t *R)
+{
+    uint32_t r[64];
+    for (int64_t i = 0; i < V; ++i) {
+        oc_sample_draws(key, i, t, r);
+        for (int j = 0; j < S; ++j)
+            R[(int64_t)j * V + i] = r[j];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Integer acceptance thresholds (Sec. 4): a flip with energy change dE > 0 is */
 /* accepted when the integer random number R is below R_max * exp(-beta dE),   */
 /* called EXP4, EXP8, EXP12.  Reading: R_max is the size of the generator's    */
 /* output range (2^31 - 1 for MINSTD, whose outputs lie in [1, 2^31 - 2];      */
-/* 2^32 for MT19937), the product is rounded up, and the test is strict, so     */
+/* 2^32 for MT19937 and the per-sample Philox numbers), the product is rounded  */
+/* up, and the test is strict, so                                             */
 /* R < T holds exactly when R < R_max * p; beta = 0 then accepts every          */
 /* proposal and beta = +inf none.  T[k-1] is the threshold for dE = 4k.        */
 /* ------------------------------------------------------------------------- */
@@ -255,7 +318,8 @@ int oc_gibbs(int Lx, int Ly, int Lz, const int8_t *J, double beta, double *meanE
 
 /* ------------------------------------------------------------------------- */
 /* n sweeps of S samples sharing one stream set (prng 0: per-site MINSTD       */
-/* states, 1: per-column MT19937 states), thresholds fixed.  Records the       */
+/* states, 1: per-column MT19937 states, 2: per-sample Philox numbers with     */
+/* state {key, next sweep index}), thresholds fixed.  Records the             */
 /* unsatisfied-bond count of every sample after every sweep when U != NULL     */
 /* (U[t*S + j]).  s: S*V bytes; J: S*3V bytes, sample-major.                    */
 /* ------------------------------------------------------------------------- */
@@ -263,16 +327,21 @@ int oc_run(int Lx, int Ly, int Lz, int S, int8_t *s, const int8_t *J, int prng, 
            int64_t nsweeps, const uint64_t T[3], int64_t *U)
 {
     const int64_t V = (int64_t)Lx * Ly * Lz;
-    uint32_t *R = (uint32_t *)malloc((size_t)V * sizeof(uint32_t));
+    uint32_t *R = (uint32_t *)malloc((size_t)V * (prng == 2 ? S : 1) * sizeof(uint32_t));
     if (!R)
         return -2;
     for (int64_t t = 0; t < nsweeps; ++t) {
-        if (prng == 0)
+        if (prng == 0) {
             oc_minstd_draws(V, (uint32_t *)state, R);
-        else
+        } else if (prng == 1) {
             oc_mt_draws(Lx, Ly, Lz, (oc_mt *)state, R);
+        } else {
+            uint64_t *ks = (uint64_t *)state;
+            oc_sample_draws_all(V, S, ks[0], (int64_t)ks[1], R);
+            ks[1] += 1;
+        }
         for (int j = 0; j < S; ++j) {
-            oc_sweep(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V, R, T);
+            oc_sweep(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V, R + (prng == 2 ? (int64_t)j * V : 0), T);
             if (U)
                 U[t * S + j] = oc_unsatisfied(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V);
         }

@@ -27,6 +27,7 @@
 // consecutive tiles land on the same XCD (blocks are dealt to the 8 XCDs round
 // robin), and tiles are numbered in column-major blocks a few tiles tall, so the
 // workgroups resident on an XCD together cover a compact block of the plane.
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -417,56 +418,6 @@ __device__ __forceinline__ uint32_t minstd_power(int64_t t)
     return (uint32_t)result;
 }
 
-// Many lattices, one sweep each per launch ("round").  Work items of all lattices
-// are numbered consecutively; item_lat maps an item to its lattice.  A lattice
-// takes part in round r while r < its sweep count for this run; its sweep index is
-// t0 + r, its current spins are buffer c0 ^ (r & 1).  The round number is read
-// from device memory, so a captured graph of rounds replays without new
-// arguments.
-__global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *__restrict__ E,
-                                                             const uint32_t *__restrict__ item_lat, int nitems,
-                                                             const int64_t *__restrict__ round_ctr)
-{
-    extern __shared__ uint64_t lds[];
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= nitems)
-        return;
-    const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
-    const BatchEntry &e = E[li];
-    const int64_t r = *round_ctr;
-    if (r >= e.nsweeps)
-        return;
-    FusedParams p;
-    p.J = e.J;
-    const int c = e.c0 ^ (int)(r & 1);
-    p.src[0] = e.spins[c];
-    p.dst[0] = e.spins[c ^ 1];
-    p.rnd[0] = nullptr;
-    p.mk[0] = e.mk;
-    p.src[1] = p.src[0];
-    p.dst[1] = p.dst[0];
-    p.rnd[1] = nullptr;
-    p.mk[1] = e.mk;
-    p.L = e.L;
-    p.P = e.L / 2;
-    p.TXp = e.TXp;
-    p.TY = e.TY;
-    p.ZC = e.ZC;
-    p.EX = e.TXp + 2;
-    p.EY = e.TY + 4;
-    p.ntx = e.ntx;
-    p.nty = e.nty;
-    p.nzc = e.nzc;
-    p.WE = e.WE;
-    p.WO[0] = p.WO[1] = 0;
-    p.band = e.band;
-    p.a = minstd_power(e.t0 + r);
-    p.a2 = 0;
-    p.nrep = 1;
-    p.T = Thresholds{e.t4, e.t8, e.t12};
-    fused_march<SG_MINSTD, 1>(p, item - e.item0, lds, std::make_integer_sequence<int, Ring<1>::value>{});
-}
-
 __global__ void k_round_advance(int64_t *round_ctr)
 {
     if (threadIdx.x == 0)
@@ -767,6 +718,69 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
     fused2_march(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2>{});
 }
 
+// Many lattices per launch ("round").  Work items of all lattices are numbered
+// consecutively; item_lat maps an item to its lattice.  A lattice with two-sweep
+// rounds does sweeps 2r and 2r+1 of its run in round r (only 2r when that is its
+// last), otherwise sweep r; it takes part while that first sweep is below its
+// sweep count for this run.  Its current spins are buffer c0 ^ (r & 1).  The
+// round number is read from device memory, so a captured graph of rounds replays
+// without new arguments.
+__global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *__restrict__ E,
+                                                             const uint32_t *__restrict__ item_lat, int nitems,
+                                                             const int64_t *__restrict__ round_ctr)
+{
+    extern __shared__ uint64_t lds[];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nitems)
+        return;
+    const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
+    const BatchEntry &e = E[li];
+    const int64_t r = *round_ctr;
+    const int64_t s0 = e.two ? 2 * r : r;  // first sweep of this round, counted from the run's start
+    if (s0 >= e.nsweeps)
+        return;
+    const bool deep = e.two && s0 + 2 <= e.nsweeps;
+    FusedParams p;
+    p.J = e.J;
+    const int c = e.c0 ^ (int)(r & 1);
+    p.src[0] = e.spins[c];
+    p.dst[0] = e.spins[c ^ 1];
+    p.rnd[0] = nullptr;
+    p.mk[0] = e.mk;
+    p.src[1] = p.src[0];
+    p.dst[1] = p.dst[0];
+    p.rnd[1] = nullptr;
+    p.mk[1] = e.mk;
+    p.L = e.L;
+    p.P = e.L / 2;
+    p.TXp = e.TXp;
+    p.TY = e.TY;
+    p.ZC = e.ZC;
+    p.ntx = e.ntx;
+    p.nty = e.nty;
+    p.nzc = e.nzc;
+    p.band = e.band;
+    p.nrep = 1;
+    p.a = minstd_power(e.t0 + s0);
+    p.T = Thresholds{e.t4, e.t8, e.t12};
+    if (deep) {
+        p.EX = e.TXp + 4;
+        p.EY = e.TY + 8;
+        p.WE = e.WE2;
+        p.WO[0] = e.WO0;
+        p.WO[1] = e.WO1;
+        p.a2 = minstd_power(e.t0 + s0 + 1);
+        fused2_march(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2>{});
+    } else {
+        p.EX = e.TXp + 2;
+        p.EY = e.TY + 4;
+        p.WE = e.WE;
+        p.WO[0] = p.WO[1] = 0;
+        p.a2 = 0;
+        fused_march<SG_MINSTD, 1>(p, item - e.item0, lds, std::make_integer_sequence<int, Ring<1>::value>{});
+    }
+}
+
 }  // namespace
 
 static size_t fused_lds_bytes(int nrep, int tile_x, int tile_y)
@@ -781,6 +795,36 @@ static int fused_threads(int tile_x, int tile_y)
     return 64 * (fused_waves_even(tile_x, tile_y) + ((tile_x + 2) * ((tile_y + 4) / 2) + 63) / 64);
 }
 static int max_threads(int) { return kMaxThreads; }
+
+// ---- two sweeps per launch ---------------------------------------------------
+static size_t fused2_lds_bytes(int tile_x, int tile_y)
+{
+    return (size_t)2 * ((tile_x + 4) * (tile_y + 8) + 1) * kF2Words * sizeof(uint64_t);
+}
+// Waves of the two-sweep workgroup: per row parity class, the outer ring rows
+// (0..2 and EY-3..EY-1) and the inner rows (3..EY-4), each in whole waves.
+struct F2Waves {
+    int outer[2], inner[2];
+};
+static F2Waves fused2_waves(int tile_x, int tile_y)
+{
+    const int EX = tile_x + 4, EY = tile_y + 8;
+    F2Waves w;
+    for (int cls = 0; cls < 2; ++cls) {
+        const int nout = (cls ? 1 : 2) + (((EY - 3) & 1) == cls ? 2 : 1);
+        const int ifirst = cls ? 3 : 4;
+        const int nin = ifirst <= EY - 4 ? (EY - 4 - ifirst) / 2 + 1 : 0;
+        w.outer[cls] = (nout * EX + 63) / 64;
+        w.inner[cls] = (nin * EX + 63) / 64;
+    }
+    return w;
+}
+static int fused2_threads(int tile_x, int tile_y)
+{
+    const F2Waves w = fused2_waves(tile_x, tile_y);
+    return 64 * (w.outer[0] + w.inner[0] + w.outer[1] + w.inner[1]);
+}
+
 
 static int max_lds_bytes();
 
@@ -867,7 +911,7 @@ static int choose_z_chunk(int L, int64_t tiles, int64_t slots, int extra)
     return best_zc;
 }
 
-bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band)
+bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band, bool two)
 {
     if (!fused_shape_ok(L, 1, tile_x, tile_y, z_chunk) || z_chunk < 1)
         return false;
@@ -880,12 +924,21 @@ bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk,
     e.nty = (L + tile_y - 1) / tile_y;
     e.nzc = (L + z_chunk - 1) / z_chunk;
     e.WE = fused_waves_even(tile_x, tile_y);
+    e.two = (two && fused2_shape_ok(L, tile_x, tile_y, z_chunk)) ? 1 : 0;
+    const F2Waves w = fused2_waves(tile_x, tile_y);
+    e.WE2 = w.outer[0] + w.inner[0];
+    e.WO0 = w.outer[0];
+    e.WO1 = w.outer[1];
     e.band = band < 1 ? 1 : (band > e.nty ? e.nty : band);
     e.nitems = e.ntx * e.nty * e.nzc;
     return true;
 }
 
-size_t fused_batch_lds_bytes(int tile_x, int tile_y) { return fused_lds_bytes(1, tile_x, tile_y); }
+size_t fused_batch_lds_bytes(const BatchEntry &e)
+{
+    const size_t one = fused_lds_bytes(1, e.TXp, e.TY);
+    return e.two ? std::max(one, fused2_lds_bytes(e.TXp, e.TY)) : one;
+}
 
 hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
                               size_t lds, hipStream_t s)
@@ -974,35 +1027,6 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     return hipGetLastError();
 }
 
-
-// ---- two sweeps per launch ---------------------------------------------------
-static size_t fused2_lds_bytes(int tile_x, int tile_y)
-{
-    return (size_t)2 * ((tile_x + 4) * (tile_y + 8) + 1) * kF2Words * sizeof(uint64_t);
-}
-// Waves of the two-sweep workgroup: per row parity class, the outer ring rows
-// (0..2 and EY-3..EY-1) and the inner rows (3..EY-4), each in whole waves.
-struct F2Waves {
-    int outer[2], inner[2];
-};
-static F2Waves fused2_waves(int tile_x, int tile_y)
-{
-    const int EX = tile_x + 4, EY = tile_y + 8;
-    F2Waves w;
-    for (int cls = 0; cls < 2; ++cls) {
-        const int nout = (cls ? 1 : 2) + (((EY - 3) & 1) == cls ? 2 : 1);
-        const int ifirst = cls ? 3 : 4;
-        const int nin = ifirst <= EY - 4 ? (EY - 4 - ifirst) / 2 + 1 : 0;
-        w.outer[cls] = (nout * EX + 63) / 64;
-        w.inner[cls] = (nin * EX + 63) / 64;
-    }
-    return w;
-}
-static int fused2_threads(int tile_x, int tile_y)
-{
-    const F2Waves w = fused2_waves(tile_x, tile_y);
-    return 64 * (w.outer[0] + w.inner[0] + w.outer[1] + w.inner[1]);
-}
 
 bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk)
 {

@@ -728,7 +728,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         const int P = l0->L / 2;
         const int txs[] = {8, 16, 32, 64};
         const int tys[] = {4, 6, 8, 12, 16, 24};
-        const int bands[] = {1, 2};
+        const int bands[] = {1, 2, 4};
         double best_ms = 1e300;
         int rc = SG_OK;
         // kind 1: one sweep per launch; kind 2: two (MINSTD); compared per sweep

@@ -1,7 +1,8 @@
 // Batch runtime of libsg: many lattices of different sizes, temperatures and
-// sweep counts advanced together.  Each round sweeps every lattice that still has
-// sweeps to do, all of them in one launch of k_fused_batch (one work item per
-// tile and z chunk of every lattice).  Rounds run eagerly or replay a captured
+// sweep counts advanced together.  Each round advances every lattice that still
+// has sweeps to do, all of them in one launch of k_fused_batch (one work item per
+// tile and z chunk of every lattice): by two sweeps on the two-sweep march (one
+// for an odd last sweep), else by one.  Rounds run eagerly or replay a captured
 // hipGraph of `rounds_per_graph` rounds; the round number lives in device memory
 // so the graph needs no new arguments.  Lattices join and leave between runs: a
 // serving loop admits and retires at those boundaries.
@@ -58,18 +59,30 @@ void drop_graph(sg_batch *b)
     b->graph_items = -1;
 }
 
-// Tile of a lattice inside a batch: the autotuned or default fused tile, z chunks
-// of up to 128 planes so that work items of big lattices stay comparable.
+// Tile of a lattice inside a batch: its chosen (autotuned) tile or the default of
+// its kernel, z chunks of up to 128 planes so that work items of big lattices stay
+// comparable.  Lattices on the automatic or two-sweep kernel get two-sweep rounds
+// when the tile allows them.
 int batch_tile(const sg_lattice *lat, BatchEntry &e)
 {
-    int tx = lat->tile_x, ty = lat->tile_y, zc = 0;
-    if (tx <= 0 || ty <= 0)
+    const bool want_two = lat->kernel == SG_KERNEL_AUTO || lat->kernel == SG_KERNEL_FUSED2;
+    int tx = 0, ty = 0, zc = 0;
+    if ((lat->kernel == SG_KERNEL_FUSED || lat->kernel == SG_KERNEL_FUSED2) && lat->tile_x > 0) {
+        tx = lat->tile_x;
+        ty = lat->tile_y;
+    } else if (want_two && lat->L >= 8) {
+        fused2_default_shape(lat->L, tx, ty, zc);
+    } else {
         fused_default_shape(lat->L, 1, tx, ty, zc);
+    }
     zc = lat->L <= 128 ? lat->L : std::max(64, std::min(128, lat->L / 4));
-    if (!fill_batch_entry(e, lat->L, tx, ty, zc, lat->band > 0 ? lat->band : 1))
+    if (!fill_batch_entry(e, lat->L, tx, ty, zc, lat->band > 0 ? lat->band : 1, want_two))
         return fail(SG_EINVAL, "no fused tile fits a lattice of side " + std::to_string(lat->L));
     return SG_OK;
 }
+
+// Rounds a lattice needs for `left` sweeps.
+int64_t rounds_for(const BatchEntry &e, int64_t left) { return e.two ? (left + 1) / 2 : left; }
 
 // Lay out the work items of the current jobs (after jobs joined or left).
 int build_layout(sg_batch *b)
@@ -88,7 +101,7 @@ int build_layout(sg_batch *b)
             return fail(SG_EINVAL, "batch work items exceed max_items");
         items += e.nitems;
         b->h_item_lat.insert(b->h_item_lat.end(), (size_t)e.nitems, (uint32_t)j);
-        lds = std::max(lds, fused_batch_lds_bytes(e.TXp, e.TY));
+        lds = std::max(lds, fused_batch_lds_bytes(e));
     }
     b->nitems = items;
     b->lds = lds;
@@ -186,8 +199,8 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
             return rc;
     }
     int64_t R = 0;
-    for (const auto &j : b->jobs)
-        R = std::max(R, j.left);
+    for (size_t j = 0; j < b->jobs.size(); ++j)
+        R = std::max(R, rounds_for(b->h_entries[j], b->jobs[j].left));
     R = std::min(R, max_rounds);
     // per-run lattice state: sweep count, current buffer, sweeps in this run
     for (size_t j = 0; j < b->jobs.size(); ++j) {
@@ -199,7 +212,7 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
         e.mk = job.lat->minstd_k;
         e.c0 = job.lat->cur;
         e.t0 = job.lat->t;
-        e.nsweeps = std::min(job.left, R);
+        e.nsweeps = std::min(job.left, e.two ? 2 * R : R);
         uint64_t T[3];
         sg_thresholds(job.beta, SG_MINSTD, T);
         e.t4 = T[0];
@@ -260,10 +273,12 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
     }
     // the host view of every lattice moves with the queued rounds
     std::vector<sg_batch::Job> keep;
-    for (auto &job : b->jobs) {
-        const int64_t d = std::min(job.left, R);
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        sg_batch::Job &job = b->jobs[j];
+        const BatchEntry &en = b->h_entries[j];
+        const int64_t d = en.nsweeps;  // sweeps done in this run
         job.lat->t += d;
-        job.lat->cur ^= (int)(d & 1);
+        job.lat->cur ^= (int)(rounds_for(en, d) & 1);
         job.left -= d;
         if (job.left == 0)
             b->finished.push_back(job.lat);
@@ -308,6 +323,29 @@ int sg_batch_size(const sg_batch *b, int *active, int *finished, int *items)
         }
         *items = n;
     }
+    return SG_OK;
+}
+
+int sg_batch_rounds_left(const sg_batch *b, int64_t *first, int64_t *last)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    int64_t lo = 0, hi = 0;
+    bool any = false;
+    for (const auto &job : b->jobs) {
+        BatchEntry e{};
+        const int rc = batch_tile(job.lat, e);
+        if (rc != SG_OK)
+            return rc;
+        const int64_t n = rounds_for(e, job.left);
+        lo = any ? std::min(lo, n) : n;
+        hi = any ? std::max(hi, n) : n;
+        any = true;
+    }
+    if (first)
+        *first = lo;
+    if (last)
+        *last = hi;
     return SG_OK;
 }
 

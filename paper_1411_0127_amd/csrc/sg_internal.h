@@ -230,6 +230,8 @@ struct BatchEntry {
     uint64_t *spins[2];
     uint32_t mk;     // MINSTD key
     int L, TXp, TY, ZC, ntx, nty, nzc, WE, band;
+    int two;         // 1: rounds of two sweeps (two-sweep march), 0: one sweep per round
+    int WE2, WO0, WO1;  // wave layout of the two-sweep march
     int c0;          // current spin buffer when the run starts
     int item0;       // first work item
     int nitems;      // work items: tiles x z chunks
@@ -237,8 +239,9 @@ struct BatchEntry {
     int64_t nsweeps; // sweeps to do in this run
     uint64_t t4, t8, t12;
 };
-bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band);
-size_t fused_batch_lds_bytes(int tile_x, int tile_y);
+// two: ask for two-sweep rounds; it is cleared when the tile does not fit them.
+bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk, int band, bool two);
+size_t fused_batch_lds_bytes(const BatchEntry &e);
 hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
                               size_t lds, hipStream_t s);
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);

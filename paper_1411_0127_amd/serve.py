@@ -94,7 +94,6 @@ class GpuBackend:
         self.autotune = autotune
         self._inflight = []  # events of queued runs; at most two are kept in flight
         self._tuned = set()
-        self._left: Dict[int, int] = {}
 
     def footprint(self, job: Job) -> int:
         return self.sg.footprint(job.L, "minstd", True)
@@ -125,16 +124,13 @@ class GpuBackend:
         elif self.autotune and job.L in self._tuned:
             self.sg.autotune([lat], reps=3)  # cache hit: sets the tuned tile
         self.batch.add(lat, job.nsweeps, job.beta)
-        self._left[id(lat)] = job.nsweeps
         return lat
 
-    def min_left(self) -> int:
-        return min(self._left.values()) if self._left else 0
+    def rounds_to_first_finish(self) -> int:
+        return self.batch.rounds_left()[0]
 
     def run(self, rounds: int) -> int:
         done = self.batch.run(rounds, self.rounds_per_graph)
-        for k in list(self._left):
-            self._left[k] -= done
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         self._inflight.append(ev)
@@ -143,10 +139,7 @@ class GpuBackend:
         return done
 
     def finished(self):
-        out = self.batch.take_finished()
-        for lat in out:
-            self._left.pop(id(lat), None)
-        return out
+        return self.batch.take_finished()
 
     def result(self, lat):
         U, e = lat.energy()  # synchronises the stream up to this lattice's last round
@@ -158,8 +151,9 @@ class GpuBackend:
 
 
 class SimBackend:
-    """A model of the device: a round costs `sec_per_site` x (sites of the active
-    lattices) + `round_overhead`, on a virtual clock."""
+    """A model of the device: a round advances every active lattice by two sweeps
+    (one for an odd last sweep), as the GPU batch does, and costs `sec_per_site` x
+    (site sweeps done) + `round_overhead`, on a virtual clock."""
 
     def __init__(self, sec_per_site: float = 1.0e-11, round_overhead: float = 20e-6):
         self.t = 0.0
@@ -184,19 +178,19 @@ class SimBackend:
         self.active[h] = [job, job.nsweeps]
         return h
 
-    def min_left(self) -> int:
-        return min(v[1] for v in self.active.values()) if self.active else 0
+    def rounds_to_first_finish(self) -> int:
+        return min((v[1] + 1) // 2 for v in self.active.values()) if self.active else 0
 
     def run(self, rounds: int) -> int:
         if not self.active:
             return 0
-        R = min(rounds, max(v[1] for v in self.active.values()))
+        R = min(rounds, max((v[1] + 1) // 2 for v in self.active.values()))
         for _ in range(R):
-            sites = sum(v[0].L**3 for v in self.active.values() if v[1] > 0)
-            self.t += self.round_overhead + sites * self.sec_per_site
+            site_sweeps = sum(v[0].L**3 * min(2, v[1]) for v in self.active.values() if v[1] > 0)
+            self.t += self.round_overhead + site_sweeps * self.sec_per_site
             for h, v in list(self.active.items()):
                 if v[1] > 0:
-                    v[1] -= 1
+                    v[1] -= min(2, v[1])
                     if v[1] == 0:
                         self._done.append(h)
         return R
@@ -281,7 +275,8 @@ class Server:
     chunk_rounds bounds the rounds queued per run, so arrivals wait at most one
     chunk to be admitted; a run also stops when the first active job finishes (but
     lasts at least min_rounds), so finished jobs are read back and their memory
-    freed promptly."""
+    freed promptly.  A round is one launch over all active lattices (two sweeps
+    each on the GPU's two-sweep march)."""
 
     def __init__(self, backend, budget_bytes: int, chunk_rounds: int = 50, min_rounds: int = 1):
         self.b = backend
@@ -320,7 +315,7 @@ class Server:
                     if records or rejected:  # idle time inside the served span
                         idle += self.b.now() - w0
                 continue
-            r = min(self.chunk, max(self.min_rounds, self.b.min_left()))
+            r = min(self.chunk, max(self.min_rounds, self.b.rounds_to_first_finish()))
             rounds += self.b.run(r)
             runs += 1
             for h in self.b.finished():

@@ -62,6 +62,7 @@ SIGNATURES = {
     "sg_batch_add": (_i, [_p, _p, _i64, _d]),
     "sg_batch_run": (_i, [_p, _i64, _i, ctypes.POINTER(_i64)]),
     "sg_batch_take_finished": (_i, [_p, ctypes.POINTER(_p), _i, ctypes.POINTER(_i)]),
+    "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "sg_batch_destroy": (_i, [_p]),
     "sg_destroy": (_i, [_p]),
@@ -280,6 +281,12 @@ class Batch:
                 out.append(self._members.pop(arr[k]))
             if n.value < 64:
                 return out
+
+    def rounds_left(self):
+        """(rounds until the first active lattice finishes, rounds until the last does)."""
+        lo, hi = _i64(), _i64()
+        _check(lib.sg_batch_rounds_left(self.handle, ctypes.byref(lo), ctypes.byref(hi)))
+        return int(lo.value), int(hi.value)
 
     def size(self):
         a, f, it = _i(), _i(), _i()

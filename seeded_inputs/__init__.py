@@ -29,7 +29,9 @@ Conventions (this project's, stated once here):
   [1, 2**31 - 2], i.e. a valid non-zero MINSTD state; fmix32 is the 32-bit
   finalizer of MurmurHash3 (A. Appleby), a bijection of 32-bit words;
 * MT19937 seed of column c = x + L*y, replica r:
-  ``out(key(spin_seed, TAG_MT, r), 1 + c) & 0xffffffff``.
+  ``out(key(spin_seed, TAG_MT, r), 1 + c) & 0xffffffff``;
+* key of the per-sample (Philox4x32-10) numbers of replica r:
+  ``key(spin_seed, TAG_PHILOX, r)``.
 """
 from __future__ import annotations
 
@@ -43,6 +45,7 @@ TAG_J = 1
 TAG_SPIN = 2
 TAG_MINSTD = 3
 TAG_MT = 4
+TAG_PHILOX = 5
 
 MINSTD_MODULUS = 2**31 - 1
 
@@ -135,6 +138,11 @@ def mt_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
     k = key(spin_seed, TAG_MT, replica)
     c = np.arange(1, L * L + 1, dtype=np.uint64)
     return (out(k, c) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def philox_key(spin_seed: int, replica: int) -> int:
+    """64-bit key of the per-sample numbers of one replica."""
+    return key(spin_seed, TAG_PHILOX, replica)
 
 
 def coupling_words_at(L: int, coupling_seed: int, sites: np.ndarray) -> np.ndarray:

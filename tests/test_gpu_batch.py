@@ -63,8 +63,12 @@ def test_batch_matches_solo_and_oracle(env, graph):
         lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
         b.add(lat, n, beta)
         lats.append(lat)
+    first, last = b.rounds_left()
+    # two-sweep rounds: a lattice of n sweeps takes ceil(n / 2) of them
+    assert (first, last) == (min((j[4] + 1) // 2 for j in JOBS), max((j[4] + 1) // 2 for j in JOBS))
     done = b.run(1000, graph)
-    assert done == max(j[4] for j in JOBS)
+    assert done == last
+    assert b.rounds_left() == (0, 0)
     fin = b.take_finished()
     assert sorted(id(x) for x in fin) == sorted(id(x) for x in lats)
     for lat, (L, cs, ss, beta, n) in zip(lats, JOBS):
@@ -108,13 +112,13 @@ def test_graph_replays_one_by_one(env):
     lats = []
     for (L, cs, ss, beta) in specs:
         lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
-        b.add(lat, 12, beta)
+        b.add(lat, 24, beta)
         lats.append(lat)
     solos = [sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream) for (L, cs, ss, _) in specs]
-    for rep in range(6):  # six replays of the same 2-round graph
+    for rep in range(6):  # six replays of the same 2-round graph, 4 sweeps each
         assert b.run(2, 2) == 2
         for lat, solo, (L, cs, ss, beta) in zip(lats, solos, specs):
-            solo.sweep(2, beta)
+            solo.sweep(4, beta)
             lat.energy()  # eager work and a synchronisation between replays
             assert np.array_equal(lat.words(), solo.words()), f"replay {rep} L={L}"
     b.close()

@@ -19,12 +19,13 @@ def test_served_results_equal_solo_runs():
     print("[case] serve small trace", flush=True)
     sys.stdout.flush()
     rng = np.random.default_rng(11)
-    jobs = []
+    # a long first job (about a thousand rounds) that the later arrivals overlap
+    jobs = [Job(0, 32, 2001, 1 / 0.9, 700, 800, 0.0)]
     t = 0.0
-    for k in range(14):
-        t += float(rng.exponential(0.01))
+    for k in range(1, 14):
+        t += float(rng.exponential(0.002))
         L = int(rng.choice([8, 16, 24, 32]))
-        jobs.append(Job(k, L, int(rng.integers(3, 30)), float(1 / rng.uniform(0.6, 1.4)), 700 + k, 800 + k, t))
+        jobs.append(Job(k, L, int(rng.integers(3, 60)), float(1 / rng.uniform(0.6, 1.4)), 700 + k, 800 + k, t))
     be = GpuBackend(max_lattices=16, max_items=100000, rounds_per_graph=2, autotune=False)
     budget = 3 * sg.footprint(32)
     words = {}
