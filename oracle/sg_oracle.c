@@ -150,7 +150,7 @@ void oc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
  * of sample j's number; planes 2q and 2q+1 are the outputs (o0 | o1 << 32) and
  * (o2 | o3 << 32) of Philox4x32-10 at counter (lo32(i), hi32(i) << 8 | q,
  * lo32(t), hi32(t)) under key (lo32(key), hi32(key)). */
-void oc_sample_draws(uint64_t key, int64_t i, int64_t t, uint32_t R[64])
+static void sample_draws_n(uint64_t key, int64_t i, int64_t t, int n, uint32_t *R)
 {
     uint64_t W[32];
     const uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
@@ -162,7 +162,7 @@ void oc_sample_draws(uint64_t key, int64_t i, int64_t t, uint32_t R[64])
         W[2 * q] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
         W[2 * q + 1] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
     }
-    for (int j = 0; j < 64; ++j) {
+    for (int j = 0; j < n; ++j) {
         uint32_t r = 0;
         for (int b = 0; b < 32; ++b)
             r |= (uint32_t)((W[b] >> j) & 1u) << (31 - b);
@@ -170,12 +170,14 @@ void oc_sample_draws(uint64_t key, int64_t i, int64_t t, uint32_t R[64])
     }
 }
 
+void oc_sample_draws(uint64_t key, int64_t i, int64_t t, uint32_t R[64]) { sample_draws_n(key, i, t, 64, R); }
+
 /* Numbers of every site for samples 0..S-1 in sweep t: R[j*V + i]. */
 void oc_sample_draws_all(int64_t V, int S, uint64_t key, int64_t t, uint32_t *R)
 {
     uint32_t r[64];
     for (int64_t i = 0; i < V; ++i) {
-        oc_sample_draws(key, i, t, r);
+        sample_draws_n(key, i, t, S, r);
         for (int j = 0; j < S; ++j)
             R[(int64_t)j * V + i] = r[j];
     }

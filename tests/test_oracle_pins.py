@@ -378,3 +378,137 @@ def test_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
         m2, err2 = _binned_mean_err(E[:, j] ** 2)
         err2 = max(err2, math.sqrt(max(var2, 0.0) / n))
         assert abs(m2 - e2) < 5 * err2, (j, m2, e2, err2)
+
+
+# ---------------------------------------------------------------------------
+# per-sample numbers (one 32-bit draw per coded sample, per site and sweep)
+# ---------------------------------------------------------------------------
+PHILOX_KAT = [  # known-answer vectors of the Philox4x32-10 definition (Salmon et al., SC'11)
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+def test_philox_known_answers():
+    for ctr, key, want in PHILOX_KAT:
+        assert tuple(int(v) for v in oracle.philox4x32_10(ctr, key)) == want
+
+
+def _rocrand_philox_tool(tmp_path):
+    """A host program computing Philox4x32-10 with rocRAND's own implementation
+    (a header shipped with ROCm), to compare the oracle against."""
+    import shutil
+    import subprocess
+
+    hdr = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hdr) or not os.path.exists(hipcc):
+        pytest.skip("rocRAND headers or hipcc not available")
+    src = tmp_path / "philox_ref.cpp"
+    src.write_text(
+        "#include <cstdio>\n#include <rocrand/rocrand_philox4x32_10.h>\n"
+        "struct Raw : rocrand_device::philox4x32_10_engine {\n"
+        "  uint4 run(uint4 c, uint2 k) { return ten_rounds(c, k); }\n};\n"
+        "int main() { Raw r; unsigned v[6];\n"
+        "  while (scanf(\"%x %x %x %x %x %x\", v, v + 1, v + 2, v + 3, v + 4, v + 5) == 6) {\n"
+        "    uint4 o = r.run(uint4{v[0], v[1], v[2], v[3]}, uint2{v[4], v[5]});\n"
+        "    printf(\"%x %x %x %x\\n\", o.x, o.y, o.z, o.w); } }\n")
+    exe = tmp_path / "philox_ref"
+    r = subprocess.run([hipcc, "-O1", "-o", str(exe), str(src)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("cannot build the rocRAND reference: " + r.stderr[-300:])
+    return exe
+
+
+def test_philox_matches_rocrand(tmp_path):
+    import subprocess
+
+    exe = _rocrand_philox_tool(tmp_path)
+    rng = np.random.default_rng(77)
+    cases = rng.integers(0, 2**32, size=(300, 6), dtype=np.uint64)
+    inp = "\n".join(" ".join(f"{int(v):x}" for v in row) for row in cases) + "\n"
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for row, line in zip(cases, out):
+        want = [int(v, 16) for v in line.split()]
+        got = oracle.philox4x32_10(row[:4], row[4:])
+        assert [int(v) for v in got] == want, row
+
+
+def test_per_sample_numbers_are_uniform_and_distinct_across_samples():
+    key = si.philox_key(5, 0)
+    R = np.stack([oracle.sample_draws(key, i, t) for i in range(300) for t in (0, 1, 7)])  # [900][64]
+    # top 4 bits of 57600 draws: chi-square with 15 degrees of freedom
+    h = np.bincount((R >> np.uint32(28)).ravel(), minlength=16)
+    e = R.size / 16
+    chi2 = float(((h - e) ** 2 / e).sum())
+    assert chi2 < 45.0, chi2  # p ~ 1e-4
+    # neighbouring samples, sites and sweeps draw different numbers
+    assert (R[:, 1:] != R[:, :-1]).mean() > 0.999
+    assert (R[1:] != R[:-1]).mean() > 0.999
+    # every bit of every sample is used: each of the 32 bit positions is set about half the time
+    bits = ((R[..., None] >> np.arange(32, dtype=np.uint32)) & np.uint32(1)).mean(axis=(0, 1))
+    assert np.all(np.abs(bits - 0.5) < 0.02)
+
+
+def test_per_sample_numbers_split_identical_samples():
+    """With one number per site (asynchronous multispin coding) samples with the
+    same couplings and start stay identical; with one number per sample they
+    evolve apart."""
+    ext = (6, 6, 6)
+    V = 216
+    rng = np.random.default_rng(3)
+    J1 = rng.integers(0, 2, size=(3, V)).astype(np.uint64) * np.uint64(0xFFFFFFFFFFFFFFFF)
+    S1 = rng.integers(0, 2, size=V).astype(np.uint64) * np.uint64(0xFFFFFFFFFFFFFFFF)
+    shared = oracle.OracleLattice(ext, 64, J1, S1, oracle.MINSTD, si.minstd_seeds(6, 9, 0))
+    own = oracle.OracleLattice(ext, 64, J1, S1, oracle.PHILOX, si.philox_key(9, 0))
+    shared.sweep(4, 0.8)
+    own.sweep(4, 0.8)
+    assert len({w.tobytes() for w in shared.s}) == 1
+    assert len({w.tobytes() for w in own.s}) > 32
+
+
+def test_per_sample_beta_zero_and_zero_temperature():
+    ext = (4, 4, 4)
+    V = 64
+    rng = np.random.default_rng(8)
+    Jw = rng.integers(0, 2**63, size=(3, V), dtype=np.uint64)
+    Sw = rng.integers(0, 2**63, size=V, dtype=np.uint64)
+    lat = oracle.OracleLattice(ext, 64, Jw, Sw, oracle.PHILOX, 12345)
+    lat.sweep(1, 0.0)
+    assert np.array_equal(lat.words(), ~Sw)  # every proposal accepted
+    prev = lat.unsatisfied()
+    for _ in range(4):
+        lat.sweep(1, math.inf)
+        U = lat.unsatisfied()
+        assert np.all(U <= prev)
+        prev = U
+
+
+@pytest.mark.parametrize("beta", [0.5, 1 / 0.7])
+def test_per_sample_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
+    """The per-sample variant is Metropolis for every sample on its own: time
+    averages of E and E^2 agree with exact enumeration within 5 standard errors."""
+    ext = (2, 2, 4)
+    V = 16
+    S = 6
+    rng = np.random.default_rng(2025)
+    Jw = rng.integers(0, 2**63, size=(3, V), dtype=np.uint64)
+    Sw = rng.integers(0, 2**63, size=V, dtype=np.uint64)
+    lat = oracle.OracleLattice(ext, S, Jw, Sw, oracle.PHILOX, si.philox_key(4, 0))
+    lat.run(1000, beta)
+    U = lat.run(30000, beta, record=True)
+    E = 2.0 * U - 3.0 * V
+    n = E.shape[0]
+    for j in range(S):
+        e1, e2, hist = oracle.gibbs(ext, lat.J[j], beta)
+        var1 = e2 - e1 * e1
+        Eu = 2.0 * np.arange(3 * V + 1) - 3.0 * V
+        var2 = float((hist * Eu**4).sum()) - e2 * e2
+        m, err = _binned_mean_err(E[:, j])
+        err = max(err, math.sqrt(max(var1, 0.0) / n))
+        assert abs(m - e1) < 5 * err, (j, m, e1, err)
+        m2, err2 = _binned_mean_err(E[:, j] ** 2)
+        err2 = max(err2, math.sqrt(max(var2, 0.0) / n))
+        assert abs(m2 - e2) < 5 * err2, (j, m2, e2, err2)
