@@ -27,10 +27,10 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # L=256 cube, 64 samples per word, 2 replicas sharing the couplings, T=0.7
-    "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd", variant="mt19937",
+    "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=("mt19937", "philox"),
                desc="L=256 periodic cube, 64 samples multispin-coded per uint64, 2 replicas sharing "
                     "J=+-1 (p=1/2), random start, T=0.7, 1000 sweeps per step, MINSTD per-site streams "
-                    "(MT19937 per-column streams as variant)"),
+                    "(variants: MT19937 per-column streams; one Philox number per sample)"),
     # L=1024 cube, 64 samples, one replica, T=1.1, 100 sweeps
     "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd", variant=None,
                desc="L=1024 periodic cube, 64 samples multispin-coded per uint64, J=+-1 (p=1/2), "
@@ -103,8 +103,8 @@ def run_gpu(args, wl):
             parts = args.tile.split(",")
             kind = parts[0] if not parts[0].isdigit() else "fused"
             nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
-            if kind == "fused2" and prng != "minstd":
-                kind = "fused"  # the two-sweep kernel takes MINSTD lattices only
+            if kind == "fused2" and prng == "mt19937":
+                kind = "fused"  # the two-sweep kernel takes MINSTD and Philox lattices
             shape = (kind,) + nums
             for l in lats:
                 l.set_kernel(kind, *nums)
@@ -117,7 +117,7 @@ def run_gpu(args, wl):
             for l in lats:
                 l.set_kernel(args.kernel)
         kind = shape[0] if shape else args.kernel
-        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng == "minstd")) and nsw % 2 == 0 else 1
+        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng != "mt19937")) and nsw % 2 == 0 else 1
 
         def step(ev=None):
             if ev is not None:
@@ -164,8 +164,11 @@ def run_gpu(args, wl):
         return res
 
     main = measure(wl["prng"])
-    variant = measure(wl["variant"]) if (wl.get("variant") and not args.no_variant) else None
-    return main, variant
+    variants = {}
+    if not args.no_variant:
+        for v in wl.get("variant") or ():
+            variants[v] = measure(v)
+    return main, variants
 
 
 def _budget_bytes(torch, frac=0.8):
@@ -317,7 +320,7 @@ def main():
         line["summary"] = res["summary"]
         print(json.dumps(line), flush=True)
         return
-    main_res, variant = run_gpu(args, wl)
+    main_res, variants = run_gpu(args, wl)
     if args.calibrate_copy:
         import torch
 
@@ -371,13 +374,16 @@ def main():
             "launch_ms": round(main_res["launch_ms"], 5),
         },
     }
-    if variant is not None:
+    if variants:
         line["variants"] = {
-            wl["variant"]: {
-                "ps_per_flip": round(variant["ps_per_flip"], 6),
-                "ms_per_step": round(variant["ms_per_step"], 4),
-                "sweep_launch_ms": round(variant["launch_ms"], 5),
+            name: {
+                "ps_per_flip": round(v["ps_per_flip"], 6),
+                "ms_per_step": round(v["ms_per_step"], 4),
+                "launch_ms": round(v["launch_ms"], 5),
+                "sweeps_per_launch": v["sweeps_per_launch"],
+                "kernel": v["kind"],
             }
+            for name, v in variants.items()
         }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -29,14 +29,24 @@
  *              replica's keyed word; no per-site state is stored;
  *   SG_MT19937 one MT19937 stream per x-y column and replica, seeded with
  *              init_genrand; in sweep t the site at height z draws the column's
- *              output number t*L + z.
+ *              output number t*L + z;
+ *   SG_PHILOX  one number per coded sample instead of one per site word (a
+ *              variant of Sec. 4's asynchronous coding): sample j of site i
+ *              draws a 32-bit R_j in sweep t from Philox4x32-10 (Salmon et al.,
+ *              SC'11) in bit-sliced form -- plane b (0..31) is a 64-bit word
+ *              whose bit j is bit 31-b of R_j, and planes 2q, 2q+1 are the
+ *              outputs (o0 | o1 << 32, o2 | o3 << 32) at counter (lo32(i),
+ *              hi32(i) << 8 | q, lo32(t), hi32(t)) under the replica's 64-bit
+ *              keyed word; the planes are drawn from the most significant down
+ *              only until every sample's comparison is decided.
  * The keys, the MT19937 seeds, the initial spins and (unless given) the
  * couplings come from the SplitMix64 keyed generator documented with the
  * seeded-input module (Steele, Lea, Flood 2014), evaluated on the device.
  *
  * Acceptance: a proposal with dE > 0 is accepted iff R < T(dE) with
  * T(dE) = ceil(R_range * exp(-beta * dE)), R_range = 2^31 - 1 (MINSTD) or 2^32
- * (MT19937); dE <= 0 is always accepted (Sec. 4, P_flip and EXP4/EXP8/EXP12).
+ * (MT19937, PHILOX); dE <= 0 is always accepted (Sec. 4, P_flip and
+ * EXP4/EXP8/EXP12).
  *
  * Conventions of every entry point:
  *   - returns SG_OK (0) or a negative SG_E* code; sg_last_error() then holds a
@@ -62,7 +72,7 @@ extern "C" {
 
 typedef struct sg_lattice sg_lattice;
 
-enum { SG_MINSTD = 0, SG_MT19937 = 1 };
+enum { SG_MINSTD = 0, SG_MT19937 = 1, SG_PHILOX = 2 };
 
 enum {
     SG_OK = 0,
@@ -80,11 +90,11 @@ enum {
  *                    columns along z, red plane k then blue plane k-1, in-plane
  *                    neighbours exchanged through LDS, old/new spins in two
  *                    buffers and tile-edge red sites recomputed by both tiles.
- * SG_KERNEL_FUSED2:  two sweeps per launch (SG_MINSTD only): the same march
+ * SG_KERNEL_FUSED2:  two sweeps per launch (SG_MINSTD, SG_PHILOX): the same march
  *                    carries sweep t+1 two planes behind sweep t, so spins and
  *                    couplings cross HBM once per two sweeps; an odd last sweep
  *                    of a call runs on SG_KERNEL_FUSED.
- * SG_KERNEL_AUTO picks SG_KERNEL_FUSED2 for SG_MINSTD lattices and
+ * SG_KERNEL_AUTO picks SG_KERNEL_FUSED2 for SG_MINSTD and SG_PHILOX lattices and
  * SG_KERNEL_FUSED otherwise, with default tiles (sg_autotune picks by timing). */
 enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2, SG_KERNEL_FUSED2 = 3 };
 
@@ -137,7 +147,8 @@ int sg_get_words(const sg_lattice *lat, uint64_t *out, size_t n);
 int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n);
 int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n);
 
-/* The random number each site used in the last sweep (n = V), for checks. */
+/* The random number each site used in the last sweep (n = V), for checks;
+ * SG_EINVAL for SG_PHILOX lattices, whose samples draw 64 numbers per site. */
 int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n);
 
 /* Integer thresholds T[k-1] for dE = 4k, k = 1,2,3 (Sec. 4, EXP4/EXP8/EXP12). */
@@ -158,7 +169,7 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
 
 /* Autotune the fused kernels for n (1 or 2) lattices swept together (n = 2:
  * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
- * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 for SG_MINSTD) and tiles are timed with
+ * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 but for SG_MT19937) and tiles are timed with
  * `reps` launches each on the lattices' own data without changing their state
  * (the launches read the current spins and write only the spare buffer; sweep
  * count and streams do not move), and compared by time per sweep.  The fastest

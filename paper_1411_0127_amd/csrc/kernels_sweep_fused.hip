@@ -52,6 +52,8 @@ struct FusedParams {
     uint32_t a2;         // two sweeps per launch: multiplier of the second sweep
     int nrep;            // two sweeps per launch: replicas, one per workgroup (interleaved items)
     uint32_t mk[2];      // MINSTD key per replica
+    uint64_t pkey[2];    // per-sample numbers (SG_PHILOX): key per replica
+    int64_t t;           // sweep index of the (first) sweep of this launch
     Thresholds T;
 };
 
@@ -130,6 +132,23 @@ __device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Of
     }
 }
 
+// New word of one site: with SG_PHILOX every sample draws its own number, keyed
+// by the site index (plane z, in-plane index xy) and the sweep; otherwise R is the
+// site's number.
+template <int PRNG>
+__device__ __forceinline__ uint64_t site_update(const FusedParams &p, int r, int64_t sweep, uint32_t z, uint32_t xy,
+                                                uint32_t R, uint64_t s, uint64_t nxp, uint64_t nyp, uint64_t nzp,
+                                                uint64_t nxm, uint64_t nym, uint64_t nzm, uint64_t jxp, uint64_t jyp,
+                                                uint64_t jzp, uint64_t jxm, uint64_t jym, uint64_t jzm)
+{
+    if (PRNG == SG_PHILOX) {
+        const uint64_t site = (uint64_t)z * ((uint64_t)p.L * (uint64_t)p.L) + xy;
+        return flip_site_ps(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, site, (uint64_t)sweep,
+                            (uint32_t)p.pkey[r], (uint32_t)(p.pkey[r] >> 32), p.T);
+    }
+    return flip_site(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+}
+
 // Half H of a pair: 0 = even x, 1 = odd x.
 template <int H, int NREP>
 __device__ __forceinline__ uint64_t sp(const Plane<NREP> &d, int r) { return H ? d.shi[r] : d.slo[r]; }
@@ -158,8 +177,8 @@ template <int PRNG, int NREP, int H>
 __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_blue,
                                            bool do_publish, const Plane<NREP> &A, const Plane<NREP> &B,
                                            const Plane<NREP> &C, Carry<NREP> &cy, const uint32_t (&zk)[NREP],
-                                           uint64_t (&rn)[NREP], uint64_t (&wlo)[NREP], uint64_t (&whi)[NREP],
-                                           uint64_t &jxl, uint64_t &jyulo, uint64_t &jyuhi)
+                                           uint32_t zr, uint32_t zb, uint64_t (&rn)[NREP], uint64_t (&wlo)[NREP],
+                                           uint64_t (&whi)[NREP], uint64_t &jxl, uint64_t &jyulo, uint64_t &jyuhi)
 {
     const uint64_t *S = lds + ((k + 2) & 1) * c.set_words;
     const int ixn = H ? c.ixp : c.ixm;  // lane holding the x-neighbour outside the pair
@@ -186,7 +205,8 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t nxm = H ? other : nbx;
             const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, zk[r]))
                                                    : (H ? B.rhi[r] : B.rlo[r]);
-            rn[r] = flip_site(s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r), jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+            rn[r] = site_update<PRNG>(p, r, p.t, zr, c.col + H, R, s, nxp, nyp, sp<H>(C, r), nxm, nym, sp<H>(A, r),
+                                      jxp, jyp, jzp, jxm, jym, jzm);
         }
     }
 
@@ -208,7 +228,8 @@ __device__ __forceinline__ void fused_step(const FusedParams &p, const Lane &c, 
             const uint64_t nxm = H ? cy.rn1[r] : nbx;
             const uint32_t R = (PRNG == SG_MINSTD) ? minstd_jump(p.a, minstd_seed(c.col + H, cy.zk1[r]))
                                                    : (H ? A.rhi[r] : A.rlo[r]);
-            const uint64_t bn = flip_site(s, nxp, nyp, rn[r], nxm, nym, cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+            const uint64_t bn = site_update<PRNG>(p, r, p.t, zb, c.col + H, R, s, nxp, nyp, rn[r], nxm, nym,
+                                                  cy.rn2[r], jxp, jyp, jzp, jxm, jym, jzm);
             wlo[r] = H ? cy.rn1[r] : bn;
             whi[r] = H ? bn : cy.rn1[r];
         }
@@ -350,10 +371,12 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
         uint32_t zk[NREP];                                                                                        \
         _Pragma("unroll") for (int r = 0; r < NREP; ++r) zk[r] = minstd_plane_key((uint32_t)wrap(k), p.mk[r]);   \
         if ((ypar + k + L) & 1)                                                                                   \
-            fused_step<PRNG, NREP, 1>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, rn, wlo, whi, jxl, jyulo, \
+            fused_step<PRNG, NREP, 1>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, (uint32_t)wrap(k),            \
+                                      (uint32_t)wrap(k - 1), rn, wlo, whi, jxl, jyulo,                            \
                                       jyuhi);                                                                     \
         else                                                                                                      \
-            fused_step<PRNG, NREP, 0>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, rn, wlo, whi, jxl, jyulo, \
+            fused_step<PRNG, NREP, 0>(p, c, lds, k, do_blue, do_pub, A, B, C, cy, zk, (uint32_t)wrap(k),            \
+                                      (uint32_t)wrap(k - 1), rn, wlo, whi, jxl, jyulo,                            \
                                       jyuhi);                                                                     \
         {                                                                                                         \
             const int64_t qo = (int64_t)wrap(k - 1) * LL * 8;                                                     \
@@ -453,7 +476,8 @@ __global__ void k_round_reset(int64_t *round_ctr)
 constexpr int kF2OldBlue = 0, kF2Red = 1, kF2Jx = 2, kF2JyLo = 3, kF2JyHi = 4, kF2Blue = 5, kF2Red2 = 6;
 constexpr int kF2Words = 7;  // LDS words per lane and buffer set
 
-// Coupling operands and stream seed of one site update.
+// Coupling operands and stream seed of one site update (MINSTD: the seed;
+// SG_PHILOX: the site's plane, the numbers being keyed by the site).
 struct SiteOps {
     uint64_t jxp, jyp, jzp, jxm, jym, jzm;
     uint32_t seed;
@@ -468,14 +492,15 @@ struct Carry2 {
     SiteOps r1, b1, r2, b2;      // first sweep's red / blue operands of steps k-1, k-2
 };
 
-template <int H>
+template <int PRNG, int H>
 __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_ab,
                                             bool do_br, bool do_bb, bool do_pub, const Plane<1> &A,
                                             const Plane<1> &B, const Plane<1> &C, const Carry2 &cy, uint32_t zk,
-                                            uint32_t zk1, uint64_t &ar0, uint64_t &ab0, uint64_t &br0,
-                                            uint64_t &bb0, SiteOps &r0, SiteOps &b0, uint64_t &jxl,
+                                            uint32_t zk1, uint32_t zr, uint32_t zb, uint64_t &ar0, uint64_t &ab0,
+                                            uint64_t &br0, uint64_t &bb0, SiteOps &r0, SiteOps &b0, uint64_t &jxl,
                                             uint64_t &jyulo, uint64_t &jyuhi)
 {
+    const uint32_t xy = c.col + H;
     const uint64_t *S = lds + ((k + 2) & 1) * c.set_words;
     const int ixn = H ? c.ixp : c.ixm;  // lane holding the x-neighbour outside the pair
     const int nl = c.nl;
@@ -490,14 +515,15 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     r0.jym = H ? jyuhi : jyulo;
     r0.jzp = H ? B.jzhi : B.jzlo;
     r0.jzm = H ? A.jzhi : A.jzlo;
-    r0.seed = minstd_seed(c.col + H, zk);
+    r0.seed = PRNG == SG_PHILOX ? zr : minstd_seed(xy, zk);
     {
         const uint64_t nbx = S[kF2OldBlue * nl + ixn];
         const uint64_t nym = S[kF2OldBlue * nl + c.iym];
         const uint64_t nyp = S[kF2OldBlue * nl + c.iyp];
         const uint64_t s = sp<H>(B, 0), other = sp<1 - H>(B, 0);
-        ar0 = flip_site(s, H ? nbx : other, nyp, sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp,
-                        r0.jzp, r0.jxm, r0.jym, r0.jzm, minstd_jump(p.a, r0.seed), p.T);
+        ar0 = site_update<PRNG>(p, 0, p.t, r0.seed, xy, minstd_jump(p.a, r0.seed), s, H ? nbx : other, nyp,
+                                sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp, r0.jzp, r0.jxm,
+                                r0.jym, r0.jzm);
     }
 
     // ---- first sweep, blue of plane k-1: neighbours are new red ----------------
@@ -507,13 +533,14 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     b0.jym = H ? cy.jyuhi : cy.jyulo;
     b0.jzp = H ? A.jzhi : A.jzlo;
     b0.jzm = H ? cy.jzm2hi : cy.jzm2lo;
-    b0.seed = minstd_seed(c.col + H, zk1);
+    b0.seed = PRNG == SG_PHILOX ? zb : minstd_seed(xy, zk1);
     if (do_ab) {
         const uint64_t nbx = S[kF2Red * nl + ixn];
         const uint64_t nym = S[kF2Red * nl + c.iym];
         const uint64_t nyp = S[kF2Red * nl + c.iyp];
-        ab0 = flip_site(sp<H>(A, 0), H ? nbx : cy.ar1, nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp,
-                        b0.jzp, b0.jxm, b0.jym, b0.jzm, minstd_jump(p.a, b0.seed), p.T);
+        ab0 = site_update<PRNG>(p, 0, p.t, b0.seed, xy, minstd_jump(p.a, b0.seed), sp<H>(A, 0), H ? nbx : cy.ar1,
+                                nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp, b0.jzp, b0.jxm, b0.jym,
+                                b0.jzm);
     }
 
     // ---- second sweep, red of plane k-2: neighbours are the first sweep's blue --
@@ -522,8 +549,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nym = S[kF2Blue * nl + c.iym];
         const uint64_t nyp = S[kF2Blue * nl + c.iyp];
         const SiteOps &o = cy.r2;
-        br0 = flip_site(cy.ar2, H ? nbx : cy.ab1, nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp,
-                        o.jxm, o.jym, o.jzm, minstd_jump(p.a2, o.seed), p.T);
+        br0 = site_update<PRNG>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ar2, H ? nbx : cy.ab1,
+                                nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
     // ---- second sweep, blue of plane k-3: neighbours are its own new red --------
@@ -532,8 +559,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nym = S[kF2Red2 * nl + c.iym];
         const uint64_t nyp = S[kF2Red2 * nl + c.iyp];
         const SiteOps &o = cy.b2;
-        bb0 = flip_site(cy.ab2, H ? nbx : cy.br1, nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp,
-                        o.jxm, o.jym, o.jzm, minstd_jump(p.a2, o.seed), p.T);
+        bb0 = site_update<PRNG>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ab2, H ? nbx : cy.br1,
+                                nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
     // ---- publish for step k+1 ----------------------------------------------------
@@ -556,7 +583,7 @@ constexpr int kRing2 = 4;
 // first step) & 1 is the same for a whole wave; with an even ring the pair half
 // of ring slot i is then (P0 + i) & 1, known at compile time, so the steps of a
 // turn of the ring are straight-line code.
-template <int P0, int... Is>
+template <int PRNG, int P0, int... Is>
 __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, uint64_t *lds, const int z0,
                                            const int ZCe, const Offsets &o, const uint32_t o_st,
                                            const bool second, std::integer_sequence<int, Is...>)
@@ -575,7 +602,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     const int kfirst = z0 - 3;
     const int klast = z0 + ZCe + 2;
     Plane<1> ring[NS];
-    ((load_plane<SG_MINSTD, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
+    ((load_plane<PRNG, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
 
     Carry2 cy;
     cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
@@ -609,8 +636,8 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         const bool do_pub = k < klast;
         const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);
         const uint32_t zk1 = minstd_plane_key((uint32_t)wrap(k - 1), p.mk[0]);
-        fused2_step<H>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, ar0, ab0, br0, bb0, r0, b0,
-                       jxl, jyulo, jyuhi);
+        fused2_step<PRNG, H>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, (uint32_t)wrap(k),
+                             (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
         {
             const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
             const int64_t qo = (int64_t)wrap(k - 3) * LL * 8;
@@ -633,14 +660,14 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         cy.r1 = r0;
         cy.b2 = cy.b1;
         cy.b1 = b0;
-        load_plane<SG_MINSTD, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);
+        load_plane<PRNG, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);
         return ++k <= klast;
     };
     while ((step(IC<Is>{}) && ...)) {
     }
 }
 
-template <int... Is>
+template <int PRNG, int... Is>
 __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
                                              std::integer_sequence<int, Is...> seq)
 {
@@ -651,6 +678,7 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     p.src[0] = pp.src[rep];
     p.dst[0] = pp.dst[rep];
     p.mk[0] = pp.mk[rep];
+    p.pkey[0] = pp.pkey[rep];
 
     Lane c;
     c.nl = p.EX * p.EY + 1;
@@ -707,15 +735,16 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     o.r = kOOB;
     const uint32_t o_st = inter ? col * 8u : kOOB;
     if ((ypar + z0 - 3 + p.L) & 1)
-        fused2_run<1>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 1>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
     else
-        fused2_run<0>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 0>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
 }
 
+template <int PRNG>
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused2_march(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2>{});
+    fused2_march<PRNG>(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2>{});
 }
 
 // Many lattices per launch ("round").  Work items of all lattices are numbered
@@ -761,6 +790,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
     p.nzc = e.nzc;
     p.band = e.band;
     p.nrep = 1;
+    p.t = e.t0 + s0;
+    p.pkey[0] = p.pkey[1] = 0;
     p.a = minstd_power(e.t0 + s0);
     p.T = Thresholds{e.t4, e.t8, e.t12};
     if (deep) {
@@ -770,7 +801,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
         p.WO[0] = e.WO0;
         p.WO[1] = e.WO1;
         p.a2 = minstd_power(e.t0 + s0 + 1);
-        fused2_march(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2>{});
+        fused2_march<SG_MINSTD>(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2>{});
     } else {
         p.EX = e.TXp + 2;
         p.EY = e.TY + 4;
@@ -972,8 +1003,14 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const void *fn = a.nrep == 1 ? (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 1> : (const void *)k_fused<SG_MT19937, 1>)
-                                     : (a.prng == SG_MINSTD ? (const void *)k_fused<SG_MINSTD, 2> : (const void *)k_fused<SG_MT19937, 2>);
+        const void *fn =
+            a.nrep == 1
+                ? (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 1>
+                   : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 1>
+                                          : (const void *)k_fused<SG_MT19937, 1>)
+                : (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 2>
+                   : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 2>
+                                          : (const void *)k_fused<SG_MT19937, 2>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
             per_cu = 1;
         const int P = a.L / 2;
@@ -1001,6 +1038,9 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.a = a.minstd_a;
     p.a2 = a.minstd_a2;
     p.nrep = a.nrep;
+    p.t = a.t;
+    p.pkey[0] = a.pkey[0];
+    p.pkey[1] = a.pkey[1];
     p.T = a.T;
     p.WE = fused_waves_even(tile_x, tile_y);
     p.WO[0] = p.WO[1] = 0;
@@ -1016,11 +1056,15 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     if (a.nrep == 1) {
         if (a.prng == SG_MINSTD)
             hipLaunchKernelGGL((k_fused<SG_MINSTD, 1>), grid, block, lds, s, p);
+        else if (a.prng == SG_PHILOX)
+            hipLaunchKernelGGL((k_fused<SG_PHILOX, 1>), grid, block, lds, s, p);
         else
             hipLaunchKernelGGL((k_fused<SG_MT19937, 1>), grid, block, lds, s, p);
     } else {
         if (a.prng == SG_MINSTD)
             hipLaunchKernelGGL((k_fused<SG_MINSTD, 2>), grid, block, lds, s, p);
+        else if (a.prng == SG_PHILOX)
+            hipLaunchKernelGGL((k_fused<SG_PHILOX, 2>), grid, block, lds, s, p);
         else
             hipLaunchKernelGGL((k_fused<SG_MT19937, 2>), grid, block, lds, s, p);
     }
@@ -1070,8 +1114,9 @@ void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk)
 
 hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)
 {
-    if (a.prng != SG_MINSTD || a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
+    if (a.prng == SG_MT19937 || a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
         return hipErrorInvalidConfiguration;
+    const void *fn = a.prng == SG_PHILOX ? (const void *)k_fused2<SG_PHILOX> : (const void *)k_fused2<SG_MINSTD>;
     const int threads = fused2_threads(tile_x, tile_y);
     const size_t lds = fused2_lds_bytes(tile_x, tile_y);
     const int P = a.L / 2;
@@ -1080,7 +1125,7 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_fused2, threads, lds) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) !=
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -1107,6 +1152,9 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     p.a = a.minstd_a;
     p.a2 = a.minstd_a2;
     p.nrep = a.nrep;
+    p.t = a.t;
+    p.pkey[0] = a.pkey[0];
+    p.pkey[1] = a.pkey[1];
     p.T = a.T;
     const F2Waves fw = fused2_waves(tile_x, tile_y);
     p.WE = fw.outer[0] + fw.inner[0];
@@ -1116,7 +1164,10 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_fused2, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
+    if (a.prng == SG_PHILOX)
+        hipLaunchKernelGGL(k_fused2<SG_PHILOX>, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
+    else
+        hipLaunchKernelGGL(k_fused2<SG_MINSTD>, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
     return hipGetLastError();
 }
 

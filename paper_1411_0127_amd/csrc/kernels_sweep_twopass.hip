@@ -14,7 +14,7 @@ constexpr int kBlock = 256;
 template <int PRNG>
 __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, const uint64_t *__restrict__ J,
                                                     const uint32_t *__restrict__ rnd, uint32_t mk, int L,
-                                                    int colour, uint32_t a, Thresholds T)
+                                                    int colour, uint32_t a, uint64_t pkey, int64_t t, Thresholds T)
 {
     const int64_t LL = (int64_t)L * L;
     const int64_t V = LL * L;
@@ -34,11 +34,18 @@ __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, co
         const int64_t izp = (z + 1 == L) ? i - (V - LL) : i + LL;
         const int64_t izm = (z == 0) ? i + (V - LL) : i - LL;
         const uint64_t s = S[i];
-        const uint32_t R = (PRNG == SG_MINSTD)
-                               ? minstd_jump(a, minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk)))
-                               : rnd[i];
-        S[i] = flip_site(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i], J[ixm],
-                         J[V + iym], J[2 * V + izm], R, T);
+        if (PRNG == SG_PHILOX) {
+            S[i] = flip_site_ps(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i],
+                                J[ixm], J[V + iym], J[2 * V + izm], (uint64_t)i, (uint64_t)t, (uint32_t)pkey,
+                                (uint32_t)(pkey >> 32), T);
+        } else {
+            const uint32_t R =
+                (PRNG == SG_MINSTD)
+                    ? minstd_jump(a, minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk)))
+                    : rnd[i];
+            S[i] = flip_site(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i],
+                             J[ixm], J[V + iym], J[2 * V + izm], R, T);
+        }
     }
 }
 
@@ -56,10 +63,13 @@ hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s)
         for (int colour = 0; colour < 2; ++colour) {
             if (a.prng == SG_MINSTD)
                 hipLaunchKernelGGL(k_twopass<SG_MINSTD>, dim3((unsigned)g), dim3(kBlock), 0, s, a.src[r], a.J,
-                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.T);
-            else
+                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.pkey[r], a.t, a.T);
+            else if (a.prng == SG_MT19937)
                 hipLaunchKernelGGL(k_twopass<SG_MT19937>, dim3((unsigned)g), dim3(kBlock), 0, s, a.src[r], a.J,
-                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.T);
+                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.pkey[r], a.t, a.T);
+            else
+                hipLaunchKernelGGL(k_twopass<SG_PHILOX>, dim3((unsigned)g), dim3(kBlock), 0, s, a.src[r], a.J,
+                                   a.rnd[r], a.mk[r], a.L, colour, a.minstd_a, a.pkey[r], a.t, a.T);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;

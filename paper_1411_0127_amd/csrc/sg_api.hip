@@ -24,7 +24,7 @@ constexpr uint32_t kM31 = 0x7FFFFFFFu;
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 bool valid_L(int L) { return L >= 2 && L <= 2048 && (L % 2) == 0; }
-bool valid_prng(int prng) { return prng == SG_MINSTD || prng == SG_MT19937; }
+bool valid_prng(int prng) { return prng == SG_MINSTD || prng == SG_MT19937 || prng == SG_PHILOX; }
 
 // 16807^(t+1) mod (2^31 - 1) by square and multiply.
 uint32_t minstd_multiplier(int64_t t)
@@ -134,6 +134,7 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     lat->key_minstd = derive_key(spin_seed, kTagMinstd, replica);
     lat->minstd_k = (uint32_t)lat->key_minstd;
     lat->key_mt = derive_key(spin_seed, kTagMt, replica);
+    lat->key_philox = derive_key(spin_seed, kTagPhilox, replica);
     lat->base = static_cast<uint8_t *>(dev_buf);
     lat->bytes = dev_bytes;
     lat->spins[0] = reinterpret_cast<uint64_t *>(lat->base + c.spins0);
@@ -156,7 +157,7 @@ int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
 {
     if (lat->kernel == SG_KERNEL_TWOPASS)
         return 0;
-    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && lat->prng == SG_MINSTD)) {
+    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && lat->prng != SG_MT19937)) {
         if (lat->kernel == SG_KERNEL_FUSED2 && lat->tile_x > 0) {
             tx = lat->tile_x;
             ty = lat->tile_y;
@@ -215,12 +216,14 @@ int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, 
     a.prng = l0->prng;
     a.minstd_a = minstd_multiplier(t);
     a.minstd_a2 = minstd_multiplier(t + 1);
+    a.t = t;
     a.T = T;
     for (int r = 0; r < n; ++r) {
         a.src[r] = lats[r]->spins[lats[r]->cur];
         a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
         a.rnd[r] = lats[r]->rbuf;
         a.mk[r] = lats[r]->minstd_k;
+        a.pkey[r] = lats[r]->key_philox;
     }
     const int band = l0->band > 0 ? l0->band : 1;
     int done = 1;
@@ -588,6 +591,8 @@ int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
         return fail(SG_EINVAL, "n must be L^3");
     if (lat->t == 0)
         return fail(SG_EINVAL, "no sweep done yet");
+    if (lat->prng == SG_PHILOX)
+        return fail(SG_EINVAL, "per-sample numbers: 64 per site, not one");
     hipError_t e;
     if (lat->prng == SG_MT19937) {
         e = hipMemcpyAsync(out, lat->rbuf, 4 * n, hipMemcpyDeviceToHost, lat->stream);
@@ -615,7 +620,7 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
 {
     if (!lat || t < 0)
         return fail(SG_EINVAL, "bad argument");
-    if (lat->prng == SG_MINSTD) {
+    if (lat->prng != SG_MT19937) {  // draws are functions of (site, sweep)
         lat->t = t;
         return SG_OK;
     }
@@ -638,8 +643,8 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
         return fail(SG_EINVAL, "unknown kernel");
     if (band < 0)
         return fail(SG_EINVAL, "band must be >= 0");
-    if (kind == SG_KERNEL_FUSED2 && lat->prng != SG_MINSTD)
-        return fail(SG_EINVAL, "the two-sweep kernel takes MINSTD lattices only");
+    if (kind == SG_KERNEL_FUSED2 && lat->prng == SG_MT19937)
+        return fail(SG_EINVAL, "the two-sweep kernel takes MINSTD and PHILOX lattices");
     if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0)) {
         if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
             return fail(SG_EINVAL, "invalid fused tile shape");
@@ -712,12 +717,14 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         a.prng = l0->prng;
         a.minstd_a = 16807u;
         a.minstd_a2 = 282475249u;
+        a.t = l0->t;
         a.T = Thresholds{T[0], T[1], T[2]};
         for (int r = 0; r < n; ++r) {
             a.src[r] = lats[r]->spins[lats[r]->cur];
             a.dst[r] = lats[r]->spins[1 - lats[r]->cur];
             a.rnd[r] = lats[r]->rbuf;
             a.mk[r] = lats[r]->minstd_k;
+            a.pkey[r] = lats[r]->key_philox;
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -733,7 +740,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         int rc = SG_OK;
         // kind 1: one sweep per launch; kind 2: two (MINSTD); compared per sweep
         for (int kind = 1; kind <= 2 && rc == SG_OK; ++kind) {
-            if (kind == 2 && l0->prng != SG_MINSTD)
+            if (kind == 2 && l0->prng == SG_MT19937)
                 break;
             for (int tx : txs) {
                 if (tx > P)

@@ -19,7 +19,7 @@ namespace sg {
 // include/sg.h.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-constexpr uint32_t kTagJ = 1, kTagSpin = 2, kTagMinstd = 3, kTagMt = 4;
+constexpr uint32_t kTagJ = 1, kTagSpin = 2, kTagMinstd = 3, kTagMt = 4, kTagPhilox = 5;
 
 __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
@@ -105,30 +105,43 @@ __device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, T);
 }
 
-// 32 samples of the update; returns the new spin word.  x[k] = J_k ^ n_k, and the
-// bond bit is b_k = x[k] ^ ~s.  The complement of s is carried through the adder
-// instead of being applied to all six inputs: a three-input sum of (x ^ c) is
-// sum(x) ^ c, a majority of (x ^ c) is maj(x) ^ c, and c cancels in the XOR of two
-// such terms.  v = b0 + ... + b5 = (B1 + B2) + 2 (K1 + K2) with B, K the sums and
-// carries of the two triples.  a4, a8, a12 are all-ones when R < T4, T8, T12; since
-// T12 <= T8 <= T4 they are nested, and the accepted set is
-// v <= 3, or v = 4 with a4, v = 5 with a8, v = 6 with a12.
-__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                              uint32_t x4, uint32_t x5, uint32_t a4, uint32_t a8, uint32_t a12)
+// Bits of the satisfied-bond count v = c2 c1 c0 of 32 samples.  x[k] = J_k ^ n_k,
+// and the bond bit is b_k = x[k] ^ ~s.  The complement of s is carried through
+// the adder instead of being applied to all six inputs: a three-input sum of
+// (x ^ c) is sum(x) ^ c, a majority of (x ^ c) is maj(x) ^ c, and c cancels in
+// the XOR of two such terms.  v = b0 + ... + b5 = (B1 + B2) + 2 (K1 + K2) with B,
+// K the sums and carries of the two triples.
+struct VBits {
+    uint32_t c0, c1, c2;
+};
+__device__ __forceinline__ VBits vcount_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                             uint32_t x4, uint32_t x5)
 {
     const uint32_t s1 = bop3<bop::kXor3>(x0, x1, x2);    // B1 = s1 ^ ~s
     const uint32_t k1 = bop3<bop::kMaj>(x0, x1, x2);     // K1 = k1 ^ ~s
     const uint32_t s2 = bop3<bop::kXor3>(x3, x4, x5);
     const uint32_t k2 = bop3<bop::kMaj>(x3, x4, x5);
-    const uint32_t c0 = s1 ^ s2;                         // bit 0 of v
+    VBits v;
+    v.c0 = s1 ^ s2;                                      // bit 0 of v
     const uint32_t k3 = bop3<bop::kBothEq>(s1, s2, s);   // carry of B1 + B2: B1 & B2, B = (s1 == s)
     const uint32_t t = k1 ^ k2;                          // K1 ^ K2
-    const uint32_t c1 = t ^ k3;                          // bit 1 of v
+    v.c1 = t ^ k3;                                       // bit 1 of v
     const uint32_t kk = bop3<bop::kBothEq>(k1, k2, s);   // K1 & K2, K = (k == s)
-    const uint32_t c2 = bop3<bop::kOrAnd>(kk, k3, t);    // bit 2 of v: majority of K1, K2, k3
-    const uint32_t mid = bop3<bop::kSel>(c0, a8, a4);    // v = 4 or 5: accepted
-    const uint32_t hi = bop3<bop::kSel>(c1, a12, mid);   // v >= 4: accepted (a12 lies in mid)
-    return bop3<bop::kXorOrNot>(s, c2, hi);              // s ^ (v <= 3 or accepted)
+    v.c2 = bop3<bop::kOrAnd>(kk, k3, t);                 // bit 2 of v: majority of K1, K2, k3
+    return v;
+}
+
+// 32 samples of the update with one number for the word; returns the new spin
+// word.  a4, a8, a12 are all-ones when R < T4, T8, T12; since T12 <= T8 <= T4
+// they are nested, and the accepted set is v <= 3, or v = 4 with a4, v = 5 with
+// a8, v = 6 with a12.
+__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                              uint32_t x4, uint32_t x5, uint32_t a4, uint32_t a8, uint32_t a12)
+{
+    const VBits v = vcount_half(s, x0, x1, x2, x3, x4, x5);
+    const uint32_t mid = bop3<bop::kSel>(v.c0, a8, a4);  // v = 4 or 5: accepted
+    const uint32_t hi = bop3<bop::kSel>(v.c1, a12, mid); // v >= 4: accepted (a12 lies in mid)
+    return bop3<bop::kXorOrNot>(s, v.c2, hi);            // s ^ (v <= 3 or accepted)
 }
 
 // New spin word of a 64-sample site: s the spin word, n0..n5 the neighbour words
@@ -152,6 +165,84 @@ __device__ __forceinline__ uint64_t flip_site(uint64_t s, uint64_t n0, uint64_t 
 }
 
 // ---------------------------------------------------------------------------
+// One number per sample (a variant of the acceptance step of Sec. 4: every coded
+// sample draws its own 32-bit number R_j, per site and sweep).  The numbers come
+// from Philox4x32-10 (J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11) in bit-sliced form: plane
+// b (b = 0..31) is a 64-bit word whose bit j is bit 31-b of R_j; planes 2q and
+// 2q+1 are the four outputs (o0 | o1 << 32, o2 | o3 << 32) of Philox at counter
+// (lo32(i), hi32(i) << 8 | q, lo32(t), hi32(t)) under the lattice's 64-bit key,
+// i the site and t the sweep.  R_j < T is then decided from the most significant
+// plane down: a sample is decided at the first plane where its bit differs from
+// T's, so the loop stops as soon as every sample of the word is decided -- the
+// result is the same as comparing the full 32-bit numbers.
+// ---------------------------------------------------------------------------
+struct PhiloxOut {
+    uint32_t o0, o1, o2, o3;
+};
+__device__ __forceinline__ PhiloxOut philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                   uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = bop3<bop::kXor3>((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = bop3<bop::kXor3>((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return PhiloxOut{c0, c1, c2, c3};
+}
+
+// New spin word of a 64-sample site whose samples draw their own numbers:
+// site index i, sweep t, Philox key (k0, k1); T as for MT19937 (range 2^32).
+__device__ __forceinline__ uint64_t flip_site_ps(uint64_t s, uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
+                                                 uint64_t n4, uint64_t n5, uint64_t j0, uint64_t j1, uint64_t j2,
+                                                 uint64_t j3, uint64_t j4, uint64_t j5, uint64_t i, uint64_t t,
+                                                 uint32_t k0, uint32_t k1, const Thresholds &T)
+{
+    const uint64_t x0 = j0 ^ n0, x1 = j1 ^ n1, x2 = j2 ^ n2, x3 = j3 ^ n3, x4 = j4 ^ n4, x5 = j5 ^ n5;
+    const VBits lo = vcount_half((uint32_t)s, (uint32_t)x0, (uint32_t)x1, (uint32_t)x2, (uint32_t)x3, (uint32_t)x4,
+                                 (uint32_t)x5);
+    const VBits hi = vcount_half((uint32_t)(s >> 32), (uint32_t)(x0 >> 32), (uint32_t)(x1 >> 32),
+                                 (uint32_t)(x2 >> 32), (uint32_t)(x3 >> 32), (uint32_t)(x4 >> 32),
+                                 (uint32_t)(x5 >> 32));
+    const uint64_t c0 = lo.c0 | ((uint64_t)hi.c0 << 32);
+    const uint64_t c1 = lo.c1 | ((uint64_t)hi.c1 << 32);
+    const uint64_t c2 = lo.c2 | ((uint64_t)hi.c2 << 32);
+    // samples with v = 4, 5, 6 (v = 7 cannot occur)
+    const uint64_t m4 = c2 & ~(c1 | c0), m5 = c2 & c0, m6 = c2 & c1;
+    // thresholds of 2^32 accept at once, of 0 reject at once; the others compare
+    const uint64_t all4 = T.t4 > 0xFFFFFFFFull ? ~0ull : 0, all8 = T.t8 > 0xFFFFFFFFull ? ~0ull : 0,
+                   all12 = T.t12 > 0xFFFFFFFFull ? ~0ull : 0;
+    const uint64_t cmp4 = (T.t4 - 1) < 0xFFFFFFFFull ? ~0ull : 0, cmp8 = (T.t8 - 1) < 0xFFFFFFFFull ? ~0ull : 0,
+                   cmp12 = (T.t12 - 1) < 0xFFFFFFFFull ? ~0ull : 0;
+    uint64_t acc = (m4 & all4) | (m5 & all8) | (m6 & all12);
+    uint64_t und = (m4 & cmp4) | (m5 & cmp8) | (m6 & cmp12);
+    const uint32_t T4 = (uint32_t)T.t4, T8 = (uint32_t)T.t8, T12 = (uint32_t)T.t12;
+    const uint32_t ilo = (uint32_t)i, ihi = (uint32_t)(i >> 32) << 8, tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+    PhiloxOut o{0, 0, 0, 0};
+    for (int b = 0; b < 32 && und != 0; ++b) {
+        if ((b & 1) == 0)
+            o = philox4x32_10(ilo, ihi | (uint32_t)(b >> 1), tlo, thi, k0, k1);
+        const uint64_t w = (b & 1) ? (o.o2 | ((uint64_t)o.o3 << 32)) : (o.o0 | ((uint64_t)o.o1 << 32));
+        const int sh = 31 - b;
+        const uint64_t tb4 = ((T4 >> sh) & 1u) ? ~0ull : 0, tb8 = ((T8 >> sh) & 1u) ? ~0ull : 0,
+                       tb12 = ((T12 >> sh) & 1u) ? ~0ull : 0;
+        // each undecided sample's threshold bit: T12 for v = 6, T8 for v = 5, T4 for v = 4
+        const uint64_t tb = (c1 & tb12) | (~c1 & ((c0 & tb8) | (~c0 & tb4)));
+        acc |= und & ~w & tb;   // its bit is 0 where T's is 1: R_j < T
+        und &= ~(w ^ tb);       // still equal to T so far
+    }
+    return s ^ (~c2 | acc);
+}
+
+// ---------------------------------------------------------------------------
 // Lattice handle
 // ---------------------------------------------------------------------------
 constexpr int kMtN = 624;
@@ -166,7 +257,7 @@ struct sg_lattice {
     int64_t V = 0;
     uint64_t coupling_seed = 0, spin_seed = 0;
     uint32_t replica = 0;
-    uint64_t key_spin = 0, key_minstd = 0, key_mt = 0, key_j = 0;
+    uint64_t key_spin = 0, key_minstd = 0, key_mt = 0, key_j = 0, key_philox = 0;
     uint32_t minstd_k = 0;  // low 32 bits of key_minstd
     uint8_t *base = nullptr;
     size_t bytes = 0;
@@ -213,6 +304,8 @@ struct SweepArgs {
     int prng;
     uint32_t minstd_a;     // 16807^(t+1) mod (2^31 - 1)
     uint32_t minstd_a2;    // 16807^(t+2) mod (2^31 - 1): second sweep of a two-sweep launch
+    uint64_t pkey[2];      // per replica: key of the per-sample numbers (SG_PHILOX)
+    int64_t t;             // sweep index of the (first) sweep of this launch
     Thresholds T;
 };
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsg.so")
 
 SG_MINSTD = 0
 SG_MT19937 = 1
+SG_PHILOX = 2
 SG_OK = 0
 SG_EINVAL = -1
 SG_ENOMEM = -2
@@ -27,7 +28,8 @@ SG_KERNEL_TWOPASS = 1
 SG_KERNEL_FUSED = 2
 SG_KERNEL_FUSED2 = 3
 
-PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937}
+PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, "philox": SG_PHILOX, SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937,
+         SG_PHILOX: SG_PHILOX}
 KERNELS = {"auto": SG_KERNEL_AUTO, "twopass": SG_KERNEL_TWOPASS, "fused": SG_KERNEL_FUSED, "fused2": SG_KERNEL_FUSED2}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 

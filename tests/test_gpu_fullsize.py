@@ -40,7 +40,13 @@ def window_check(L, prng, cseed, sseed, replica, words, nsweeps, beta, centers):
         J = si.coupling_words_at(L, cseed, gsite)
         # local bond (i, i+d) must be the global bond (g, g+d): identical inside the window
         S0 = si.spin_words_at(L, sseed, replica, gsite)
-        if prng == "minstd":
+        if prng == "philox":
+            key = si.philox_key(sseed, replica)
+            ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.PHILOX, key)
+            for t in range(nsweeps):  # every window site draws the numbers of its global site
+                R = np.stack([oracle.sample_draws(key, int(g), t) for g in gsite], axis=1)  # [64][W^3]
+                ref.sweep_with(R, beta)
+        elif prng == "minstd":
             ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.MINSTD,
                                        si.minstd_seeds_at(L, sseed, replica, gsite))
             ref.sweep(nsweeps, beta)
@@ -88,7 +94,7 @@ def test_L1024_sampled_sites_after_two_sweeps():
     window_check(L, "minstd", 1, 2, 0, words, n, beta, centers_for(L, np.random.default_rng(5), 120, shape[1:3]))
 
 
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "philox"])
 def test_L256_two_replicas_sampled_sites(prng):
     from paper_1411_0127_amd import sg
 

@@ -31,11 +31,19 @@ def sg():
     return mod
 
 
-PRNG = {"minstd": oracle.MINSTD, "mt19937": oracle.MT19937}
+PRNG = {"minstd": oracle.MINSTD, "mt19937": oracle.MT19937, "philox": oracle.PHILOX}
+
+
+def stream_seeds(L, prng, sseed, r):
+    if PRNG[prng] == oracle.MINSTD:
+        return si.minstd_seeds(L, sseed, r)
+    if PRNG[prng] == oracle.MT19937:
+        return si.mt_seeds(L, sseed, r)
+    return si.philox_key(sseed, r)
 
 
 def oracle_for(L, S, prng, cseed, sseed, r=0, J=None, words=None):
-    seeds = si.minstd_seeds(L, sseed, r) if PRNG[prng] == oracle.MINSTD else si.mt_seeds(L, sseed, r)
+    seeds = stream_seeds(L, prng, sseed, r)
     return oracle.OracleLattice((L, L, L), S, si.coupling_words(L, cseed) if J is None else J,
                                 si.spin_words(L, sseed, r) if words is None else words, PRNG[prng], seeds)
 
@@ -238,6 +246,66 @@ def test_two_sweep_kernel_argument_checks(sg):
     lat = sg.Lattice(16, 64, "minstd", coupling_seed=1, spin_seed=2)
     with pytest.raises(sg.SGError):
         lat.set_kernel("fused2", 9, 40, 0)  # more lanes than a workgroup holds
+
+
+# ---------------------------------------------------------------------------
+# one number per sample (SG_PHILOX): every kernel, every sweep split
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [8, 16, 18, 32])
+@pytest.mark.parametrize("kernel", ["fused2", "fused", "twopass", "auto"])
+def test_per_sample_numbers_every_call(sg, L, kernel):
+    say("philox", L, kernel)
+    lat = sg.Lattice(L, 64, "philox", coupling_seed=3, spin_seed=4)
+    lat.set_kernel(kernel)
+    ref = oracle_for(L, 64, "philox", 3, 4)
+    t = 0
+    for n, beta in [(1, 0.9), (2, 0.9), (3, 0.3), (2, 2.0), (1, 1 / 1.1), (2, math.inf), (2, 0.0)]:
+        lat.sweep(n, beta)
+        ref.sweep(n, beta)
+        t += n
+        assert_same(lat.words(), ref, 64, f"L={L} philox {kernel} after {t} sweeps")
+    assert np.array_equal(lat.energy()[0], ref.unsatisfied())
+
+
+@pytest.mark.parametrize("kernel", ["fused2", "fused"])
+def test_per_sample_numbers_two_replicas(sg, kernel):
+    say("philox replicas", kernel)
+    L = 16
+    a = sg.Lattice(L, 64, "philox", coupling_seed=7, spin_seed=100, replica=0)
+    a.set_kernel(kernel)
+    b = sg.Lattice.replica_of(a, spin_seed=100, replica=1)
+    b.set_kernel(kernel)
+    ra = oracle_for(L, 64, "philox", 7, 100, 0)
+    rb = oracle_for(L, 64, "philox", 7, 100, 1)
+    for n in (2, 1, 2):
+        sg.sweep_replicas([a, b], n, 1 / 0.7)
+        ra.sweep(n, 1 / 0.7)
+        rb.sweep(n, 1 / 0.7)
+        assert_same(a.words(), ra, 64, f"replica 0 after {a.t}")
+        assert_same(b.words(), rb, 64, f"replica 1 after {b.t}")
+
+
+def test_per_sample_numbers_split_identical_samples_on_the_gpu(sg):
+    """Identical samples (same couplings, same start) stay identical under one
+    number per site and evolve apart under one number per sample."""
+    say("philox identical samples")
+    L = 16
+    V = L**3
+    rng = np.random.default_rng(3)
+    J = rng.integers(0, 2, size=(3, V)).astype(np.uint64) * np.uint64(0xFFFFFFFFFFFFFFFF)
+    w0 = rng.integers(0, 2, size=V).astype(np.uint64) * np.uint64(0xFFFFFFFFFFFFFFFF)
+    shared = sg.Lattice(L, 64, "minstd", couplings=J, spin_seed=5)
+    own = sg.Lattice(L, 64, "philox", couplings=J, spin_seed=5)
+    shared.set_words(w0)
+    own.set_words(w0)
+    shared.sweep(4, 0.8)
+    own.sweep(4, 0.8)
+    ws = shared.words()
+    assert np.all((ws == 0) | (ws == np.uint64(0xFFFFFFFFFFFFFFFF)))
+    wo = own.words()
+    assert np.mean((wo != 0) & (wo != np.uint64(0xFFFFFFFFFFFFFFFF))) > 0.2
+    with pytest.raises(sg.SGError):
+        own.randoms()  # 64 numbers per site: no single number to return
 
 
 # ---------------------------------------------------------------------------
