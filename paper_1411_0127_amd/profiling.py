@@ -78,6 +78,8 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
 
     sweep_f = pick(f, SWEEP_KERNEL)
     sweep_w = pick(w, SWEEP_KERNEL)
+    names = sorted({k for k in f if SWEEP_KERNEL in k})
+    short = sorted({n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0] for n in names})
     copy_f = max(pick(f, COPY_KERNEL))
     copy_w = max(pick(w, COPY_KERNEL))
     # counters are in KiB; the copy read and wrote copy_bytes each
@@ -86,7 +88,7 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
     fb = statistics.median(sweep_f) * 1024.0 * f_scale
     wb = statistics.median(sweep_w) * 1024.0 * w_scale
     rec = {
-        "kernel": "sg::k_fused",
+        "kernel": ", ".join(short),
         "workload": workload,
         "kernel_source_sha": kernel_source_sha(),
         "fetch_kib_per_launch_raw": statistics.median(sweep_f),
