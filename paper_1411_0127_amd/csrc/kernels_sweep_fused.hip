@@ -414,6 +414,18 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
 // items go to the same XCD when the grid is a multiple of 8.
 __device__ __forceinline__ int xcd_item(int b, int nb) { return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b; }
 
+// Block b -> work item of a batch, whose items differ in length (lattices of
+// different sides): groups of kBatchGroup consecutive items are dealt to the XCDs
+// round robin, so every XCD gets a similar share of long and short items while the
+// items running together on one XCD stay neighbours.  The grid is a multiple of
+// 8 * kBatchGroup; this is a bijection of [0, grid).
+constexpr int kBatchGroup = 32;
+__device__ __forceinline__ int xcd_group_item(int b)
+{
+    const int x = b & 7, k = b >> 3;
+    return ((k / kBatchGroup) * 8 + x) * kBatchGroup + k % kBatchGroup;
+}
+
 template <int PRNG, int NREP>
 __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
 {
@@ -759,7 +771,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
                                                              const int64_t *__restrict__ round_ctr)
 {
     extern __shared__ uint64_t lds[];
-    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int item = xcd_group_item(blockIdx.x);
     if (item >= nitems)
         return;
     const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
@@ -978,7 +990,11 @@ hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int
         return hipSuccess;
     if (lds > (size_t)max_lds_bytes())
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_fused_batch, dim3((unsigned)nitems), dim3(kMaxThreads), lds, s, E, item_lat, nitems, round_ctr);
+    const int64_t per = 8 * kBatchGroup;
+    const int64_t grid = (nitems + per - 1) / per * per;
+    if (grid > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_fused_batch, dim3((unsigned)grid), dim3(kMaxThreads), lds, s, E, item_lat, nitems, round_ctr);
     return hipGetLastError();
 }
 

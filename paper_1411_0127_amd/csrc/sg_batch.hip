@@ -60,8 +60,8 @@ void drop_graph(sg_batch *b)
 }
 
 // Tile of a lattice inside a batch: its chosen (autotuned) tile or the default of
-// its kernel, z chunks of up to 128 planes so that work items of big lattices stay
-// comparable.  Lattices on the automatic or two-sweep kernel get two-sweep rounds
+// its kernel; z chunks of the whole column up to L = 256 and half of it above for
+// the two-sweep march, of up to 128 planes for the one-sweep march.  Lattices on the automatic or two-sweep kernel get two-sweep rounds
 // when the tile allows them.
 int batch_tile(const sg_lattice *lat, BatchEntry &e)
 {
@@ -75,7 +75,11 @@ int batch_tile(const sg_lattice *lat, BatchEntry &e)
     } else {
         fused_default_shape(lat->L, 1, tx, ty, zc);
     }
-    zc = lat->L <= 128 ? lat->L : std::max(64, std::min(128, lat->L / 4));
+    // a chunk of the two-sweep march recomputes six planes, of the one-sweep march two
+    if (want_two && lat->L >= 8 && fused2_shape_ok(lat->L, tx, ty, 0))
+        zc = lat->L <= 256 ? lat->L : lat->L / 2;
+    else
+        zc = lat->L <= 128 ? lat->L : std::max(64, std::min(128, lat->L / 4));
     if (!fill_batch_entry(e, lat->L, tx, ty, zc, lat->band > 0 ? lat->band : 1, want_two))
         return fail(SG_EINVAL, "no fused tile fits a lattice of side " + std::to_string(lat->L));
     return SG_OK;
