@@ -334,6 +334,7 @@ def main():
     V = L**3
     bps = algorithmic_bytes_per_site(wl["prng"], R)
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
+    eq = achieved * main_res["sweeps_per_launch"]
     traffic = load_traffic(args.workload)
     line = {
         "metric": METRIC,
@@ -372,6 +373,11 @@ def main():
             "bytes_per_site": bps,
             "sweeps_per_launch": main_res["sweeps_per_launch"],
             "launch_ms": round(main_res["launch_ms"], 5),
+            # what a one-sweep kernel would have to sustain for the same time per sweep
+            "one_sweep_equivalent": {
+                "achieved": round(eq, 1),
+                "frac": round(eq / HBM_PEAK_GBS, 4),
+            },
         },
     }
     if variants:
