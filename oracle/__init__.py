@@ -14,8 +14,8 @@ What it computes (Lulli, Bernaschi, Parisi, arXiv:1411.0127):
 * asynchronous multispin coding: the samples coded at one site share that site's
   random number (Sec. 4) -- here every sample is simulated on its own, one byte per
   spin, with the shared number;
-* MINSTD and MT19937 generators (Sec. 3), one MINSTD stream per site and one
-  MT19937 stream per x-y column;
+* MINSTD, MT19937 and Parisi-Rapuano generators (Sec. 3), one MINSTD stream per
+  site, one MT19937 or Parisi-Rapuano stream per x-y column;
 * a per-sample variant of the acceptance step: every coded sample draws its own
   32-bit number per site and sweep (Philox4x32-10, Salmon et al., SC'11), instead
   of sharing the site's;
@@ -43,9 +43,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MINSTD = 0
 MT19937 = 1
 PHILOX = 2  # one number per sample, per site and sweep
+PARISI_RAPUANO = 3
 MINSTD_RANGE = 2**31 - 1
 MT19937_RANGE = 2**32
 PHILOX_RANGE = 2**32
+PR_RANGE = 2**32
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -88,6 +90,10 @@ def lib() -> ctypes.CDLL:
         L.oc_run.argtypes = [ci, ci, ci, ci, p, p, ci, p, i64, p, p]
         L.oc_run.restype = ci
         L.oc_philox4x32_10.argtypes = [p, p, p]
+        L.oc_pr_sizeof.restype = i64
+        L.oc_pr_init_many.argtypes = [i64, p, p]
+        L.oc_pr_outputs.argtypes = [p, i64, p]
+        L.oc_pr_draws.argtypes = [ci, ci, ci, p, p]
         L.oc_sample_draws.argtypes = [ctypes.c_uint64, i64, i64, p]
         L.oc_sample_draws_all.argtypes = [i64, ci, ctypes.c_uint64, i64, p]
         _lib = L
@@ -112,6 +118,15 @@ def mt19937_outputs(seed: int, n: int) -> np.ndarray:
     return out
 
 
+def pr_outputs(seed_words, n: int) -> np.ndarray:
+    """First n Parisi-Rapuano numbers from the 61 seed words x_{-61} .. x_{-1}."""
+    seed = np.ascontiguousarray(np.asarray(seed_words, dtype=np.uint32))
+    assert seed.shape == (61,)
+    out = np.empty(n, dtype=np.uint32)
+    lib().oc_pr_outputs(_ptr(seed), n, _ptr(out))
+    return out
+
+
 def philox4x32_10(counter, key) -> np.ndarray:
     """Philox4x32-10 of a 4-word counter under a 2-word key (uint32 words)."""
     c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint32))
@@ -129,7 +144,7 @@ def sample_draws(key: int, site: int, t: int) -> np.ndarray:
 
 
 def thresholds(beta: float, prng: int) -> np.ndarray:
-    rng = MINSTD_RANGE if prng == MINSTD else (MT19937_RANGE if prng == MT19937 else PHILOX_RANGE)
+    rng = MINSTD_RANGE if prng == MINSTD else 2**32
     T = np.zeros(3, dtype=np.uint64)
     lib().oc_thresholds(float(beta), rng, _ptr(T))
     return T
@@ -170,7 +185,8 @@ class OracleLattice:
 
     ``J_words``: uint64 [3][V]; ``spin_words``: uint64 [V];
     ``stream_seeds``: uint32 per-site MINSTD seeds [V], or per-column MT19937
-    seeds [Lx*Ly], or the 64-bit Philox key of the per-sample numbers.  Samples
+    seeds [Lx*Ly], or per-column Parisi-Rapuano seed words [Lx*Ly][61], or the
+    64-bit Philox key of the per-sample numbers.  Samples
     j < S are simulated, each with its own couplings (bit j of every coupling
     word) and the site's shared random number -- or, with PHILOX, its own.
     """
@@ -193,6 +209,11 @@ class OracleLattice:
             assert int(self.state.min()) >= 1 and int(self.state.max()) <= MINSTD_RANGE - 1
         elif self.prng == PHILOX:
             self.state = np.array([int(stream_seeds) & 0xFFFFFFFFFFFFFFFF, 0], dtype=np.uint64)  # key, next sweep
+        elif self.prng == PARISI_RAPUANO:
+            seeds = np.ascontiguousarray(np.asarray(stream_seeds, dtype=np.uint32))
+            assert seeds.shape == (self.Lx * self.Ly, 61)
+            self.state = np.zeros(seeds.shape[0] * int(L.oc_pr_sizeof()), dtype=np.uint8)
+            L.oc_pr_init_many(seeds.shape[0], _ptr(self.state), _ptr(seeds))
         else:
             seeds = np.ascontiguousarray(np.asarray(stream_seeds, dtype=np.uint32))
             assert seeds.shape == (self.Lx * self.Ly,)
@@ -212,6 +233,8 @@ class OracleLattice:
         R = np.empty(self.V, dtype=np.uint32)
         if self.prng == MINSTD:
             lib().oc_minstd_draws(self.V, _ptr(self.state), _ptr(R))
+        elif self.prng == PARISI_RAPUANO:
+            lib().oc_pr_draws(self.Lx, self.Ly, self.Lz, _ptr(self.state), _ptr(R))
         else:
             lib().oc_mt_draws(self.Lx, self.Ly, self.Lz, _ptr(self.state), _ptr(R))
         return R

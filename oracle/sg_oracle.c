@@ -120,6 +120,62 @@ void oc_mt_draws(int Lx, int Ly, int Lz, oc_mt *cols, uint32_t *R)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Parisi-Rapuano (Sec. 3; G. Parisi, F. Rapuano, Phys. Lett. B 157 (1985)     */
+/* 301): a lagged-Fibonacci generator,                                        */
+/*   x_n = x_{n-24} + x_{n-55}  (mod 2^32),   R_n = x_n XOR x_{n-61},          */
+/* started from 61 seed words x_{-61} .. x_{-1}.  The state is a circular     */
+/* buffer of 64 words, x_n at index n mod 64 (61 live words suffice).         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t w[64];
+    int64_t n; /* index of the next number */
+} oc_pr;
+
+int64_t oc_pr_sizeof(void) { return (int64_t)sizeof(oc_pr); }
+
+void oc_pr_init(oc_pr *s, const uint32_t seed[61])
+{
+    memset(s, 0, sizeof(*s));
+    for (int k = 0; k < 61; ++k)
+        s->w[(k - 61 + 64) & 63] = seed[k];
+    s->n = 0;
+}
+
+uint32_t oc_pr_next(oc_pr *s)
+{
+    const int64_t n = s->n;
+    const uint32_t x = s->w[(n - 24) & 63] + s->w[(n - 55) & 63];
+    const uint32_t r = x ^ s->w[(n - 61) & 63];
+    s->w[n & 63] = x;
+    s->n = n + 1;
+    return r;
+}
+
+void oc_pr_init_many(int64_t n, oc_pr *s, const uint32_t *seeds)
+{
+    for (int64_t c = 0; c < n; ++c)
+        oc_pr_init(&s[c], seeds + 61 * c);
+}
+
+void oc_pr_outputs(const uint32_t seed[61], int64_t n, uint32_t *out)
+{
+    oc_pr s;
+    oc_pr_init(&s, seed);
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = oc_pr_next(&s);
+}
+
+/* Column streams as for MT19937: in a sweep the site at height z of column c
+ * takes that column's next number, z = 0 .. Lz-1 in order. */
+void oc_pr_draws(int Lx, int Ly, int Lz, oc_pr *cols, uint32_t *R)
+{
+    const int64_t LL = (int64_t)Lx * Ly;
+    for (int64_t c = 0; c < LL; ++c)
+        for (int z = 0; z < Lz; ++z)
+            R[z * LL + c] = oc_pr_next(&cols[c]);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-sample draws (a variant of Sec. 4 with one random number per coded     */
 /* sample instead of one per site word): Philox4x32-10 (J. K. Salmon, M. A.  */
 /* Moraes, R. O. Dror, D. E. Shaw, "Parallel random numbers: as easy as 1, 2, */
@@ -188,7 +244,8 @@ void oc_sample_draws_all(int64_t V, int S, uint64_t key, int64_t t, uint32_t *R)
 /* accepted when the integer random number R is below R_max * exp(-beta dE),   */
 /* called EXP4, EXP8, EXP12.  Reading: R_max is the size of the generator's    */
 /* output range (2^31 - 1 for MINSTD, whose outputs lie in [1, 2^31 - 2];      */
-/* 2^32 for MT19937 and the per-sample Philox numbers), the product is rounded  */
+/* 2^32 for MT19937, Parisi-Rapuano and the per-sample Philox numbers), the     */
+/* product is rounded  */
 /* up, and the test is strict, so                                             */
 /* R < T holds exactly when R < R_max * p; beta = 0 then accepts every          */
 /* proposal and beta = +inf none.  T[k-1] is the threshold for dE = 4k.        */
@@ -321,7 +378,8 @@ int oc_gibbs(int Lx, int Ly, int Lz, const int8_t *J, double beta, double *meanE
 /* ------------------------------------------------------------------------- */
 /* n sweeps of S samples sharing one stream set (prng 0: per-site MINSTD       */
 /* states, 1: per-column MT19937 states, 2: per-sample Philox numbers with     */
-/* state {key, next sweep index}), thresholds fixed.  Records the             */
+/* state {key, next sweep index}, 3: per-column Parisi-Rapuano states),       */
+/* thresholds fixed.  Records the                                              */
 /* unsatisfied-bond count of every sample after every sweep when U != NULL     */
 /* (U[t*S + j]).  s: S*V bytes; J: S*3V bytes, sample-major.                    */
 /* ------------------------------------------------------------------------- */
@@ -337,6 +395,8 @@ int oc_run(int Lx, int Ly, int Lz, int S, int8_t *s, const int8_t *J, int prng, 
             oc_minstd_draws(V, (uint32_t *)state, R);
         } else if (prng == 1) {
             oc_mt_draws(Lx, Ly, Lz, (oc_mt *)state, R);
+        } else if (prng == 3) {
+            oc_pr_draws(Lx, Ly, Lz, (oc_pr *)state, R);
         } else {
             uint64_t *ks = (uint64_t *)state;
             oc_sample_draws_all(V, S, ks[0], (int64_t)ks[1], R);

@@ -31,7 +31,10 @@ Conventions (this project's, stated once here):
 * MT19937 seed of column c = x + L*y, replica r:
   ``out(key(spin_seed, TAG_MT, r), 1 + c) & 0xffffffff``;
 * key of the per-sample (Philox4x32-10) numbers of replica r:
-  ``key(spin_seed, TAG_PHILOX, r)``.
+  ``key(spin_seed, TAG_PHILOX, r)``;
+* Parisi-Rapuano seed words x_{-61+k}, k = 0..60, of column c, replica r:
+  ``out(key(spin_seed, TAG_PR, r), 1 + 61*c + k) & 0xffffffff``, with the lowest
+  bit of word k = 0 set (an odd word guarantees the generator's full period).
 """
 from __future__ import annotations
 
@@ -46,6 +49,7 @@ TAG_SPIN = 2
 TAG_MINSTD = 3
 TAG_MT = 4
 TAG_PHILOX = 5
+TAG_PR = 6
 
 MINSTD_MODULUS = 2**31 - 1
 
@@ -138,6 +142,21 @@ def mt_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
     k = key(spin_seed, TAG_MT, replica)
     c = np.arange(1, L * L + 1, dtype=np.uint64)
     return (out(k, c) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def pr_seeds_at(L: int, spin_seed: int, replica: int, columns) -> np.ndarray:
+    """uint32 [len(columns)][61] Parisi-Rapuano seed words of the given columns."""
+    k = key(spin_seed, TAG_PR, replica)
+    c = np.asarray(columns, dtype=np.uint64)[:, None]
+    n = np.uint64(1) + np.uint64(61) * c + np.arange(61, dtype=np.uint64)[None, :]
+    w = (out(k, n) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    w[:, 0] |= np.uint32(1)
+    return w
+
+
+def pr_seeds(L: int, spin_seed: int, replica: int) -> np.ndarray:
+    """uint32 [L*L][61] Parisi-Rapuano seed words of every column c = x + L*y."""
+    return pr_seeds_at(L, spin_seed, replica, np.arange(L * L))
 
 
 def philox_key(spin_seed: int, replica: int) -> int:

@@ -512,3 +512,77 @@ def test_per_sample_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
         m2, err2 = _binned_mean_err(E[:, j] ** 2)
         err2 = max(err2, math.sqrt(max(var2, 0.0) / n))
         assert abs(m2 - e2) < 5 * err2, (j, m2, e2, err2)
+
+
+# ---------------------------------------------------------------------------
+# Parisi-Rapuano (Sec. 3).  No independent implementation or published values of
+# its 32-bit words are at hand ("parity unpinned" for the full words): the pins are
+# the linear recurrence of the lowest bit, which follows from addition mod 2 (a
+# wrong lag breaks it), uniformity, and the Gibbs law of the dynamics it drives.
+# ---------------------------------------------------------------------------
+def test_parisi_rapuano_lowest_bit_obeys_the_lagged_xor_recurrence():
+    seeds = si.pr_seeds(4, 11, 0)
+    for c in (0, 5, 15):
+        R = oracle.pr_outputs(seeds[c], 20000)
+        b = (R & np.uint32(1)).astype(np.uint8)
+        n = np.arange(116, b.size)
+        assert np.array_equal(b[n], b[n - 24] ^ b[n - 55])
+        # the neighbouring lags do not hold
+        assert not np.array_equal(b[n], b[n - 23] ^ b[n - 55])
+        assert not np.array_equal(b[n], b[n - 24] ^ b[n - 54])
+
+
+def test_parisi_rapuano_outputs_are_uniform_and_streams_differ():
+    seeds = si.pr_seeds(8, 3, 0)
+    R = np.stack([oracle.pr_outputs(seeds[c], 4000) for c in range(16)])
+    h = np.bincount((R >> np.uint32(28)).ravel(), minlength=16)
+    e = R.size / 16
+    chi2 = float(((h - e) ** 2 / e).sum())
+    assert chi2 < 45.0, chi2
+    bits = ((R[..., None] >> np.arange(32, dtype=np.uint32)) & np.uint32(1)).mean(axis=(0, 1))
+    assert np.all(np.abs(bits - 0.5) < 0.02)
+    assert (R[1:] != R[:-1]).mean() > 0.999  # columns draw different numbers
+    # lag-1 serial correlation of the normalised numbers
+    u = R.astype(np.float64) / 2**32
+    corr = float(np.mean((u[:, 1:] - 0.5) * (u[:, :-1] - 0.5)) / np.var(u))
+    assert abs(corr) < 0.02
+
+
+def test_parisi_rapuano_column_streams_in_sweep_order():
+    """Site (x, y, z) takes number t*L + z of column x + L*y in sweep t."""
+    L = 4
+    seeds = si.pr_seeds(L, 7, 1)
+    rng = np.random.default_rng(1)
+    Jw = rng.integers(0, 2**63, size=(3, L**3), dtype=np.uint64)
+    Sw = rng.integers(0, 2**63, size=L**3, dtype=np.uint64)
+    lat = oracle.OracleLattice((L, L, L), 1, Jw, Sw, oracle.PARISI_RAPUANO, seeds)
+    got = np.stack([lat.draws() for _ in range(3)])  # [t][V]
+    for c in (0, 3, 9, 15):
+        want = oracle.pr_outputs(seeds[c], 3 * L).reshape(3, L)
+        assert np.array_equal(got[:, c::L * L], want)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1 / 0.7])
+def test_parisi_rapuano_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
+    ext = (2, 2, 4)
+    V = 16
+    S = 6
+    rng = np.random.default_rng(2026)
+    Jw = rng.integers(0, 2**63, size=(3, V), dtype=np.uint64)
+    Sw = rng.integers(0, 2**63, size=V, dtype=np.uint64)
+    lat = oracle.OracleLattice(ext, S, Jw, Sw, oracle.PARISI_RAPUANO, si.pr_seeds(2, 4, 0))
+    lat.run(2000, beta)
+    U = lat.run(60000, beta, record=True)
+    E = 2.0 * U - 3.0 * V
+    n = E.shape[0]
+    for j in range(S):
+        e1, e2, hist = oracle.gibbs(ext, lat.J[j], beta)
+        var1 = e2 - e1 * e1
+        Eu = 2.0 * np.arange(3 * V + 1) - 3.0 * V
+        var2 = float((hist * Eu**4).sum()) - e2 * e2
+        m, err = _binned_mean_err(E[:, j])
+        err = max(err, math.sqrt(max(var1, 0.0) / n))
+        assert abs(m - e1) < 5 * err, (j, m, e1, err)
+        m2, err2 = _binned_mean_err(E[:, j] ** 2)
+        err2 = max(err2, math.sqrt(max(var2, 0.0) / n))
+        assert abs(m2 - e2) < 5 * err2, (j, m2, e2, err2)
