@@ -27,10 +27,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # L=256 cube, 64 samples per word, 2 replicas sharing the couplings, T=0.7
-    "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=("mt19937", "philox"),
+    "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd",
+               variant=("mt19937", "parisi_rapuano", "philox"),
                desc="L=256 periodic cube, 64 samples multispin-coded per uint64, 2 replicas sharing "
                     "J=+-1 (p=1/2), random start, T=0.7, 1000 sweeps per step, MINSTD per-site streams "
-                    "(variants: MT19937 per-column streams; one Philox number per sample)"),
+                    "(variants: MT19937 and Parisi-Rapuano per-column streams; one Philox number per sample)"),
     # L=1024 cube, 64 samples, one replica, T=1.1, 100 sweeps
     "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd", variant=None,
                desc="L=1024 periodic cube, 64 samples multispin-coded per uint64, J=+-1 (p=1/2), "
@@ -56,12 +57,12 @@ def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
 
     Couplings: 3 words read once for all replicas (24 B).  Per replica: the spin
     word read and written (16 B); with MT19937 also the draw read from the
-    buffer the fill kernel wrote (4 B).  MINSTD draws are computed from the site
+    buffer the fill kernel wrote (4 B), as with Parisi-Rapuano.  MINSTD draws are computed from the site
     and the sweep, nothing is read for them.  The MT19937 fill kernel's own state
     traffic is not part of the sweep kernel.  A two-sweep launch must move the
     same bytes: it reads and writes every word once for both sweeps.
     """
-    return 24 + replicas * (16 + (4 if prng == "mt19937" else 0))
+    return 24 + replicas * (16 + (4 if prng in ("mt19937", "parisi_rapuano") else 0))
 
 
 def kernel_source_sha() -> str:
@@ -103,7 +104,7 @@ def run_gpu(args, wl):
             parts = args.tile.split(",")
             kind = parts[0] if not parts[0].isdigit() else "fused"
             nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
-            if kind == "fused2" and prng == "mt19937":
+            if kind == "fused2" and prng in ("mt19937", "parisi_rapuano"):
                 kind = "fused"  # the two-sweep kernel takes MINSTD and Philox lattices
             shape = (kind,) + nums
             for l in lats:
@@ -117,7 +118,7 @@ def run_gpu(args, wl):
             for l in lats:
                 l.set_kernel(args.kernel)
         kind = shape[0] if shape else args.kernel
-        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng != "mt19937")) and nsw % 2 == 0 else 1
+        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng in ("minstd", "philox"))) and nsw % 2 == 0 else 1
 
         def step(ev=None):
             if ev is not None:

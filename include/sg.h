@@ -30,6 +30,11 @@
  *   SG_MT19937 one MT19937 stream per x-y column and replica, seeded with
  *              init_genrand; in sweep t the site at height z draws the column's
  *              output number t*L + z;
+ *   SG_PARISI_RAPUANO  one Parisi-Rapuano stream per x-y column and replica
+ *              (Sec. 3): x_n = x_{n-24} + x_{n-55} mod 2^32, R_n = x_n ^ x_{n-61},
+ *              started from 61 seed words x_{-61+k} = lo32(out(key, 1 + 61c + k)),
+ *              k = 0..60, the first made odd; the site at height z draws the
+ *              column's number t*L + z in sweep t;
  *   SG_PHILOX  one number per coded sample instead of one per site word (a
  *              variant of Sec. 4's asynchronous coding): sample j of site i
  *              draws a 32-bit R_j in sweep t from Philox4x32-10 (Salmon et al.,
@@ -45,7 +50,7 @@
  *
  * Acceptance: a proposal with dE > 0 is accepted iff R < T(dE) with
  * T(dE) = ceil(R_range * exp(-beta * dE)), R_range = 2^31 - 1 (MINSTD) or 2^32
- * (MT19937, PHILOX); dE <= 0 is always accepted (Sec. 4, P_flip and
+ * (MT19937, PARISI_RAPUANO, PHILOX); dE <= 0 is always accepted (Sec. 4, P_flip and
  * EXP4/EXP8/EXP12).
  *
  * Conventions of every entry point:
@@ -72,7 +77,7 @@ extern "C" {
 
 typedef struct sg_lattice sg_lattice;
 
-enum { SG_MINSTD = 0, SG_MT19937 = 1, SG_PHILOX = 2 };
+enum { SG_MINSTD = 0, SG_MT19937 = 1, SG_PHILOX = 2, SG_PARISI_RAPUANO = 3 };
 
 enum {
     SG_OK = 0,

@@ -4,7 +4,10 @@
 //  - MT19937 (Matsumoto-Nishimura 1998) per-column streams: init_genrand, and a
 //    per-sweep fill of the L draws every column needs (Sec. 3 of the paper: a
 //    per-stream MT19937 whose state is laid out so that consecutive streams are
-//    consecutive in memory, word k of stream c at k*ncols + c).
+//    consecutive in memory, word k of stream c at k*ncols + c);
+//  - Parisi-Rapuano per-column streams (Sec. 3): x_n = x_{n-24} + x_{n-55} mod
+//    2^32, R_n = x_n ^ x_{n-61}, state x_n at word n mod 64 in the same strided
+//    layout; the per-sweep fill keeps each column's 64 words in LDS.
 #include "sg_internal.h"
 
 namespace sg {
@@ -121,6 +124,56 @@ __global__ __launch_bounds__(256) void k_mt_fill(MtFillArgs a, int L, int64_t t)
     }
 }
 
+// Parisi-Rapuano seed words x_{-61+k} = lo32(out(key, 1 + 61 c + k)), k = 0..60,
+// word k = 0 made odd (a full-period start needs one odd word); x_n lives at word
+// n mod 64, so the seeds go to words 3..63.
+__global__ void k_init_pr(uint32_t *__restrict__ st, int ncols, uint64_t key)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols)
+        return;
+    for (int k = 0; k < 3; ++k)
+        st[(size_t)k * ncols + c] = 0u;
+    for (int k = 0; k < 61; ++k) {
+        uint32_t w = (uint32_t)sm_out(key, 1ull + 61ull * (uint64_t)c + (uint64_t)k);
+        if (k == 0)
+            w |= 1u;
+        st[(size_t)(k + 3) * ncols + c] = w;
+    }
+}
+
+// The L numbers of sweep t (numbers t*L .. t*L + L-1) of every column, for up to
+// two stream sets (blockIdx.y).  A thread owns one column; its 64 state words sit
+// in LDS at word k * kPrBlock + thread (no bank conflicts) while it steps the
+// recurrence, and go back to HBM at the end.
+constexpr int kPrBlock = 128;
+struct PrFillArgs {
+    uint32_t *st[2];
+    uint32_t *R[2];
+};
+__global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64_t t)
+{
+    __shared__ uint32_t buf[64 * kPrBlock];
+    const int ncols = L * L;
+    const int c = blockIdx.x * kPrBlock + threadIdx.x;
+    if (c >= ncols)
+        return;
+    uint32_t *__restrict__ st = a.st[blockIdx.y];
+    uint32_t *__restrict__ R = a.R[blockIdx.y];
+    uint32_t *b = buf + threadIdx.x;
+    for (int k = 0; k < 64; ++k)
+        b[k * kPrBlock] = st[(size_t)k * ncols + c];
+    const int64_t n0 = t * (int64_t)L;
+    for (int z = 0; z < L; ++z) {
+        const int n = (int)((n0 + z) & 63);
+        const uint32_t x = b[((n - 24) & 63) * kPrBlock] + b[((n - 55) & 63) * kPrBlock];
+        R[(size_t)z * ncols + c] = x ^ b[((n - 61) & 63) * kPrBlock];
+        b[n * kPrBlock] = x;
+    }
+    for (int k = 0; k < 64; ++k)
+        st[(size_t)k * ncols + c] = b[k * kPrBlock];
+}
+
 }  // namespace
 
 hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s)
@@ -141,6 +194,25 @@ hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s)
 {
     const int ncols = L * L;
     hipLaunchKernelGGL(k_init_mt, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s, state, ncols, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pr(uint32_t *state, int L, uint64_t key, hipStream_t s)
+{
+    const int ncols = L * L;
+    hipLaunchKernelGGL(k_init_pr, dim3((ncols + kBlock - 1) / kBlock), dim3(kBlock), 0, s, state, ncols, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s)
+{
+    const int ncols = L * L;
+    PrFillArgs a{};
+    for (int r = 0; r < n && r < 2; ++r) {
+        a.st[r] = state[r];
+        a.R[r] = rbuf[r];
+    }
+    hipLaunchKernelGGL(k_pr_fill, dim3((ncols + kPrBlock - 1) / kPrBlock, n), dim3(kPrBlock), 0, s, a, L, t);
     return hipGetLastError();
 }
 

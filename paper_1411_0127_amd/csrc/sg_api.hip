@@ -24,7 +24,10 @@ constexpr uint32_t kM31 = 0x7FFFFFFFu;
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 bool valid_L(int L) { return L >= 2 && L <= 2048 && (L % 2) == 0; }
-bool valid_prng(int prng) { return prng == SG_MINSTD || prng == SG_MT19937 || prng == SG_PHILOX; }
+bool valid_prng(int prng)
+{
+    return prng == SG_MINSTD || prng == SG_MT19937 || prng == SG_PHILOX || prng == SG_PARISI_RAPUANO;
+}
 
 // 16807^(t+1) mod (2^31 - 1) by square and multiply.
 uint32_t minstd_multiplier(int64_t t)
@@ -79,8 +82,10 @@ Carve carve(int L, int prng, bool own_J)
     c.mt_state = off;
     if (prng == SG_MT19937)
         off = align_up(off + (size_t)4 * kMtN * L * L);
+    if (prng == SG_PARISI_RAPUANO)
+        off = align_up(off + (size_t)4 * 64 * L * L);
     c.rbuf = off;
-    if (prng == SG_MT19937)
+    if (buffered_draws(prng))
         off = align_up(off + 4 * V);
     c.scratch = off;
     off = align_up(off + 8 * ((size_t)kMaxReduceBlocks * 64 + 64));
@@ -108,11 +113,12 @@ int init_streams(sg_lattice *lat)
     hipError_t e = launch_init_spins(lat->spins[0], lat->L, lat->key_spin, lat->stream);
     if (e != hipSuccess)
         return hip_fail(e, "init spins");
-    if (lat->prng == SG_MT19937) {
+    if (lat->prng == SG_MT19937)
         e = launch_init_mt(lat->mt_state, lat->L, lat->key_mt, lat->stream);
-        if (e != hipSuccess)
-            return hip_fail(e, "init streams");
-    }
+    else if (lat->prng == SG_PARISI_RAPUANO)
+        e = launch_init_pr(lat->mt_state, lat->L, lat->key_pr, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init streams");
     return SG_OK;
 }
 
@@ -135,14 +141,15 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     lat->minstd_k = (uint32_t)lat->key_minstd;
     lat->key_mt = derive_key(spin_seed, kTagMt, replica);
     lat->key_philox = derive_key(spin_seed, kTagPhilox, replica);
+    lat->key_pr = derive_key(spin_seed, kTagPr, replica);
     lat->base = static_cast<uint8_t *>(dev_buf);
     lat->bytes = dev_bytes;
     lat->spins[0] = reinterpret_cast<uint64_t *>(lat->base + c.spins0);
     lat->spins[1] = reinterpret_cast<uint64_t *>(lat->base + c.spins1);
     if (own_J)
         lat->J = reinterpret_cast<uint64_t *>(lat->base + c.J);
-    lat->mt_state = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.mt_state) : nullptr;
-    lat->rbuf = prng == SG_MT19937 ? reinterpret_cast<uint32_t *>(lat->base + c.rbuf) : nullptr;
+    lat->mt_state = buffered_draws(prng) ? reinterpret_cast<uint32_t *>(lat->base + c.mt_state) : nullptr;
+    lat->rbuf = buffered_draws(prng) ? reinterpret_cast<uint32_t *>(lat->base + c.rbuf) : nullptr;
     lat->scratch = reinterpret_cast<uint64_t *>(lat->base + c.scratch);
     lat->stream = static_cast<hipStream_t>(stream);
     lat->cur = 0;
@@ -157,7 +164,7 @@ int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
 {
     if (lat->kernel == SG_KERNEL_TWOPASS)
         return 0;
-    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && lat->prng != SG_MT19937)) {
+    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && !buffered_draws(lat->prng))) {
         if (lat->kernel == SG_KERNEL_FUSED2 && lat->tile_x > 0) {
             tx = lat->tile_x;
             ty = lat->tile_y;
@@ -199,21 +206,23 @@ int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, 
     sg_lattice *l0 = lats[0];
     const int64_t t = l0->t;
     hipError_t e;
-    if (l0->prng == SG_MT19937) {
+    if (buffered_draws(l0->prng)) {
         uint32_t *st[2], *rb[2];
         for (int r = 0; r < n; ++r) {
             st[r] = lats[r]->mt_state;
             rb[r] = lats[r]->rbuf;
         }
-        e = launch_mt_fill(st, rb, n, l0->L, t, l0->stream);
+        e = l0->prng == SG_MT19937 ? launch_mt_fill(st, rb, n, l0->L, t, l0->stream)
+                                   : launch_pr_fill(st, rb, n, l0->L, t, l0->stream);
         if (e != hipSuccess)
-            return hip_fail(e, "MT19937 fill");
+            return hip_fail(e, "stream fill");
     }
     SweepArgs a{};
     a.J = l0->J;
     a.nrep = n;
     a.L = l0->L;
-    a.prng = l0->prng;
+    // the sweep kernels read buffered numbers the same way for both generators
+    a.prng = buffered_draws(l0->prng) ? SG_MT19937 : l0->prng;
     a.minstd_a = minstd_multiplier(t);
     a.minstd_a2 = minstd_multiplier(t + 1);
     a.t = t;
@@ -594,7 +603,7 @@ int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
     if (lat->prng == SG_PHILOX)
         return fail(SG_EINVAL, "per-sample numbers: 64 per site, not one");
     hipError_t e;
-    if (lat->prng == SG_MT19937) {
+    if (buffered_draws(lat->prng)) {
         e = hipMemcpyAsync(out, lat->rbuf, 4 * n, hipMemcpyDeviceToHost, lat->stream);
     } else {
         // MINSTD draws are a function of (site, sweep): evaluate the last sweep's on
@@ -620,16 +629,17 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
 {
     if (!lat || t < 0)
         return fail(SG_EINVAL, "bad argument");
-    if (lat->prng != SG_MT19937) {  // draws are functions of (site, sweep)
+    if (!buffered_draws(lat->prng)) {  // draws are functions of (site, sweep)
         lat->t = t;
         return SG_OK;
     }
     if (t < lat->t || lat->t != 0)
-        return fail(SG_EINVAL, "an MT19937 lattice can only be moved forward before its first sweep");
+        return fail(SG_EINVAL, "a lattice with stream states can only be moved forward before its first sweep");
     for (int64_t k = 0; k < t; ++k) {
-        hipError_t e = launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream);
+        hipError_t e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream)
+                                               : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream);
         if (e != hipSuccess)
-            return hip_fail(e, "MT19937 fill");
+            return hip_fail(e, "stream fill");
     }
     lat->t = t;
     return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
@@ -643,7 +653,7 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
         return fail(SG_EINVAL, "unknown kernel");
     if (band < 0)
         return fail(SG_EINVAL, "band must be >= 0");
-    if (kind == SG_KERNEL_FUSED2 && lat->prng == SG_MT19937)
+    if (kind == SG_KERNEL_FUSED2 && buffered_draws(lat->prng))
         return fail(SG_EINVAL, "the two-sweep kernel takes MINSTD and PHILOX lattices");
     if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0)) {
         if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
@@ -714,7 +724,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         a.J = l0->J;
         a.nrep = n;
         a.L = l0->L;
-        a.prng = l0->prng;
+        a.prng = buffered_draws(l0->prng) ? SG_MT19937 : l0->prng;
         a.minstd_a = 16807u;
         a.minstd_a2 = 282475249u;
         a.t = l0->t;
@@ -740,7 +750,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         int rc = SG_OK;
         // kind 1: one sweep per launch; kind 2: two (MINSTD); compared per sweep
         for (int kind = 1; kind <= 2 && rc == SG_OK; ++kind) {
-            if (kind == 2 && l0->prng == SG_MT19937)
+            if (kind == 2 && buffered_draws(l0->prng))
                 break;
             for (int tx : txs) {
                 if (tx > P)

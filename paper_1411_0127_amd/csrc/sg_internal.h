@@ -19,7 +19,7 @@ namespace sg {
 // include/sg.h.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-constexpr uint32_t kTagJ = 1, kTagSpin = 2, kTagMinstd = 3, kTagMt = 4, kTagPhilox = 5;
+constexpr uint32_t kTagJ = 1, kTagSpin = 2, kTagMinstd = 3, kTagMt = 4, kTagPhilox = 5, kTagPr = 6;
 
 __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
@@ -257,7 +257,7 @@ struct sg_lattice {
     int64_t V = 0;
     uint64_t coupling_seed = 0, spin_seed = 0;
     uint32_t replica = 0;
-    uint64_t key_spin = 0, key_minstd = 0, key_mt = 0, key_j = 0, key_philox = 0;
+    uint64_t key_spin = 0, key_minstd = 0, key_mt = 0, key_j = 0, key_philox = 0, key_pr = 0;
     uint32_t minstd_k = 0;  // low 32 bits of key_minstd
     uint8_t *base = nullptr;
     size_t bytes = 0;
@@ -265,8 +265,8 @@ struct sg_lattice {
     int cur = 0;  // spins[cur] holds the current configuration
     uint64_t *J = nullptr;
     const sg_lattice *J_owner = nullptr;  // nullptr: this lattice owns J
-    uint32_t *mt_state = nullptr;         // MT19937 state, word k of column c at k*L*L + c
-    uint32_t *rbuf = nullptr;             // MT19937 draws of the sweep being done [V]
+    uint32_t *mt_state = nullptr;         // MT19937 (624 words) or Parisi-Rapuano (64) state, word k of column c at k*L*L + c
+    uint32_t *rbuf = nullptr;             // MT19937 / Parisi-Rapuano draws of the sweep being done [V]
     uint64_t *scratch = nullptr;          // reduction partials
     hipStream_t stream = nullptr;
     int64_t t = 0;  // sweeps done
@@ -292,6 +292,10 @@ hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s);
 // Draws of sweep t for n (1 or 2) stream sets of side L.
 hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
+hipError_t launch_init_pr(uint32_t *state, int L, uint64_t key, hipStream_t s);
+hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
+// Generators whose numbers are read from a per-sweep buffer filled beforehand.
+inline bool buffered_draws(int prng) { return prng == SG_MT19937 || prng == SG_PARISI_RAPUANO; }
 
 struct SweepArgs {
     const uint64_t *J;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsg.so")
 SG_MINSTD = 0
 SG_MT19937 = 1
 SG_PHILOX = 2
+SG_PARISI_RAPUANO = 3
 SG_OK = 0
 SG_EINVAL = -1
 SG_ENOMEM = -2
@@ -28,8 +29,8 @@ SG_KERNEL_TWOPASS = 1
 SG_KERNEL_FUSED = 2
 SG_KERNEL_FUSED2 = 3
 
-PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, "philox": SG_PHILOX, SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937,
-         SG_PHILOX: SG_PHILOX}
+PRNGS = {"minstd": SG_MINSTD, "mt19937": SG_MT19937, "philox": SG_PHILOX, "parisi_rapuano": SG_PARISI_RAPUANO,
+         SG_MINSTD: SG_MINSTD, SG_MT19937: SG_MT19937, SG_PHILOX: SG_PHILOX, SG_PARISI_RAPUANO: SG_PARISI_RAPUANO}
 KERNELS = {"auto": SG_KERNEL_AUTO, "twopass": SG_KERNEL_TWOPASS, "fused": SG_KERNEL_FUSED, "fused2": SG_KERNEL_FUSED2}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 

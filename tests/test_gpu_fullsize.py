@@ -46,6 +46,15 @@ def window_check(L, prng, cseed, sseed, replica, words, nsweeps, beta, centers):
             for t in range(nsweeps):  # every window site draws the numbers of its global site
                 R = np.stack([oracle.sample_draws(key, int(g), t) for g in gsite], axis=1)  # [64][W^3]
                 ref.sweep_with(R, beta)
+        elif prng == "parisi_rapuano":
+            cols = (gx + L * gy).reshape(W, W, W)[0].ravel()
+            seeds = si.pr_seeds_at(L, sseed, replica, cols)
+            outs = np.stack([oracle.pr_outputs(s_, nsweeps * L) for s_ in seeds])
+            ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.PARISI_RAPUANO, seeds)
+            zg = gz.reshape(W, W, W)
+            for t in range(nsweeps):
+                R = outs[np.tile(np.arange(W * W), W), (t * L + zg.ravel())].astype(np.uint32)
+                ref.sweep_with(R, beta)
         elif prng == "minstd":
             ref = oracle.OracleLattice((W, W, W), 64, J, S0, oracle.MINSTD,
                                        si.minstd_seeds_at(L, sseed, replica, gsite))
@@ -94,7 +103,7 @@ def test_L1024_sampled_sites_after_two_sweeps():
     window_check(L, "minstd", 1, 2, 0, words, n, beta, centers_for(L, np.random.default_rng(5), 120, shape[1:3]))
 
 
-@pytest.mark.parametrize("prng", ["minstd", "mt19937", "philox"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "philox", "parisi_rapuano"])
 def test_L256_two_replicas_sampled_sites(prng):
     from paper_1411_0127_amd import sg
 

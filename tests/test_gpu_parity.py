@@ -31,7 +31,8 @@ def sg():
     return mod
 
 
-PRNG = {"minstd": oracle.MINSTD, "mt19937": oracle.MT19937, "philox": oracle.PHILOX}
+PRNG = {"minstd": oracle.MINSTD, "mt19937": oracle.MT19937, "philox": oracle.PHILOX,
+        "parisi_rapuano": oracle.PARISI_RAPUANO}
 
 
 def stream_seeds(L, prng, sseed, r):
@@ -39,6 +40,8 @@ def stream_seeds(L, prng, sseed, r):
         return si.minstd_seeds(L, sseed, r)
     if PRNG[prng] == oracle.MT19937:
         return si.mt_seeds(L, sseed, r)
+    if PRNG[prng] == oracle.PARISI_RAPUANO:
+        return si.pr_seeds(L, sseed, r)
     return si.philox_key(sseed, r)
 
 
@@ -116,7 +119,7 @@ def test_single_sample_L16_1000_sweeps_every_sweep(sg, kernel):
 # 64 samples, both kernels, both generators, every sweep
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [2, 4, 8, 16, 18, 32])
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "parisi_rapuano"])
 @pytest.mark.parametrize("kernel", ["fused", "twopass"])
 def test_64_samples_every_sweep(sg, L, prng, kernel):
     say("64 samples", L, prng, kernel)
@@ -134,7 +137,7 @@ def test_64_samples_every_sweep(sg, L, prng, kernel):
     (24, (12, 24, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 20, 11)), (34, (17, 21, 34)),
     (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)),
 ])
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "parisi_rapuano"])
 def test_fused_tile_shapes_and_ragged_edges(sg, L, tiles, prng):
     say("tiles", L, tiles, prng)
     lat = sg.Lattice(L, 64, prng, coupling_seed=8, spin_seed=21)
@@ -249,6 +252,34 @@ def test_two_sweep_kernel_argument_checks(sg):
 
 
 # ---------------------------------------------------------------------------
+# Parisi-Rapuano column streams: the device's numbers and a resumed lattice
+# ---------------------------------------------------------------------------
+def test_parisi_rapuano_device_numbers_and_forward_moves(sg):
+    say("parisi-rapuano numbers")
+    L = 18
+    lat = sg.Lattice(L, 64, "parisi_rapuano", coupling_seed=2, spin_seed=3)
+    seeds = si.pr_seeds(L, 3, 0)
+    for t in range(4):
+        lat.sweep(1, 0.9)
+        got = lat.randoms()
+        for c in (0, 1, 17, 100, L * L - 1):
+            want = oracle.pr_outputs(seeds[c], (t + 1) * L)[t * L:]
+            assert np.array_equal(got[c::L * L], want), (t, c)
+    a = sg.Lattice(L, 64, "parisi_rapuano", coupling_seed=2, spin_seed=3)
+    a.sweep(5, 0.9)
+    b = sg.Lattice(L, 64, "parisi_rapuano", coupling_seed=2, spin_seed=3)
+    b.sweep(2, 0.9)
+    w = b.words()
+    c = sg.Lattice(L, 64, "parisi_rapuano", coupling_seed=2, spin_seed=3)
+    c.set_sweep_count(2)  # regenerates the column streams forward
+    c.set_words(w)
+    c.sweep(3, 0.9)
+    assert np.array_equal(c.words(), a.words())
+    with pytest.raises(sg.SGError):
+        c.set_kernel("fused2")
+
+
+# ---------------------------------------------------------------------------
 # one number per sample (SG_PHILOX): every kernel, every sweep split
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [8, 16, 18, 32])
@@ -312,7 +343,7 @@ def test_per_sample_numbers_split_identical_samples_on_the_gpu(sg):
 # replicas, overlap, energies
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [8, 16, 30])
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "parisi_rapuano"])
 @pytest.mark.parametrize("kernel", ["fused", "twopass"])
 def test_two_replicas_in_one_pass(sg, L, prng, kernel):
     say("replicas", L, prng, kernel)
