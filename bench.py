@@ -165,11 +165,44 @@ def run_gpu(args, wl):
         return res
 
     main = measure(wl["prng"])
+    if args.layout_ab:
+        main["layout_ab"] = layout_ab(sg, torch, wl, stream, dev)
     variants = {}
     if not args.no_variant:
         for v in wl.get("variant") or ():
             variants[v] = measure(v)
     return main, variants
+
+
+def layout_ab(sg, torch, wl, stream, dev, nsw=4):
+    """ms per sweep of the two-pass kernel on the cube and on the colour-separated
+    layout (conversion excluded: the difference of nsw sweeps and none), same lattice."""
+    L, beta = wl["L"], wl["beta"]
+    lat = sg.Lattice(L, 64, wl["prng"], coupling_seed=1, spin_seed=2, device=dev, stream=stream)
+    work = torch.empty(sg.sliced_footprint(L), dtype=torch.uint8, device=dev)
+    lat.set_kernel("twopass")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    cube = timed(lambda: lat.sweep(nsw, beta)) / nsw
+    full = timed(lambda: lat.sweep_sliced(nsw, beta, work))
+    conv = timed(lambda: lat.sweep_sliced(0, beta, work))
+    lat.set_kernel("auto")
+    fused = timed(lambda: lat.sweep(nsw, beta)) / nsw
+    lat.close()
+    del work
+    torch.cuda.empty_cache()
+    return {"lattice": f"L={L}, 64 samples, one replica", "twopass_cube_ms_per_sweep": round(cube, 4),
+            "twopass_sliced_ms_per_sweep": round((full - conv) / nsw, 4), "sliced_conversion_ms": round(conv, 4),
+            "fused_default_ms_per_sweep": round(fused, 4)}
 
 
 def _budget_bytes(torch, frac=0.8):
@@ -280,6 +313,8 @@ def main():
                     help="c3/c4: multiply every job's sweep count (the full mixes take minutes)")
     ap.add_argument("--jobs", type=int, default=0, help="c3/c4: number of jobs (default 256 / 64)")
     ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
+    ap.add_argument("--layout-ab", action="store_true",
+                    help="also time the two-pass kernel on the cube and on the colour-separated layout")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also make 3 device copies of BYTES bytes, for counter calibration")
     args = ap.parse_args()
@@ -381,6 +416,8 @@ def main():
             },
         },
     }
+    if "layout_ab" in main_res:
+        line["layout_ab"] = main_res["layout_ab"]
     if variants:
         line["variants"] = {
             name: {

@@ -135,6 +135,18 @@ int sg_sweep(sg_lattice *lat, int64_t nsweeps, double beta);
  * the same L, prng and stream. */
 int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double beta);
 
+/* ---- Colour-separated layout (the layout study of Sec. 2) ----------------------
+ * Bytes of the work buffer sg_sweep_sliced needs: 32 per site. */
+int sg_sliced_footprint(int L, size_t *dev_bytes);
+
+/* nsweeps sweeps with the two-pass kernel on the colour-separated layout: the
+ * current spins and the couplings are copied into `work` (caller's device buffer,
+ * >= sg_sliced_footprint bytes, 256-byte aligned) with red and blue sites of each
+ * row in separate arrays indexed by (z, y, x/2) and each site's three couplings with
+ * its colour, swept there, and the spins copied back.  The spins are bit-identical
+ * to sg_sweep's; `work` is scratch, free again when the queued work is done. */
+int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes);
+
 /* Observables of Sec. 1, Eq. (1), per sample j < nsamples:
  * unsat[j] = number of unsatisfied bonds (-J s_i s_k = +1) among the 3V bonds,
  * e_per_spin[j] = (2*unsat[j] - 3V) / V.  Either output may be NULL. */

@@ -19,6 +19,7 @@ SOURCES = [
     "kernels_observe.hip",
     "kernels_sweep_twopass.hip",
     "kernels_sweep_fused.hip",
+    "kernels_sliced.hip",
     "sg_batch.hip",
 ]
 

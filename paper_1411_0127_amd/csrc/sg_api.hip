@@ -482,6 +482,66 @@ int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double be
     return SG_OK;
 }
 
+int sg_sliced_footprint(int L, size_t *dev_bytes)
+{
+    if (L < 2 || (L & 1) || L > 2048 || !dev_bytes)
+        return fail(SG_EINVAL, "L must be even, 2..2048");
+    *dev_bytes = (size_t)32 * L * L * L;  // spins and three coupling words per site
+    return SG_OK;
+}
+
+int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    size_t need = 0;
+    sg_sliced_footprint(lat->L, &need);
+    if (!work || work_bytes < need)
+        return fail(SG_EINVAL, "sliced work buffer too small: need " + std::to_string(need) + " bytes");
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0)
+        return fail(SG_EINVAL, "sliced work buffer must be 256-byte aligned");
+    uint64_t T[3];
+    sg_thresholds(beta, lat->prng, T);
+    const int64_t V = lat->V;
+    uint64_t *S = static_cast<uint64_t *>(work);
+    uint64_t *K = S + V;
+    hipError_t e = launch_to_sliced(lat->spins[lat->cur], S, lat->L, 1, lat->stream);
+    if (e == hipSuccess)
+        e = launch_to_sliced(lat->J, K, lat->L, 3, lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "to sliced layout");
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        const int64_t t = lat->t;
+        if (buffered_draws(lat->prng)) {
+            e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, lat->stream)
+                                        : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, lat->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "stream fill");
+        }
+        SweepArgs a{};
+        a.J = nullptr;
+        a.nrep = 1;
+        a.L = lat->L;
+        a.prng = buffered_draws(lat->prng) ? SG_MT19937 : lat->prng;
+        a.minstd_a = minstd_multiplier(t);
+        a.t = t;
+        a.T = Thresholds{T[0], T[1], T[2]};
+        a.rnd[0] = lat->rbuf;
+        a.mk[0] = lat->minstd_k;
+        a.pkey[0] = lat->key_philox;
+        e = launch_sweep_sliced(a, S, K, lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "sliced sweep");
+        lat->t += 1;
+    }
+    e = launch_from_sliced(S, lat->spins[lat->cur], lat->L, lat->stream);
+    return e == hipSuccess ? SG_OK : hip_fail(e, "from sliced layout");
+}
+
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin)
 {
     if (!lat)

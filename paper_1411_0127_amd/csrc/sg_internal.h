@@ -313,6 +313,11 @@ struct SweepArgs {
     Thresholds T;
 };
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
+// Colour-separated layout: conversion of nwords cube arrays (stride V), and a sweep
+// of one lattice (a.src[0] unused) on sliced spins S [2][V/2] and couplings K [3][2][V/2].
+hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, hipStream_t s);
+hipError_t launch_from_sliced(const uint64_t *sliced, uint64_t *cube, int L, hipStream_t s);
+hipError_t launch_sweep_sliced(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s);
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);

@@ -65,6 +65,8 @@ SIGNATURES = {
     "sg_batch_add": (_i, [_p, _p, _i64, _d]),
     "sg_batch_run": (_i, [_p, _i64, _i, ctypes.POINTER(_i64)]),
     "sg_batch_take_finished": (_i, [_p, ctypes.POINTER(_p), _i, ctypes.POINTER(_i)]),
+    "sg_sliced_footprint": (_i, [_i, ctypes.POINTER(_sz)]),
+    "sg_sweep_sliced": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "sg_batch_destroy": (_i, [_p]),
@@ -110,6 +112,12 @@ def thresholds(beta: float, prng="minstd") -> np.ndarray:
     T = np.zeros(3, dtype=np.uint64)
     _check(lib.sg_thresholds(float(beta), PRNGS[prng], _ptr(T)))
     return T
+
+
+def sliced_footprint(L: int) -> int:
+    n = _sz()
+    _check(lib.sg_sliced_footprint(int(L), ctypes.byref(n)))
+    return int(n.value)
 
 
 def footprint(L: int, prng="minstd", own_couplings: bool = True) -> int:
@@ -167,6 +175,14 @@ class Lattice:
     # -- dynamics -----------------------------------------------------------------
     def sweep(self, n: int, beta: float):
         _check(lib.sg_sweep(self.handle, int(n), float(beta)))
+
+    def sweep_sliced(self, n: int, beta: float, work=None):
+        """n sweeps on the colour-separated layout (sg_sweep_sliced); ``work`` is a
+        uint8 device tensor of sliced_footprint(L) bytes, allocated when None."""
+        if work is None:
+            work = _torch().empty(sliced_footprint(self.L), dtype=_torch().uint8, device=self.buf.device)
+        _check(lib.sg_sweep_sliced(self.handle, int(n), float(beta), _p(work.data_ptr()), int(work.numel())))
+        return work
 
     def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0, band: int = 0):
         _check(lib.sg_set_kernel(self.handle, KERNELS[kind] if isinstance(kind, str) else int(kind),

@@ -340,6 +340,43 @@ def test_per_sample_numbers_split_identical_samples_on_the_gpu(sg):
 
 
 # ---------------------------------------------------------------------------
+# colour-separated layout (the layout study): the same spins as the cube kernels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 4, 8, 18, 32])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "parisi_rapuano", "philox"])
+def test_sliced_layout_sweeps_match_the_oracle(sg, L, prng):
+    say("sliced", L, prng)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=5, spin_seed=6)
+    ref = oracle_for(L, 64, prng, 5, 6)
+    work = None
+    t = 0
+    for n, beta in [(1, 0.9), (2, 0.4), (3, 1.6), (0, 0.9)]:
+        work = lat.sweep_sliced(n, beta, work)
+        ref.sweep(n, beta)
+        t += n
+        assert lat.t == t
+        assert_same(lat.words(), ref, 64, f"L={L} {prng} sliced after {t} sweeps")
+
+
+def test_sliced_layout_equals_the_cube_kernels_at_L64(sg):
+    say("sliced vs cube L64")
+    L = 64
+    a = sg.Lattice(L, 64, "minstd", coupling_seed=9, spin_seed=10)
+    b = sg.Lattice(L, 64, "minstd", coupling_seed=9, spin_seed=10)
+    a.sweep(3, 0.8)      # fused kernels
+    b.sweep_sliced(3, 0.8)
+    assert np.array_equal(a.words(), b.words())
+    a.sweep(2, 1.3)
+    b.set_kernel("twopass")
+    b.sweep(1, 1.3)      # mixing layouts between calls keeps the trajectory
+    b.sweep_sliced(1, 1.3)
+    assert np.array_equal(a.words(), b.words())
+    with pytest.raises(sg.SGError):
+        lib_small = sg.lib.sg_sweep_sliced(b.handle, 1, 1.0, None, 0)
+        sg._check(lib_small)
+
+
+# ---------------------------------------------------------------------------
 # replicas, overlap, energies
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [8, 16, 30])
