@@ -320,7 +320,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent lattices and replicas would shard by job placement, one GPU each).",
               file=sys.stderr)
         sys.exit(2)
