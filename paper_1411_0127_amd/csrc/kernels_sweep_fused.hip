@@ -588,20 +588,23 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     }
 }
 
-// Planes in flight for the two-sweep march.
-constexpr int kRing2 = 4;
+// Planes in flight for the two-sweep march: a plane is requested NS-2 steps before
+// the step that first reads it.
+constexpr int kRing2 = 5;
+constexpr int kRing2Steps = kRing2 % 2 ? 2 * kRing2 : kRing2;  // unrolled steps per loop turn
 
 // The march of one work item after its lanes are set up.  P0 = (row parity +
 // first step) & 1 is the same for a whole wave; with an even ring the pair half
 // of ring slot i is then (P0 + i) & 1, known at compile time, so the steps of a
 // turn of the ring are straight-line code.
-template <int PRNG, int P0, int... Is>
+template <int PRNG, int P0, int NS, int... Is>
 __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, uint64_t *lds, const int z0,
                                            const int ZCe, const Offsets &o, const uint32_t o_st,
                                            const bool second, std::integer_sequence<int, Is...>)
 {
-    constexpr int NS = sizeof...(Is);
-    static_assert(NS % 2 == 0, "an odd ring would change the pair half of a slot from turn to turn");
+    // Is enumerates the unrolled steps: one turn of an even ring, two of an odd one,
+    // so that each unrolled step has a fixed ring slot and pair half.
+    static_assert(sizeof...(Is) == (NS % 2 ? 2 * NS : NS), "one or two turns of the ring");
     const int L = p.L;
     const int64_t LL = (int64_t)L * L;
     Offsets o_none;
@@ -614,7 +617,9 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     const int kfirst = z0 - 3;
     const int klast = z0 + ZCe + 2;
     Plane<1> ring[NS];
-    ((load_plane<PRNG, 1>(p, wrap(kfirst - 1 + Is), o, ring[Is])), ...);
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+        load_plane<PRNG, 1>(p, wrap(kfirst - 1 + j), o, ring[j]);
 
     Carry2 cy;
     cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
@@ -637,7 +642,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     auto step = [&](auto I) -> bool {
         constexpr int i = decltype(I)::value;
         constexpr int H = (P0 + i) & 1;
-        Plane<1> &A = ring[i];
+        Plane<1> &A = ring[i % NS];
         const Plane<1> &B = ring[(i + 1) % NS];
         const Plane<1> &C = ring[(i + 2) % NS];
         uint64_t ar0 = 0, ab0 = 0, br0 = 0, bb0 = 0, jxl, jyulo, jyuhi;
@@ -747,16 +752,16 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     o.r = kOOB;
     const uint32_t o_st = inter ? col * 8u : kOOB;
     if ((ypar + z0 - 3 + p.L) & 1)
-        fused2_run<PRNG, 1>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 1, kRing2>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
     else
-        fused2_run<PRNG, 0>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 0, kRing2>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
 }
 
 template <int PRNG>
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused2_march<PRNG>(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2>{});
+    fused2_march<PRNG>(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2Steps>{});
 }
 
 // Many lattices per launch ("round").  Work items of all lattices are numbered
@@ -813,7 +818,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
         p.WO[0] = e.WO0;
         p.WO[1] = e.WO1;
         p.a2 = minstd_power(e.t0 + s0 + 1);
-        fused2_march<SG_MINSTD>(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2>{});
+        fused2_march<SG_MINSTD>(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2Steps>{});
     } else {
         p.EX = e.TXp + 2;
         p.EY = e.TY + 4;
