@@ -117,3 +117,27 @@ def test_L256_two_replicas_sampled_sites(prng):
     rng = np.random.default_rng(9)
     window_check(L, prng, 1, 2, 0, wa, n, beta, centers_for(L, rng, 60, shape[1:3]))
     window_check(L, prng, 1, 2, 1, wb, n, beta, centers_for(L, rng, 30, shape[1:3]))
+
+
+def test_beyond_two_to_the_31_sites():
+    """L = 1300: V = 2.2e9 sites, past every signed 32-bit index.  Two sweeps on
+    the two-sweep kernel and one on the one-sweep kernel, checked on sampled
+    sites, the last rows and planes among them."""
+    import torch
+
+    from paper_1411_0127_amd import sg
+
+    L, beta, n = 1300, 1 / 1.1, 3
+    assert L**3 > 2**31
+    say("L1300 window parity")
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=4, spin_seed=5)
+    lat.sweep(2, beta)  # one two-sweep launch
+    lat.sweep(1, beta)  # one one-sweep launch
+    words = lat.words()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(12)
+    centers = [(L - 1, L - 1, L - 1), (0, L - 1, L - 1), (L - 2, 0, L - 1), (L // 2, L - 1, L - 2), (17, 33, L - 1)]
+    centers += [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(25)]
+    window_check(L, "minstd", 4, 5, 0, words, n, beta, centers)
