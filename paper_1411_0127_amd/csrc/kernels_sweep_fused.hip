@@ -637,6 +637,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     __syncthreads();
 
     int k = kfirst;
+    uint32_t zk_prev = minstd_plane_key((uint32_t)wrap(kfirst - 1), p.mk[0]);
     // One step with ring slots (A, B, C) = planes (k-1, k, k+1); A's slot receives
     // plane k+NS-1 at the end.
     auto step = [&](auto I) -> bool {
@@ -652,7 +653,8 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         const bool do_bb = second && k >= z0 + 3;
         const bool do_pub = k < klast;
         const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);
-        const uint32_t zk1 = minstd_plane_key((uint32_t)wrap(k - 1), p.mk[0]);
+        const uint32_t zk1 = zk_prev;  // key of plane k-1, from the previous step
+        zk_prev = zk;
         fused2_step<PRNG, H>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, (uint32_t)wrap(k),
                              (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
         {
