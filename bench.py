@@ -106,9 +106,10 @@ def run_gpu(args, wl):
             nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
             if kind == "fused2" and prng in ("mt19937", "parisi_rapuano"):
                 kind = "fused"  # the two-sweep kernel takes MINSTD and Philox lattices
-            shape = (kind,) + nums
             for l in lats:
-                l.set_kernel(kind, *nums)
+                l.set_kernel(kind, *nums[:4])
+                if len(nums) > 4:
+                    l.set_ring(nums[4])
         elif args.kernel == "auto":
             # pick the fused kernel and tile on these lattices, before the timed region
             shape, _ = sg.autotune(lats[:2], reps=5)
@@ -117,6 +118,8 @@ def run_gpu(args, wl):
         else:
             for l in lats:
                 l.set_kernel(args.kernel)
+        if shape is not None or args.tile:
+            shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
         kind = shape[0] if shape else args.kernel
         per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng in ("minstd", "philox"))) and nsw % 2 == 0 else 1
 
@@ -305,7 +308,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
     ap.add_argument("--tile", default="",
-                    help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band (skips the autotuner)")
+                    help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band[,planes] (skips the autotuner)")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")

@@ -184,13 +184,23 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t);
  * shapes return SG_EINVAL and change nothing. */
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
+/* Planes the two-sweep march keeps in flight (requested planes-2 steps ahead): 5 or
+ * 6, or 0 for the default (6 from L = 512 up, 5 below).  Reset by sg_set_kernel. */
+int sg_set_ring(sg_lattice *lat, int planes);
+
+/* The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,
+ * _FUSED or _FUSED2), tile_x, tile_y, z_chunk (0 = chosen at launch), band, and the
+ * planes in flight of the two-sweep march (0 for the others). */
+int sg_get_kernel(const sg_lattice *lat, int out[6]);
+
 /* Autotune the fused kernels for n (1 or 2) lattices swept together (n = 2:
  * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
- * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 but for SG_MT19937) and tiles are timed with
+ * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or 6 planes in flight but for
+ * the buffered generators) and tiles are timed with
  * `reps` launches each on the lattices' own data without changing their state
  * (the launches read the current spins and write only the spare buffer; sweep
  * count and streams do not move), and compared by time per sweep.  The fastest
- * is set on every lattice (as sg_set_kernel) and remembered for this device, L,
+ * is set on every lattice (as sg_set_kernel and sg_set_ring) and remembered for this device, L,
  * n and prng; a later call with the same key reuses it without timing unless
  * reps < 0 forces a new search.  best[5] (may be NULL) receives kind, tile_x,
  * tile_y, z_chunk, band; ms (may be NULL) the best time per sweep, or -1 when the

@@ -149,6 +149,20 @@ __device__ __forceinline__ uint64_t site_update(const FusedParams &p, int r, int
     return flip_site(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
 }
 
+// Loads of one plane given its byte offset qo = plane * L*L * 8 (draw-buffered
+// generators excluded: their numbers are not read by the two-sweep march).
+__device__ __forceinline__ void load_plane_at(const FusedParams &p, int64_t qo, const Offsets &o, Plane<1> &d)
+{
+    const int64_t LL8 = (int64_t)p.L * p.L * 8;
+    const int64_t V8 = LL8 * p.L;
+    const uint32_t pb = (uint32_t)LL8;
+    ld_pair(plane_rsrc(p.src[0], qo, pb), o.s, d.slo[0], d.shi[0]);
+    ld_pair(plane_rsrc(p.J, V8 + qo, pb), o.s, d.jylo, d.jyhi);
+    ld_pair(plane_rsrc(p.J, qo, pb), o.f, d.jxlo, d.jxhi);
+    ld_pair(plane_rsrc(p.J, 2 * V8 + qo, pb), o.f, d.jzlo, d.jzhi);
+    d.rlo[0] = d.rhi[0] = 0;
+}
+
 // Half H of a pair: 0 = even x, 1 = odd x.
 template <int H, int NREP>
 __device__ __forceinline__ uint64_t sp(const Plane<NREP> &d, int r) { return H ? d.shi[r] : d.slo[r]; }
@@ -588,10 +602,11 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     }
 }
 
-// Planes in flight for the two-sweep march: a plane is requested NS-2 steps before
-// the step that first reads it.
-constexpr int kRing2 = 5;
-constexpr int kRing2Steps = kRing2 % 2 ? 2 * kRing2 : kRing2;  // unrolled steps per loop turn
+// Planes in flight for the two-sweep march (a plane is requested NS-2 steps before
+// the step that first reads it): 5 or 6, chosen per lattice; batches use 5.
+constexpr int kRing2Batch = 5;
+template <int NS>
+using Ring2Steps = std::make_integer_sequence<int, NS % 2 ? 2 * NS : NS>;  // unrolled steps per loop turn
 
 // The march of one work item after its lanes are set up.  P0 = (row parity +
 // first step) & 1 is the same for a whole wave; with an even ring the pair half
@@ -616,10 +631,15 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     // first sweep's red runs over planes z0-3 .. z0+ZCe+2, reading old planes one beyond
     const int kfirst = z0 - 3;
     const int klast = z0 + ZCe + 2;
+    const int64_t LL8 = LL * 8, V8 = LL8 * L;
     Plane<1> ring[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-        load_plane<PRNG, 1>(p, wrap(kfirst - 1 + j), o, ring[j]);
+        load_plane_at(p, (int64_t)wrap(kfirst - 1 + j) * LL8, o, ring[j]);
+    // byte offsets of the next plane to load (k + NS - 1) and of the plane stored at
+    // step k (k - 3), both advanced by one plane per step
+    int64_t q_load = (int64_t)wrap(kfirst + NS - 1) * LL8;
+    int64_t q_store = (int64_t)wrap(kfirst - 3) * LL8;
 
     Carry2 cy;
     cy.jzm2lo = cy.jzm2hi = cy.jxl = cy.jyulo = cy.jyuhi = 0;
@@ -659,8 +679,8 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
                              (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
         {
             const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
-            const int64_t qo = (int64_t)wrap(k - 3) * LL * 8;
-            st_pair(plane_rsrc(p.dst[0], qo, (uint32_t)(LL * 8)), do_bb ? o_st : kOOB, wlo, whi);
+            st_pair(plane_rsrc(p.dst[0], q_store, (uint32_t)LL8), do_bb ? o_st : kOOB, wlo, whi);
+            q_store = q_store + LL8 == V8 ? 0 : q_store + LL8;
         }
         if (do_pub)
             __syncthreads();
@@ -679,14 +699,15 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         cy.r1 = r0;
         cy.b2 = cy.b1;
         cy.b1 = b0;
-        load_plane<PRNG, 1>(p, wrap(k + NS - 1), (k + NS - 1 <= klast + 1) ? o : o_none, A);
+        load_plane_at(p, q_load, (k + NS - 1 <= klast + 1) ? o : o_none, A);
+        q_load = q_load + LL8 == V8 ? 0 : q_load + LL8;
         return ++k <= klast;
     };
     while ((step(IC<Is>{}) && ...)) {
     }
 }
 
-template <int PRNG, int... Is>
+template <int PRNG, int NS, int... Is>
 __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
                                              std::integer_sequence<int, Is...> seq)
 {
@@ -754,16 +775,16 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     o.r = kOOB;
     const uint32_t o_st = inter ? col * 8u : kOOB;
     if ((ypar + z0 - 3 + p.L) & 1)
-        fused2_run<PRNG, 1, kRing2>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 1, NS>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
     else
-        fused2_run<PRNG, 0, kRing2>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 0, NS>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
 }
 
-template <int PRNG>
+template <int PRNG, int NS>
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused2_march<PRNG>(p, xcd_item(blockIdx.x, gridDim.x), lds, std::make_integer_sequence<int, kRing2Steps>{});
+    fused2_march<PRNG, NS>(p, xcd_item(blockIdx.x, gridDim.x), lds, Ring2Steps<NS>{});
 }
 
 // Many lattices per launch ("round").  Work items of all lattices are numbered
@@ -820,7 +841,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
         p.WO[0] = e.WO0;
         p.WO[1] = e.WO1;
         p.a2 = minstd_power(e.t0 + s0 + 1);
-        fused2_march<SG_MINSTD>(p, item - e.item0, lds, std::make_integer_sequence<int, kRing2Steps>{});
+        fused2_march<SG_MINSTD, kRing2Batch>(p, item - e.item0, lds, Ring2Steps<kRing2Batch>{});
     } else {
         p.EX = e.TXp + 2;
         p.EY = e.TY + 4;
@@ -1135,11 +1156,20 @@ void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk)
         }
 }
 
-hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)
+int fused2_default_ring(int L) { return L >= 512 ? 6 : 5; }
+
+hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, int ring,
+                               hipStream_t s)
 {
     if (a.prng == SG_MT19937 || a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
         return hipErrorInvalidConfiguration;
-    const void *fn = a.prng == SG_PHILOX ? (const void *)k_fused2<SG_PHILOX> : (const void *)k_fused2<SG_MINSTD>;
+    if (ring == 0)
+        ring = fused2_default_ring(a.L);
+    if (ring != 5 && ring != 6)
+        return hipErrorInvalidValue;
+    const bool px = a.prng == SG_PHILOX;
+    const void *fn = ring == 5 ? (px ? (const void *)k_fused2<SG_PHILOX, 5> : (const void *)k_fused2<SG_MINSTD, 5>)
+                               : (px ? (const void *)k_fused2<SG_PHILOX, 6> : (const void *)k_fused2<SG_MINSTD, 6>);
     const int threads = fused2_threads(tile_x, tile_y);
     const size_t lds = fused2_lds_bytes(tile_x, tile_y);
     const int P = a.L / 2;
@@ -1187,11 +1217,9 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
-    if (a.prng == SG_PHILOX)
-        hipLaunchKernelGGL(k_fused2<SG_PHILOX>, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
-    else
-        hipLaunchKernelGGL(k_fused2<SG_MINSTD>, dim3((unsigned)blocks), dim3((unsigned)threads), lds, s, p);
-    return hipGetLastError();
+    void *args[] = {&p};
+    return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)threads), args, lds, s);
+    
 }
 
 }  // namespace sg

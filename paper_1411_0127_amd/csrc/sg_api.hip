@@ -237,7 +237,7 @@ int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, 
     const int band = l0->band > 0 ? l0->band : 1;
     int done = 1;
     if (kind == 2) {
-        e = launch_sweep_fused2(a, tx, ty, zc, band, l0->stream);
+        e = launch_sweep_fused2(a, tx, ty, zc, band, l0->ring, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "two-sweep launch");
         done = 2;
@@ -726,6 +726,7 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
     }
     lat->kernel = kind;
     lat->band = band;
+    lat->ring = 0;
     if (kind == SG_KERNEL_FUSED || kind == SG_KERNEL_FUSED2) {
         lat->tile_x = tile_x;
         lat->tile_y = tile_y;
@@ -734,6 +735,33 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
         lat->tile_x = lat->tile_y = 0;
         lat->z_chunk = z_chunk;
     }
+    return SG_OK;
+}
+
+int sg_set_ring(sg_lattice *lat, int planes)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (planes != 0 && planes != 5 && planes != 6)
+        return fail(SG_EINVAL, "planes in flight must be 0 (default), 5 or 6");
+    lat->ring = planes;
+    return SG_OK;
+}
+
+int sg_get_kernel(const sg_lattice *lat, int out[6])
+{
+    if (!lat || !out)
+        return fail(SG_EINVAL, "NULL argument");
+    int tx = 0, ty = 0, zc = 0;
+    const int kind = pick_kernel(lat, 1, tx, ty, zc);
+    if (kind < 0)
+        return kind;
+    out[0] = kind == 2 ? SG_KERNEL_FUSED2 : (kind == 1 ? SG_KERNEL_FUSED : SG_KERNEL_TWOPASS);
+    out[1] = tx;
+    out[2] = ty;
+    out[3] = zc;
+    out[4] = lat->band > 0 ? lat->band : 1;
+    out[5] = kind == 2 ? (lat->ring ? lat->ring : fused2_default_ring(lat->L)) : 0;
     return SG_OK;
 }
 
@@ -746,7 +774,7 @@ struct TuneKey {
     }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<int, 5>> g_tuned;  // kind, tile_x, tile_y, z_chunk, band
+std::map<TuneKey, std::array<int, 6>> g_tuned;  // kind, tile_x, tile_y, z_chunk, band, ring
 }  // namespace
 
 int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *ms)
@@ -765,7 +793,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
     if (hipGetDevice(&dev) != hipSuccess)
         dev = 0;
     const TuneKey key{dev, l0->L, n, l0->prng};
-    std::array<int, 5> pick{0, 0, 0, 0, 1};
+    std::array<int, 6> pick{0, 0, 0, 0, 1, 0};
     double pick_ms = -1.0;
     bool cached = false;
     if (reps >= 0) {
@@ -808,44 +836,52 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         const int bands[] = {1, 2, 4};
         double best_ms = 1e300;
         int rc = SG_OK;
-        // kind 1: one sweep per launch; kind 2: two (MINSTD); compared per sweep
+        // kind 1: one sweep per launch; kind 2: two (MINSTD, PHILOX) with a ring of 5 or
+        // 6 planes; compared per sweep
         for (int kind = 1; kind <= 2 && rc == SG_OK; ++kind) {
             if (kind == 2 && buffered_draws(l0->prng))
                 break;
-            for (int tx : txs) {
-                if (tx > P)
-                    continue;
-                for (int ty : tys) {
-                    if (ty > l0->L)
+            for (int ring : {5, 6}) {
+                if (kind == 1 && ring == 6)
+                    break;
+                for (int tx : txs) {
+                    if (tx > P)
                         continue;
-                    if (kind == 1 ? !fused_shape_ok(l0->L, n, tx, ty, 0) : !fused2_shape_ok(l0->L, tx, ty, 0))
-                        continue;
-                    for (int band : bands) {
-                        auto launch = [&]() {
-                            return kind == 1 ? launch_sweep_fused(a, tx, ty, 0, band, l0->stream)
-                                             : launch_sweep_fused2(a, tx, ty, 0, band, l0->stream);
-                        };
-                        hipError_t e = launch();  // warm-up
-                        if (e == hipSuccess)
-                            e = hipEventRecord(e0, l0->stream);
-                        for (int k = 0; e == hipSuccess && k < nrep_launch; ++k)
-                            e = launch();
-                        if (e == hipSuccess)
-                            e = hipEventRecord(e1, l0->stream);
-                        if (e == hipSuccess)
-                            e = hipEventSynchronize(e1);
-                        float t_ms = 0.f;
-                        if (e == hipSuccess)
-                            e = hipEventElapsedTime(&t_ms, e0, e1);
-                        if (e != hipSuccess) {
-                            rc = hip_fail(e, "autotune launch");
+                    for (int ty : tys) {
+                        if (ty > l0->L)
+                            continue;
+                        if (kind == 1 ? !fused_shape_ok(l0->L, n, tx, ty, 0) : !fused2_shape_ok(l0->L, tx, ty, 0))
+                            continue;
+                        for (int band : bands) {
+                            auto launch = [&]() {
+                                return kind == 1 ? launch_sweep_fused(a, tx, ty, 0, band, l0->stream)
+                                                 : launch_sweep_fused2(a, tx, ty, 0, band, ring, l0->stream);
+                            };
+                            hipError_t e = launch();  // warm-up
+                            if (e == hipSuccess)
+                                e = hipEventRecord(e0, l0->stream);
+                            for (int k = 0; e == hipSuccess && k < nrep_launch; ++k)
+                                e = launch();
+                            if (e == hipSuccess)
+                                e = hipEventRecord(e1, l0->stream);
+                            if (e == hipSuccess)
+                                e = hipEventSynchronize(e1);
+                            float t_ms = 0.f;
+                            if (e == hipSuccess)
+                                e = hipEventElapsedTime(&t_ms, e0, e1);
+                            if (e != hipSuccess) {
+                                rc = hip_fail(e, "autotune launch");
+                                break;
+                            }
+                            const double per_sweep = (double)t_ms / nrep_launch / kind;
+                            if (per_sweep < best_ms) {
+                                best_ms = per_sweep;
+                                pick = {kind == 1 ? SG_KERNEL_FUSED : SG_KERNEL_FUSED2, tx, ty, 0, band,
+                                        kind == 1 ? 0 : ring};
+                            }
+                        }
+                        if (rc != SG_OK)
                             break;
-                        }
-                        const double per_sweep = (double)t_ms / nrep_launch / kind;
-                        if (per_sweep < best_ms) {
-                            best_ms = per_sweep;
-                            pick = {kind == 1 ? SG_KERNEL_FUSED : SG_KERNEL_FUSED2, tx, ty, 0, band};
-                        }
                     }
                     if (rc != SG_OK)
                         break;
@@ -870,6 +906,7 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         lats[r]->tile_y = pick[2];
         lats[r]->z_chunk = pick[3];
         lats[r]->band = pick[4];
+        lats[r]->ring = pick[5];
     }
     if (best)
         for (int k = 0; k < 5; ++k)

@@ -272,6 +272,7 @@ struct sg_lattice {
     int64_t t = 0;  // sweeps done
     int kernel = SG_KERNEL_AUTO;
     int tile_x = 0, tile_y = 0, z_chunk = 0, band = 0;
+    int ring = 0;  // planes in flight of the two-sweep march (0 = default)
 };
 
 namespace sg {
@@ -324,7 +325,10 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
 // Two sweeps (t and t+1) per launch, MINSTD only; replicas share one launch.
 bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk);
 void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk);
-hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
+// ring: planes in flight, 5 or 6 (0 = the default for the side, fused2_default_ring).
+hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, int ring,
+                               hipStream_t s);
+int fused2_default_ring(int L);
 
 // One lattice of a batched launch (device copy; see k_fused_batch).
 struct BatchEntry {

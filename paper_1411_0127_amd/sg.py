@@ -59,6 +59,8 @@ SIGNATURES = {
     "sg_sweep_count": (_i64, [_p]),
     "sg_set_sweep_count": (_i, [_p, _i64]),
     "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
+    "sg_set_ring": (_i, [_p, _i]),
+    "sg_get_kernel": (_i, [_p, _p]),
     "sg_autotune": (_i, [ctypes.POINTER(_p), _i, _i, _p, ctypes.POINTER(_d)]),
     "sg_batch_footprint": (_i, [_i, _i, ctypes.POINTER(_sz)]),
     "sg_batch_create": (_i, [_i, _i, _p, _sz, _p, ctypes.POINTER(_p)]),
@@ -187,6 +189,16 @@ class Lattice:
     def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0, band: int = 0):
         _check(lib.sg_set_kernel(self.handle, KERNELS[kind] if isinstance(kind, str) else int(kind),
                                  int(tile_x), int(tile_y), int(z_chunk), int(band)))
+
+    def set_ring(self, planes: int = 0):
+        """Planes in flight of the two-sweep march: 5, 6 or 0 (default)."""
+        _check(lib.sg_set_ring(self.handle, int(planes)))
+
+    def kernel(self):
+        """(kind, tile_x, tile_y, z_chunk, band, planes in flight) the next sweeps use."""
+        out = np.zeros(6, dtype=np.int32)
+        _check(lib.sg_get_kernel(self.handle, _ptr(out)))
+        return (KERNEL_NAMES[int(out[0])],) + tuple(int(v) for v in out[1:])
 
     @property
     def t(self) -> int:

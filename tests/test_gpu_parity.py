@@ -154,10 +154,13 @@ def test_fused_tile_shapes_and_ragged_edges(sg, L, tiles, prng):
 # launches and, for an odd count, one one-sweep launch
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [8, 10, 16, 18, 32, 34])
-def test_two_sweeps_per_launch_every_call(sg, L):
-    say("fused2 64 samples", L)
+@pytest.mark.parametrize("ring", [5, 6])
+def test_two_sweeps_per_launch_every_call(sg, L, ring):
+    say("fused2 64 samples", L, ring)
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4)
     lat.set_kernel("fused2")
+    lat.set_ring(ring)
+    assert lat.kernel()[0] == "fused2" and lat.kernel()[5] == ring
     ref = oracle_for(L, 64, "minstd", 3, 4)
     t = 0
     for n, beta in [(2, 0.9), (3, 0.3), (4, 2.0), (2, 1 / 1.1), (1, 0.9), (2, 0.7)]:
@@ -173,10 +176,12 @@ def test_two_sweeps_per_launch_every_call(sg, L):
     (24, (12, 20, 24)), (24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (34, (16, 16, 11)),
     (20, (1, 1, 1)), (22, (11, 22, 3)), (36, (6, 10, 36)), (40, (20, 6, 0)), (16, (8, 16, 5)),
 ])
-def test_two_sweep_tile_shapes_and_ragged_edges(sg, L, tiles):
-    say("fused2 tiles", L, tiles)
+@pytest.mark.parametrize("ring", [5, 6])
+def test_two_sweep_tile_shapes_and_ragged_edges(sg, L, tiles, ring):
+    say("fused2 tiles", L, tiles, ring)
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=8, spin_seed=21)
     lat.set_kernel("fused2", *tiles)
+    lat.set_ring(ring)
     ref = oracle_for(L, 64, "minstd", 8, 21)
     for k in range(3):
         lat.sweep(2, 0.75)
@@ -234,6 +239,11 @@ def test_two_sweeps_beta_zero_and_infinite(sg):
 
 
 def test_two_sweep_kernel_argument_checks(sg):
+    lat = sg.Lattice(16, 64, "minstd", coupling_seed=1, spin_seed=2)
+    for bad in (1, 4, 7):
+        with pytest.raises(sg.SGError):
+            lat.set_ring(bad)
+    assert lat.kernel()[5] == 5  # default below L = 512
     mt = sg.Lattice(16, 64, "mt19937", coupling_seed=1, spin_seed=2)
     with pytest.raises(sg.SGError) as e:
         mt.set_kernel("fused2")
@@ -538,6 +548,7 @@ def test_autotune_leaves_state_and_parity(sg, prng):
     wa, wb = a.words(), b.words()
     shape, ms = sg.autotune([a, b], reps=2)
     assert shape[0] in (("fused", "fused2") if prng == "minstd" else ("fused",))
+    assert a.kernel()[:5] == shape and b.kernel()[:5] == shape
     assert shape[1] > 0 and shape[2] > 0 and ms > 0
     assert a.t == 2 and b.t == 2
     assert np.array_equal(a.words(), wa) and np.array_equal(b.words(), wb)
