@@ -134,8 +134,8 @@ __device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Of
 
 // New word of one site: with SG_PHILOX every sample draws its own number, keyed
 // by the site index (plane z, in-plane index xy) and the sweep; otherwise R is the
-// site's number.
-template <int PRNG>
+// site's number.  Fold picks the counter form of flip_site.
+template <int PRNG, bool Fold = false>
 __device__ __forceinline__ uint64_t site_update(const FusedParams &p, int r, int64_t sweep, uint32_t z, uint32_t xy,
                                                 uint32_t R, uint64_t s, uint64_t nxp, uint64_t nyp, uint64_t nzp,
                                                 uint64_t nxm, uint64_t nym, uint64_t nzm, uint64_t jxp, uint64_t jyp,
@@ -146,7 +146,7 @@ __device__ __forceinline__ uint64_t site_update(const FusedParams &p, int r, int
         return flip_site_ps(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, site, (uint64_t)sweep,
                             (uint32_t)p.pkey[r], (uint32_t)(p.pkey[r] >> 32), p.T);
     }
-    return flip_site(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
+    return flip_site<PRNG == SG_MINSTD, Fold>(s, nxp, nyp, nzp, nxm, nym, nzm, jxp, jyp, jzp, jxm, jym, jzm, R, p.T);
 }
 
 // Loads of one plane given its byte offset qo = plane * L*L * 8 (draw-buffered
@@ -518,7 +518,7 @@ struct Carry2 {
     SiteOps r1, b1, r2, b2;      // first sweep's red / blue operands of steps k-1, k-2
 };
 
-template <int PRNG, int H>
+template <int PRNG, int H, bool Fold>
 __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c, uint64_t *lds, int k, bool do_ab,
                                             bool do_br, bool do_bb, bool do_pub, const Plane<1> &A,
                                             const Plane<1> &B, const Plane<1> &C, const Carry2 &cy, uint32_t zk,
@@ -547,9 +547,9 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nym = S[kF2OldBlue * nl + c.iym];
         const uint64_t nyp = S[kF2OldBlue * nl + c.iyp];
         const uint64_t s = sp<H>(B, 0), other = sp<1 - H>(B, 0);
-        ar0 = site_update<PRNG>(p, 0, p.t, r0.seed, xy, minstd_jump(p.a, r0.seed), s, H ? nbx : other, nyp,
-                                sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp, r0.jzp, r0.jxm,
-                                r0.jym, r0.jzm);
+        ar0 = site_update<PRNG, Fold>(p, 0, p.t, r0.seed, xy, minstd_jump(p.a, r0.seed), s, H ? nbx : other, nyp,
+                                      sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp, r0.jzp, r0.jxm,
+                                      r0.jym, r0.jzm);
     }
 
     // ---- first sweep, blue of plane k-1: neighbours are new red ----------------
@@ -564,9 +564,9 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nbx = S[kF2Red * nl + ixn];
         const uint64_t nym = S[kF2Red * nl + c.iym];
         const uint64_t nyp = S[kF2Red * nl + c.iyp];
-        ab0 = site_update<PRNG>(p, 0, p.t, b0.seed, xy, minstd_jump(p.a, b0.seed), sp<H>(A, 0), H ? nbx : cy.ar1,
-                                nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp, b0.jzp, b0.jxm, b0.jym,
-                                b0.jzm);
+        ab0 = site_update<PRNG, Fold>(p, 0, p.t, b0.seed, xy, minstd_jump(p.a, b0.seed), sp<H>(A, 0), H ? nbx : cy.ar1,
+                                      nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp, b0.jzp, b0.jxm, b0.jym,
+                                      b0.jzm);
     }
 
     // ---- second sweep, red of plane k-2: neighbours are the first sweep's blue --
@@ -575,8 +575,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nym = S[kF2Blue * nl + c.iym];
         const uint64_t nyp = S[kF2Blue * nl + c.iyp];
         const SiteOps &o = cy.r2;
-        br0 = site_update<PRNG>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ar2, H ? nbx : cy.ab1,
-                                nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
+        br0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ar2, H ? nbx : cy.ab1,
+                                      nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
     // ---- second sweep, blue of plane k-3: neighbours are its own new red --------
@@ -585,8 +585,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         const uint64_t nym = S[kF2Red2 * nl + c.iym];
         const uint64_t nyp = S[kF2Red2 * nl + c.iyp];
         const SiteOps &o = cy.b2;
-        bb0 = site_update<PRNG>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ab2, H ? nbx : cy.br1,
-                                nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
+        bb0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ab2, H ? nbx : cy.br1,
+                                      nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
     // ---- publish for step k+1 ----------------------------------------------------
@@ -675,8 +675,11 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);
         const uint32_t zk1 = zk_prev;  // key of plane k-1, from the previous step
         zk_prev = zk;
-        fused2_step<PRNG, H>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, (uint32_t)wrap(k),
-                             (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
+        // six planes in flight (the large-lattice march) count with the fold form,
+        // which measured faster there; five with the shorter three-input form
+        constexpr bool kFold = NS == 6;
+        fused2_step<PRNG, H, kFold>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, (uint32_t)wrap(k),
+                                    (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
         {
             const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
             st_pair(plane_rsrc(p.dst[0], q_store, (uint32_t)LL8), do_bb ? o_st : kOOB, wlo, whi);

@@ -92,6 +92,7 @@ namespace bop {
 constexpr uint32_t A = 0xF0, B = 0xCC, C = 0xAA;
 constexpr int table(uint32_t v) { return (int)(v & 0xFFu); }
 constexpr int kXor3 = table(A ^ B ^ C);                          // a ^ b ^ c
+constexpr int kXnor3 = table(~(A ^ B ^ C));                      // ~(a ^ b ^ c)
 constexpr int kMaj = table((A & B) | (A & C) | (B & C));         // majority
 constexpr int kBothEq = table(~(A ^ C) & ~(B ^ C));              // bitwise a == c and b == c
 constexpr int kOrAnd = table(A | (B & C));                       // a | (b & c)
@@ -105,62 +106,99 @@ __device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, T);
 }
 
-// Bits of the satisfied-bond count v = c2 c1 c0 of 32 samples.  x[k] = J_k ^ n_k,
-// and the bond bit is b_k = x[k] ^ ~s.  The complement of s is carried through
-// the adder instead of being applied to all six inputs: a three-input sum of
-// (x ^ c) is sum(x) ^ c, a majority of (x ^ c) is maj(x) ^ c, and c cancels in
-// the XOR of two such terms.  v = b0 + ... + b5 = (B1 + B2) + 2 (K1 + K2) with B,
-// K the sums and carries of the two triples.
+// Bits of the satisfied-bond count v = c2 c1 c0 of 32 samples.  Bond k is
+// satisfied when J_k s n_k = +1; with bit 1 for J = -1 and for a spin +1 that is
+// w_k = ~(j_k ^ s ^ n_k), one three-input operation per bond.  v = w0 + ... + w5
+// = (B1 + B2) + 2 (K1 + K2), B and K the sums and carries of the two triples.
 struct VBits {
     uint32_t c0, c1, c2;
 };
-__device__ __forceinline__ VBits vcount_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                             uint32_t x4, uint32_t x5)
+__device__ __forceinline__ VBits vcount_half(uint32_t s, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                             uint32_t n4, uint32_t n5, uint32_t j0, uint32_t j1, uint32_t j2,
+                                             uint32_t j3, uint32_t j4, uint32_t j5)
 {
+    const uint32_t w0 = bop3<bop::kXnor3>(j0, n0, s), w1 = bop3<bop::kXnor3>(j1, n1, s),
+                   w2 = bop3<bop::kXnor3>(j2, n2, s), w3 = bop3<bop::kXnor3>(j3, n3, s),
+                   w4 = bop3<bop::kXnor3>(j4, n4, s), w5 = bop3<bop::kXnor3>(j5, n5, s);
+    const uint32_t b1 = bop3<bop::kXor3>(w0, w1, w2), k1 = bop3<bop::kMaj>(w0, w1, w2);
+    const uint32_t b2 = bop3<bop::kXor3>(w3, w4, w5), k2 = bop3<bop::kMaj>(w3, w4, w5);
+    const uint32_t k3 = b1 & b2;  // carry of B1 + B2
+    VBits v;
+    v.c0 = b1 ^ b2;
+    v.c1 = bop3<bop::kXor3>(k1, k2, k3);
+    v.c2 = bop3<bop::kMaj>(k1, k2, k3);
+    return v;
+}
+
+// The same three bits from x_k = j_k ^ n_k, the spin folded in afterwards: w_k =
+// x_k ^ ~s, and since a three-input sum or majority of (x ^ c) is sum(x) ^ c or
+// maj(x) ^ c, the complement of s is carried through the adder and cancels in the
+// XOR of two such terms.  Two more operations than vcount_half, but the six x_k
+// do not wait for s.
+__device__ __forceinline__ VBits vcount_half_fold(uint32_t s, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                                  uint32_t n4, uint32_t n5, uint32_t j0, uint32_t j1, uint32_t j2,
+                                                  uint32_t j3, uint32_t j4, uint32_t j5)
+{
+    const uint32_t x0 = j0 ^ n0, x1 = j1 ^ n1, x2 = j2 ^ n2, x3 = j3 ^ n3, x4 = j4 ^ n4, x5 = j5 ^ n5;
     const uint32_t s1 = bop3<bop::kXor3>(x0, x1, x2);    // B1 = s1 ^ ~s
     const uint32_t k1 = bop3<bop::kMaj>(x0, x1, x2);     // K1 = k1 ^ ~s
     const uint32_t s2 = bop3<bop::kXor3>(x3, x4, x5);
     const uint32_t k2 = bop3<bop::kMaj>(x3, x4, x5);
     VBits v;
-    v.c0 = s1 ^ s2;                                      // bit 0 of v
-    const uint32_t k3 = bop3<bop::kBothEq>(s1, s2, s);   // carry of B1 + B2: B1 & B2, B = (s1 == s)
-    const uint32_t t = k1 ^ k2;                          // K1 ^ K2
-    v.c1 = t ^ k3;                                       // bit 1 of v
+    v.c0 = s1 ^ s2;
+    const uint32_t k3 = bop3<bop::kBothEq>(s1, s2, s);   // B1 & B2, B = (s1 == s)
+    const uint32_t t = k1 ^ k2;
+    v.c1 = t ^ k3;
     const uint32_t kk = bop3<bop::kBothEq>(k1, k2, s);   // K1 & K2, K = (k == s)
-    v.c2 = bop3<bop::kOrAnd>(kk, k3, t);                 // bit 2 of v: majority of K1, K2, k3
+    v.c2 = bop3<bop::kOrAnd>(kk, k3, t);                 // majority of K1, K2, k3
     return v;
 }
 
 // 32 samples of the update with one number for the word; returns the new spin
 // word.  a4, a8, a12 are all-ones when R < T4, T8, T12; since T12 <= T8 <= T4
 // they are nested, and the accepted set is v <= 3, or v = 4 with a4, v = 5 with
-// a8, v = 6 with a12.
-__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                              uint32_t x4, uint32_t x5, uint32_t a4, uint32_t a8, uint32_t a12)
+// a8, v = 6 with a12.  Fold selects vcount_half_fold.
+template <bool Fold>
+__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                              uint32_t n4, uint32_t n5, uint32_t j0, uint32_t j1, uint32_t j2,
+                                              uint32_t j3, uint32_t j4, uint32_t j5, uint32_t a4, uint32_t a8,
+                                              uint32_t a12)
 {
-    const VBits v = vcount_half(s, x0, x1, x2, x3, x4, x5);
+    const VBits v = Fold ? vcount_half_fold(s, n0, n1, n2, n3, n4, n5, j0, j1, j2, j3, j4, j5)
+                         : vcount_half(s, n0, n1, n2, n3, n4, n5, j0, j1, j2, j3, j4, j5);
     const uint32_t mid = bop3<bop::kSel>(v.c0, a8, a4);  // v = 4 or 5: accepted
     const uint32_t hi = bop3<bop::kSel>(v.c1, a12, mid); // v >= 4: accepted (a12 lies in mid)
     return bop3<bop::kXorOrNot>(s, v.c2, hi);            // s ^ (v <= 3 or accepted)
 }
 
+#define SG_LO(v) ((uint32_t)(v))          // low and high 32 samples of a word
+#define SG_HI(v) ((uint32_t)((v) >> 32))
+
 // New spin word of a 64-sample site: s the spin word, n0..n5 the neighbour words
 // and j0..j5 the coupling words of the same six bonds, one R for the word.
+// Narrow: every threshold lies below 2^32 (MINSTD's range is 2^31 - 1), so the
+// comparisons take 32 bits.  Fold: count with vcount_half_fold.
+template <bool Narrow = false, bool Fold = false>
 __device__ __forceinline__ uint64_t flip_site(uint64_t s, uint64_t n0, uint64_t n1, uint64_t n2, uint64_t n3,
                                               uint64_t n4, uint64_t n5, uint64_t j0, uint64_t j1, uint64_t j2,
                                               uint64_t j3, uint64_t j4, uint64_t j5, uint32_t R,
                                               const Thresholds &T)
 {
-    const uint64_t r = (uint64_t)R;
-    const uint32_t a4 = (r < T.t4) ? ~0u : 0u;
-    const uint32_t a8 = (r < T.t8) ? ~0u : 0u;
-    const uint32_t a12 = (r < T.t12) ? ~0u : 0u;
-    const uint64_t x0 = j0 ^ n0, x1 = j1 ^ n1, x2 = j2 ^ n2, x3 = j3 ^ n3, x4 = j4 ^ n4, x5 = j5 ^ n5;
-    const uint32_t lo = flip_half((uint32_t)s, (uint32_t)x0, (uint32_t)x1, (uint32_t)x2, (uint32_t)x3,
-                                  (uint32_t)x4, (uint32_t)x5, a4, a8, a12);
-    const uint32_t hi = flip_half((uint32_t)(s >> 32), (uint32_t)(x0 >> 32), (uint32_t)(x1 >> 32),
-                                  (uint32_t)(x2 >> 32), (uint32_t)(x3 >> 32), (uint32_t)(x4 >> 32),
-                                  (uint32_t)(x5 >> 32), a4, a8, a12);
+    uint32_t a4, a8, a12;
+    if (Narrow) {
+        a4 = R < (uint32_t)T.t4 ? ~0u : 0u;
+        a8 = R < (uint32_t)T.t8 ? ~0u : 0u;
+        a12 = R < (uint32_t)T.t12 ? ~0u : 0u;
+    } else {
+        const uint64_t r = (uint64_t)R;
+        a4 = r < T.t4 ? ~0u : 0u;
+        a8 = r < T.t8 ? ~0u : 0u;
+        a12 = r < T.t12 ? ~0u : 0u;
+    }
+    const uint32_t lo = flip_half<Fold>(SG_LO(s), SG_LO(n0), SG_LO(n1), SG_LO(n2), SG_LO(n3), SG_LO(n4), SG_LO(n5),
+                                  SG_LO(j0), SG_LO(j1), SG_LO(j2), SG_LO(j3), SG_LO(j4), SG_LO(j5), a4, a8, a12);
+    const uint32_t hi = flip_half<Fold>(SG_HI(s), SG_HI(n0), SG_HI(n1), SG_HI(n2), SG_HI(n3), SG_HI(n4), SG_HI(n5),
+                                  SG_HI(j0), SG_HI(j1), SG_HI(j2), SG_HI(j3), SG_HI(j4), SG_HI(j5), a4, a8, a12);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
@@ -206,12 +244,12 @@ __device__ __forceinline__ uint64_t flip_site_ps(uint64_t s, uint64_t n0, uint64
                                                  uint64_t j3, uint64_t j4, uint64_t j5, uint64_t i, uint64_t t,
                                                  uint32_t k0, uint32_t k1, const Thresholds &T)
 {
-    const uint64_t x0 = j0 ^ n0, x1 = j1 ^ n1, x2 = j2 ^ n2, x3 = j3 ^ n3, x4 = j4 ^ n4, x5 = j5 ^ n5;
-    const VBits lo = vcount_half((uint32_t)s, (uint32_t)x0, (uint32_t)x1, (uint32_t)x2, (uint32_t)x3, (uint32_t)x4,
-                                 (uint32_t)x5);
-    const VBits hi = vcount_half((uint32_t)(s >> 32), (uint32_t)(x0 >> 32), (uint32_t)(x1 >> 32),
-                                 (uint32_t)(x2 >> 32), (uint32_t)(x3 >> 32), (uint32_t)(x4 >> 32),
-                                 (uint32_t)(x5 >> 32));
+    const VBits lo = vcount_half(SG_LO(s), SG_LO(n0), SG_LO(n1), SG_LO(n2), SG_LO(n3), SG_LO(n4), SG_LO(n5),
+                                 SG_LO(j0), SG_LO(j1), SG_LO(j2), SG_LO(j3), SG_LO(j4), SG_LO(j5));
+    const VBits hi = vcount_half(SG_HI(s), SG_HI(n0), SG_HI(n1), SG_HI(n2), SG_HI(n3), SG_HI(n4), SG_HI(n5),
+                                 SG_HI(j0), SG_HI(j1), SG_HI(j2), SG_HI(j3), SG_HI(j4), SG_HI(j5));
+#undef SG_LO
+#undef SG_HI
     const uint64_t c0 = lo.c0 | ((uint64_t)hi.c0 << 32);
     const uint64_t c1 = lo.c1 | ((uint64_t)hi.c1 << 32);
     const uint64_t c2 = lo.c2 | ((uint64_t)hi.c2 << 32);
