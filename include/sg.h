@@ -95,11 +95,12 @@ enum {
  *                    columns along z, red plane k then blue plane k-1, in-plane
  *                    neighbours exchanged through LDS, old/new spins in two
  *                    buffers and tile-edge red sites recomputed by both tiles.
- * SG_KERNEL_FUSED2:  two sweeps per launch (SG_MINSTD, SG_PHILOX): the same march
- *                    carries sweep t+1 two planes behind sweep t, so spins and
- *                    couplings cross HBM once per two sweeps; an odd last sweep
- *                    of a call runs on SG_KERNEL_FUSED.
- * SG_KERNEL_AUTO picks SG_KERNEL_FUSED2 for SG_MINSTD and SG_PHILOX lattices and
+ * SG_KERNEL_FUSED2:  two sweeps per launch: the same march carries sweep t+1 two
+ *                    planes behind sweep t, so spins and couplings cross HBM once
+ *                    per two sweeps (the buffered generators, SG_MT19937 and
+ *                    SG_PARISI_RAPUANO, first write both sweeps' numbers); an odd
+ *                    last sweep of a call runs on SG_KERNEL_FUSED.
+ * SG_KERNEL_AUTO picks SG_KERNEL_FUSED2 where its tile fits (L >= 8) and
  * SG_KERNEL_FUSED otherwise, with default tiles (sg_autotune picks by timing). */
 enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2, SG_KERNEL_FUSED2 = 3 };
 
@@ -185,7 +186,8 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t);
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
 /* Planes the two-sweep march keeps in flight (requested planes-2 steps ahead): 5 or
- * 6, or 0 for the default (6 from L = 512 up, 5 below).  Reset by sg_set_kernel. */
+ * 6, or 0 for the default (6 from L = 512 up, 5 below; always 5 for the buffered
+ * generators, which reject 6).  Reset by sg_set_kernel. */
 int sg_set_ring(sg_lattice *lat, int planes);
 
 /* The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,
@@ -195,8 +197,8 @@ int sg_get_kernel(const sg_lattice *lat, int out[6]);
 
 /* Autotune the fused kernels for n (1 or 2) lattices swept together (n = 2:
  * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
- * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or 6 planes in flight but for
- * the buffered generators) and tiles are timed with
+ * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or, but for the buffered
+ * generators, 6 planes in flight) and tiles are timed with
  * `reps` launches each on the lattices' own data without changing their state
  * (the launches read the current spins and write only the spare buffer; sweep
  * count and streams do not move), and compared by time per sweep.  The fastest

@@ -64,8 +64,9 @@ __device__ __forceinline__ uint32_t mt_temper(uint32_t y)
     return y;
 }
 
-// Draws of sweep t: column c produces its outputs t*L .. t*L + L - 1 and writes
-// output t*L + z to R[z*L*L + c].  The twist is done one word at a time, right
+// Draws of sweeps t .. t+nsw-1: column c produces its outputs t*L .. (t+nsw)*L - 1
+// and writes output t*L + u to R[u*L*L + c], so sweep t+s's draws fill
+// R[s*L^3 .. (s+1)*L^3).  The twist is done one word at a time, right
 // before the word is output: word i of a new block is computed from word i and
 // i+1 of the previous block and word i+397 (already renewed when i+397 >= 624
 // wraps), which is exactly the order of the sequential in-place twist.
@@ -83,9 +84,10 @@ struct MtFillArgs {
 
 constexpr int kMtGroup = 8;
 
-__global__ __launch_bounds__(256) void k_mt_fill(MtFillArgs a, int L, int64_t t)
+__global__ __launch_bounds__(256) void k_mt_fill(MtFillArgs a, int L, int64_t t, int nsw)
 {
     const int ncols = L * L;
+    const int nz = nsw * L;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols)
         return;
@@ -93,8 +95,8 @@ __global__ __launch_bounds__(256) void k_mt_fill(MtFillArgs a, int L, int64_t t)
     uint32_t *__restrict__ R = a.R[blockIdx.y];
     int i = (int)(((int64_t)t * L) % kMtN);
     uint32_t cur = st[(size_t)i * ncols + c];
-    for (int z0 = 0; z0 < L; z0 += kMtGroup) {
-        const int n = min(kMtGroup, L - z0);
+    for (int z0 = 0; z0 < nz; z0 += kMtGroup) {
+        const int n = min(kMtGroup, nz - z0);
         uint32_t nxt[kMtGroup], far[kMtGroup];
 #pragma unroll
         for (int u = 0; u < kMtGroup; ++u) {
@@ -142,8 +144,8 @@ __global__ void k_init_pr(uint32_t *__restrict__ st, int ncols, uint64_t key)
     }
 }
 
-// The L numbers of sweep t (numbers t*L .. t*L + L-1) of every column, for up to
-// two stream sets (blockIdx.y).  A thread owns one column; its 64 state words sit
+// The numbers of sweeps t .. t+nsw-1 (numbers t*L .. (t+nsw)*L - 1) of every
+// column, laid out as for MT19937, for up to two stream sets (blockIdx.y).  A thread owns one column; its 64 state words sit
 // in LDS at word k * kPrBlock + thread (no bank conflicts) while it steps the
 // recurrence, and go back to HBM at the end.
 constexpr int kPrBlock = 128;
@@ -151,7 +153,7 @@ struct PrFillArgs {
     uint32_t *st[2];
     uint32_t *R[2];
 };
-__global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64_t t)
+__global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64_t t, int nsw)
 {
     __shared__ uint32_t buf[64 * kPrBlock];
     const int ncols = L * L;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64
     for (int k = 0; k < 64; ++k)
         b[k * kPrBlock] = st[(size_t)k * ncols + c];
     const int64_t n0 = t * (int64_t)L;
-    for (int z = 0; z < L; ++z) {
+    for (int z = 0; z < nsw * L; ++z) {
         const int n = (int)((n0 + z) & 63);
         const uint32_t x = b[((n - 24) & 63) * kPrBlock] + b[((n - 55) & 63) * kPrBlock];
         R[(size_t)z * ncols + c] = x ^ b[((n - 61) & 63) * kPrBlock];
@@ -204,27 +206,33 @@ hipError_t launch_init_pr(uint32_t *state, int L, uint64_t key, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s)
+hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
+                          hipStream_t s)
 {
+    if (nsw < 1 || nsw > 2)
+        return hipErrorInvalidValue;
     const int ncols = L * L;
     PrFillArgs a{};
     for (int r = 0; r < n && r < 2; ++r) {
         a.st[r] = state[r];
         a.R[r] = rbuf[r];
     }
-    hipLaunchKernelGGL(k_pr_fill, dim3((ncols + kPrBlock - 1) / kPrBlock, n), dim3(kPrBlock), 0, s, a, L, t);
+    hipLaunchKernelGGL(k_pr_fill, dim3((ncols + kPrBlock - 1) / kPrBlock, n), dim3(kPrBlock), 0, s, a, L, t, nsw);
     return hipGetLastError();
 }
 
-hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s)
+hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
+                          hipStream_t s)
 {
+    if (nsw < 1 || nsw > 2)
+        return hipErrorInvalidValue;
     const int ncols = L * L;
     MtFillArgs a{};
     for (int r = 0; r < n && r < 2; ++r) {
         a.st[r] = state[r];
         a.R[r] = rbuf[r];
     }
-    hipLaunchKernelGGL(k_mt_fill, dim3((ncols + kBlock - 1) / kBlock, n), dim3(kBlock), 0, s, a, L, t);
+    hipLaunchKernelGGL(k_mt_fill, dim3((ncols + kBlock - 1) / kBlock, n), dim3(kBlock), 0, s, a, L, t, nsw);
     return hipGetLastError();
 }
 

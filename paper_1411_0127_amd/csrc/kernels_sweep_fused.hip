@@ -61,7 +61,8 @@ template <int NREP>
 struct Plane {
     uint64_t slo[NREP], shi[NREP];
     uint64_t jxlo, jxhi, jylo, jyhi, jzlo, jzhi;
-    uint32_t rlo[NREP], rhi[NREP];
+    uint32_t rlo[NREP], rhi[NREP];  // buffered draws of the (first) sweep
+    uint32_t r2lo, r2hi;            // two-sweep march: buffered draws of the second sweep
 };
 
 // Raw buffer access.  A plane of an array gets its own descriptor (base = the
@@ -151,6 +152,7 @@ __device__ __forceinline__ uint64_t site_update(const FusedParams &p, int r, int
 
 // Loads of one plane given its byte offset qo = plane * L*L * 8 (draw-buffered
 // generators excluded: their numbers are not read by the two-sweep march).
+template <int PRNG>
 __device__ __forceinline__ void load_plane_at(const FusedParams &p, int64_t qo, const Offsets &o, Plane<1> &d)
 {
     const int64_t LL8 = (int64_t)p.L * p.L * 8;
@@ -160,7 +162,16 @@ __device__ __forceinline__ void load_plane_at(const FusedParams &p, int64_t qo, 
     ld_pair(plane_rsrc(p.J, V8 + qo, pb), o.s, d.jylo, d.jyhi);
     ld_pair(plane_rsrc(p.J, qo, pb), o.f, d.jxlo, d.jxhi);
     ld_pair(plane_rsrc(p.J, 2 * V8 + qo, pb), o.f, d.jzlo, d.jzhi);
-    d.rlo[0] = d.rhi[0] = 0;
+    if (PRNG == SG_MT19937) {  // buffered draws of both sweeps, 4 bytes per site each
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[0], qo / 2, pb / 2), o.r, 0, 0);
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[0], V8 / 2 + qo / 2, pb / 2), o.r, 0, 0);
+        d.rlo[0] = v.x;
+        d.rhi[0] = v.y;
+        d.r2lo = w.x;
+        d.r2hi = w.y;
+    } else {
+        d.rlo[0] = d.rhi[0] = d.r2lo = d.r2hi = 0;
+    }
 }
 
 // Half H of a pair: 0 = even x, 1 = odd x.
@@ -506,7 +517,7 @@ constexpr int kF2Words = 7;  // LDS words per lane and buffer set
 // SG_PHILOX: the site's plane, the numbers being keyed by the site).
 struct SiteOps {
     uint64_t jxp, jyp, jzp, jxm, jym, jzm;
-    uint32_t seed;
+    uint32_t seed;  // MINSTD seed, Philox plane key, or the second sweep's buffered draw
 };
 
 struct Carry2 {
@@ -565,12 +576,16 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     r0.jym = H ? jyuhi : jyulo;
     r0.jzp = H ? B.jzhi : B.jzlo;
     r0.jzm = H ? A.jzhi : A.jzlo;
-    r0.seed = PRNG == SG_PHILOX ? zr : minstd_seed(xy, zk);
+    // the number a site draws: MINSTD jumps its seed to the sweep, buffered draws
+    // come with the plane (the second sweep's is carried in the seed slot)
+    constexpr bool kBuf = PRNG == SG_MT19937;
+    r0.seed = PRNG == SG_PHILOX ? zr : kBuf ? (H ? B.r2hi : B.r2lo) : minstd_seed(xy, zk);
     {
         uint64_t nbx, nym, nyp;
         words(0, nbx, nym, nyp);
         const uint64_t s = sp<H>(B, 0), other = sp<1 - H>(B, 0);
-        ar0 = site_update<PRNG, Fold>(p, 0, p.t, r0.seed, xy, minstd_jump(p.a, r0.seed), s, H ? nbx : other, nyp,
+        const uint32_t R = kBuf ? (H ? B.rhi[0] : B.rlo[0]) : minstd_jump(p.a, r0.seed);
+        ar0 = site_update<PRNG, Fold>(p, 0, p.t, r0.seed, xy, R, s, H ? nbx : other, nyp,
                                       sp<H>(C, 0), H ? other : nbx, nym, sp<H>(A, 0), r0.jxp, r0.jyp, r0.jzp, r0.jxm,
                                       r0.jym, r0.jzm);
     }
@@ -582,11 +597,12 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     b0.jym = H ? cy.jyuhi : cy.jyulo;
     b0.jzp = H ? A.jzhi : A.jzlo;
     b0.jzm = H ? cy.jzm2hi : cy.jzm2lo;
-    b0.seed = PRNG == SG_PHILOX ? zb : minstd_seed(xy, zk1);
+    b0.seed = PRNG == SG_PHILOX ? zb : kBuf ? (H ? A.r2hi : A.r2lo) : minstd_seed(xy, zk1);
     if (do_ab) {
         uint64_t nbx, nym, nyp;
         words(1, nbx, nym, nyp);
-        ab0 = site_update<PRNG, Fold>(p, 0, p.t, b0.seed, xy, minstd_jump(p.a, b0.seed), sp<H>(A, 0), H ? nbx : cy.ar1,
+        const uint32_t R = kBuf ? (H ? A.rhi[0] : A.rlo[0]) : minstd_jump(p.a, b0.seed);
+        ab0 = site_update<PRNG, Fold>(p, 0, p.t, b0.seed, xy, R, sp<H>(A, 0), H ? nbx : cy.ar1,
                                       nyp, ar0, H ? cy.ar1 : nbx, nym, cy.ar2, b0.jxp, b0.jyp, b0.jzp, b0.jxm, b0.jym,
                                       b0.jzm);
     }
@@ -596,7 +612,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         uint64_t nbx, nym, nyp;
         words(2, nbx, nym, nyp);
         const SiteOps &o = cy.r2;
-        br0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ar2, H ? nbx : cy.ab1,
+        const uint32_t R = kBuf ? o.seed : minstd_jump(p.a2, o.seed);
+        br0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, R, cy.ar2, H ? nbx : cy.ab1,
                                       nyp, ab0, H ? cy.ab1 : nbx, nym, cy.ab2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
@@ -605,7 +622,8 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
         uint64_t nbx, nym, nyp;
         words(3, nbx, nym, nyp);
         const SiteOps &o = cy.b2;
-        bb0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, minstd_jump(p.a2, o.seed), cy.ab2, H ? nbx : cy.br1,
+        const uint32_t R = kBuf ? o.seed : minstd_jump(p.a2, o.seed);
+        bb0 = site_update<PRNG, Fold>(p, 0, p.t + 1, o.seed, xy, R, cy.ab2, H ? nbx : cy.br1,
                                       nyp, br0, H ? cy.br1 : nbx, nym, cy.br2, o.jxp, o.jyp, o.jzp, o.jxm, o.jym, o.jzm);
     }
 
@@ -655,7 +673,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     Plane<1> ring[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-        load_plane_at(p, (int64_t)wrap(kfirst - 1 + j) * LL8, o, ring[j]);
+        load_plane_at<PRNG>(p, (int64_t)wrap(kfirst - 1 + j) * LL8, o, ring[j]);
     // byte offsets of the next plane to load (k + NS - 1) and of the plane stored at
     // step k (k - 3), both advanced by one plane per step
     int64_t q_load = (int64_t)wrap(kfirst + NS - 1) * LL8;
@@ -722,7 +740,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         cy.r1 = r0;
         cy.b2 = cy.b1;
         cy.b1 = b0;
-        load_plane_at(p, q_load, (k + NS - 1 <= klast + 1) ? o : o_none, A);
+        load_plane_at<PRNG>(p, q_load, (k + NS - 1 <= klast + 1) ? o : o_none, A);
         q_load = q_load + LL8 == V8 ? 0 : q_load + LL8;
         return ++k <= klast;
     };
@@ -740,6 +758,7 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     FusedParams p = pp;
     p.src[0] = pp.src[rep];
     p.dst[0] = pp.dst[rep];
+    p.rnd[0] = pp.rnd[rep];
     p.mk[0] = pp.mk[rep];
     p.pkey[0] = pp.pkey[rep];
 
@@ -795,7 +814,7 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     Offsets o;
     o.s = c.lane ? col * 8u : kOOB;
     o.f = full ? col * 8u : kOOB;
-    o.r = kOOB;
+    o.r = PRNG == SG_MT19937 && full ? col * 4u : kOOB;  // 4-byte draws
     const uint32_t o_st = inter ? col * 8u : kOOB;
     if ((ypar + z0 - 3 + p.L) & 1)
         fused2_run<PRNG, 1, NS>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
@@ -1184,15 +1203,17 @@ int fused2_default_ring(int L) { return L >= 512 ? 6 : 5; }
 hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, int ring,
                                hipStream_t s)
 {
-    if (a.prng == SG_MT19937 || a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
+    if (a.nrep < 1 || a.nrep > 2 || !fused2_shape_ok(a.L, tile_x, tile_y, z_chunk))
         return hipErrorInvalidConfiguration;
+    const bool buf = a.prng == SG_MT19937;  // buffered draws of two sweeps in a.rnd
     if (ring == 0)
-        ring = fused2_default_ring(a.L);
-    if (ring != 5 && ring != 6)
+        ring = buf ? 5 : fused2_default_ring(a.L);
+    if (ring != 5 && (ring != 6 || buf))
         return hipErrorInvalidValue;
     const bool px = a.prng == SG_PHILOX;
-    const void *fn = ring == 5 ? (px ? (const void *)k_fused2<SG_PHILOX, 5> : (const void *)k_fused2<SG_MINSTD, 5>)
-                               : (px ? (const void *)k_fused2<SG_PHILOX, 6> : (const void *)k_fused2<SG_MINSTD, 6>);
+    const void *fn = buf         ? (const void *)k_fused2<SG_MT19937, 5>
+                     : ring == 5 ? (px ? (const void *)k_fused2<SG_PHILOX, 5> : (const void *)k_fused2<SG_MINSTD, 5>)
+                                 : (px ? (const void *)k_fused2<SG_PHILOX, 6> : (const void *)k_fused2<SG_MINSTD, 6>);
     const int threads = fused2_threads(tile_x, tile_y);
     const size_t lds = fused2_lds_bytes(tile_x, tile_y);
     const int P = a.L / 2;
@@ -1212,7 +1233,7 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     for (int r = 0; r < 2; ++r) {
         p.src[r] = a.src[r];
         p.dst[r] = a.dst[r];
-        p.rnd[r] = nullptr;
+        p.rnd[r] = a.rnd[r];
         p.mk[r] = a.mk[r];
     }
     p.L = a.L;

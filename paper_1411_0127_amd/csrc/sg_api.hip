@@ -85,8 +85,8 @@ Carve carve(int L, int prng, bool own_J)
     if (prng == SG_PARISI_RAPUANO)
         off = align_up(off + (size_t)4 * 64 * L * L);
     c.rbuf = off;
-    if (buffered_draws(prng))
-        off = align_up(off + 4 * V);
+    if (buffered_draws(prng))  // draws of the two sweeps of a two-sweep launch
+        off = align_up(off + 8 * V);
     c.scratch = off;
     off = align_up(off + 8 * ((size_t)kMaxReduceBlocks * 64 + 64));
     c.total = off;
@@ -164,7 +164,7 @@ int pick_kernel(const sg_lattice *lat, int nrep, int &tx, int &ty, int &zc)
 {
     if (lat->kernel == SG_KERNEL_TWOPASS)
         return 0;
-    if (lat->kernel == SG_KERNEL_FUSED2 || (lat->kernel == SG_KERNEL_AUTO && !buffered_draws(lat->prng))) {
+    if (lat->kernel == SG_KERNEL_FUSED2 || lat->kernel == SG_KERNEL_AUTO) {
         if (lat->kernel == SG_KERNEL_FUSED2 && lat->tile_x > 0) {
             tx = lat->tile_x;
             ty = lat->tile_y;
@@ -212,10 +212,13 @@ int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, 
             st[r] = lats[r]->mt_state;
             rb[r] = lats[r]->rbuf;
         }
-        e = l0->prng == SG_MT19937 ? launch_mt_fill(st, rb, n, l0->L, t, l0->stream)
-                                   : launch_pr_fill(st, rb, n, l0->L, t, l0->stream);
+        const int nsw = kind == 2 ? 2 : 1;
+        e = l0->prng == SG_MT19937 ? launch_mt_fill(st, rb, n, l0->L, t, nsw, l0->stream)
+                                   : launch_pr_fill(st, rb, n, l0->L, t, nsw, l0->stream);
         if (e != hipSuccess)
             return hip_fail(e, "stream fill");
+        for (int r = 0; r < n; ++r)
+            lats[r]->rlast = nsw - 1;
     }
     SweepArgs a{};
     a.J = l0->J;
@@ -517,8 +520,9 @@ int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, s
     for (int64_t k = 0; k < nsweeps; ++k) {
         const int64_t t = lat->t;
         if (buffered_draws(lat->prng)) {
-            e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, lat->stream)
-                                        : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, lat->stream);
+            e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream)
+                                        : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream);
+            lat->rlast = 0;
             if (e != hipSuccess)
                 return hip_fail(e, "stream fill");
         }
@@ -664,7 +668,7 @@ int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
         return fail(SG_EINVAL, "per-sample numbers: 64 per site, not one");
     hipError_t e;
     if (buffered_draws(lat->prng)) {
-        e = hipMemcpyAsync(out, lat->rbuf, 4 * n, hipMemcpyDeviceToHost, lat->stream);
+        e = hipMemcpyAsync(out, lat->rbuf + (size_t)lat->rlast * n, 4 * n, hipMemcpyDeviceToHost, lat->stream);
     } else {
         // MINSTD draws are a function of (site, sweep): evaluate the last sweep's on
         // the host with the device's own seed and jump functions
@@ -696,11 +700,13 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
     if (t < lat->t || lat->t != 0)
         return fail(SG_EINVAL, "a lattice with stream states can only be moved forward before its first sweep");
     for (int64_t k = 0; k < t; ++k) {
-        hipError_t e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream)
-                                               : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, lat->stream);
+        hipError_t e = lat->prng == SG_MT19937
+                           ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, 1, lat->stream)
+                           : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, k, 1, lat->stream);
         if (e != hipSuccess)
             return hip_fail(e, "stream fill");
     }
+    lat->rlast = 0;
     lat->t = t;
     return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
 }
@@ -713,8 +719,6 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
         return fail(SG_EINVAL, "unknown kernel");
     if (band < 0)
         return fail(SG_EINVAL, "band must be >= 0");
-    if (kind == SG_KERNEL_FUSED2 && buffered_draws(lat->prng))
-        return fail(SG_EINVAL, "the two-sweep kernel takes MINSTD and PHILOX lattices");
     if (kind == SG_KERNEL_FUSED && (tile_x != 0 || tile_y != 0)) {
         if (!fused_shape_ok(lat->L, 1, tile_x, tile_y, z_chunk))
             return fail(SG_EINVAL, "invalid fused tile shape");
@@ -744,6 +748,8 @@ int sg_set_ring(sg_lattice *lat, int planes)
         return fail(SG_EINVAL, "NULL lattice");
     if (planes != 0 && planes != 5 && planes != 6)
         return fail(SG_EINVAL, "planes in flight must be 0 (default), 5 or 6");
+    if (planes == 6 && buffered_draws(lat->prng))
+        return fail(SG_EINVAL, "with buffered draws the two-sweep march keeps 5 planes in flight");
     lat->ring = planes;
     return SG_OK;
 }
@@ -761,7 +767,7 @@ int sg_get_kernel(const sg_lattice *lat, int out[6])
     out[2] = ty;
     out[3] = zc;
     out[4] = lat->band > 0 ? lat->band : 1;
-    out[5] = kind == 2 ? (lat->ring ? lat->ring : fused2_default_ring(lat->L)) : 0;
+    out[5] = kind == 2 ? (lat->ring ? lat->ring : buffered_draws(lat->prng) ? 5 : fused2_default_ring(lat->L)) : 0;
     return SG_OK;
 }
 
@@ -836,13 +842,11 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
         const int bands[] = {1, 2, 4};
         double best_ms = 1e300;
         int rc = SG_OK;
-        // kind 1: one sweep per launch; kind 2: two (MINSTD, PHILOX) with a ring of 5 or
-        // 6 planes; compared per sweep
+        // kind 1: one sweep per launch; kind 2: two, with a ring of 5 or 6 planes (5
+        // only for buffered draws); compared per sweep
         for (int kind = 1; kind <= 2 && rc == SG_OK; ++kind) {
-            if (kind == 2 && buffered_draws(l0->prng))
-                break;
             for (int ring : {5, 6}) {
-                if (kind == 1 && ring == 6)
+                if (ring == 6 && (kind == 1 || buffered_draws(l0->prng)))
                     break;
                 for (int tx : txs) {
                     if (tx > P)

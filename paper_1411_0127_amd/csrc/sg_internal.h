@@ -304,7 +304,8 @@ struct sg_lattice {
     uint64_t *J = nullptr;
     const sg_lattice *J_owner = nullptr;  // nullptr: this lattice owns J
     uint32_t *mt_state = nullptr;         // MT19937 (624 words) or Parisi-Rapuano (64) state, word k of column c at k*L*L + c
-    uint32_t *rbuf = nullptr;             // MT19937 / Parisi-Rapuano draws of the sweep being done [V]
+    uint32_t *rbuf = nullptr;             // MT19937 / Parisi-Rapuano draws of the sweeps being done [2V]
+    int rlast = 0;                        // half of rbuf that holds the last sweep's draws
     uint64_t *scratch = nullptr;          // reduction partials
     hipStream_t stream = nullptr;
     int64_t t = 0;  // sweeps done
@@ -330,9 +331,13 @@ hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s
 hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s);
 hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s);
 // Draws of sweep t for n (1 or 2) stream sets of side L.
-hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
+// Buffered draws of sweeps t .. t+nsw-1 (nsw = 1 or 2) of n stream sets: sweep
+// t+s's draw of site i goes to rbuf[r][s*L^3 + i].
+hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
+                          hipStream_t s);
 hipError_t launch_init_pr(uint32_t *state, int L, uint64_t key, hipStream_t s);
-hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, hipStream_t s);
+hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
+                          hipStream_t s);
 // Generators whose numbers are read from a per-sweep buffer filled beforehand.
 inline bool buffered_draws(int prng) { return prng == SG_MT19937 || prng == SG_PARISI_RAPUANO; }
 

@@ -208,6 +208,77 @@ def test_two_sweeps_two_replicas(sg, L):
     assert np.array_equal(nd, oracle.ndiff(ra, rb))
 
 
+# ---------------------------------------------------------------------------
+# two sweeps per launch with buffered draws (MT19937, Parisi-Rapuano): the fill
+# writes both sweeps' numbers, and the march reads them with the planes
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [8, 10, 16, 18, 32, 34])
+@pytest.mark.parametrize("prng", ["mt19937", "parisi_rapuano"])
+def test_two_sweeps_buffered_draws_every_call(sg, L, prng):
+    say("fused2 buffered", L, prng)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=3, spin_seed=4)
+    lat.set_kernel("fused2")
+    assert lat.kernel()[0] == "fused2" and lat.kernel()[5] == 5
+    ref = oracle_for(L, 64, prng, 3, 4)
+    t = 0
+    for n, beta in [(2, 0.9), (3, 0.3), (4, 2.0), (2, 1 / 1.1), (1, 0.9), (2, 0.7)]:
+        lat.sweep(n, beta)
+        ref.sweep(n, beta)
+        t += n
+        assert lat.t == t
+        assert_same(lat.words(), ref, 64, f"L={L} {prng} fused2 after {t} sweeps")
+        assert np.array_equal(lat.randoms(), ref.last_R), f"draws of sweep {t}"
+    assert np.array_equal(lat.energy()[0], ref.unsatisfied())
+
+
+@pytest.mark.parametrize("L,tiles", [(24, (5, 7, 5)), (26, (4, 9, 6)), (34, (17, 3, 34)), (20, (1, 1, 1)),
+                                     (36, (6, 10, 36)), (16, (8, 16, 5))])
+@pytest.mark.parametrize("prng", ["mt19937", "parisi_rapuano"])
+def test_two_sweeps_buffered_tile_shapes(sg, L, tiles, prng):
+    say("fused2 buffered tiles", L, tiles, prng)
+    lat = sg.Lattice(L, 64, prng, coupling_seed=8, spin_seed=21)
+    lat.set_kernel("fused2", *tiles)
+    ref = oracle_for(L, 64, prng, 8, 21)
+    for k in range(3):
+        lat.sweep(2, 0.75)
+        ref.sweep(2, 0.75)
+        assert_same(lat.words(), ref, 64, f"L={L} {prng} fused2 tiles={tiles} after {2 * k + 2} sweeps")
+
+
+@pytest.mark.parametrize("prng", ["mt19937", "parisi_rapuano"])
+def test_two_sweeps_buffered_two_replicas(sg, prng):
+    say("fused2 buffered replicas", prng)
+    L = 18
+    a = sg.Lattice(L, 64, prng, coupling_seed=7, spin_seed=100, replica=0)
+    a.set_kernel("fused2")
+    b = sg.Lattice.replica_of(a, spin_seed=100, replica=1)
+    b.set_kernel("fused2")
+    ra = oracle_for(L, 64, prng, 7, 100, 0)
+    rb = oracle_for(L, 64, prng, 7, 100, 1)
+    for n in (2, 3, 2):
+        sg.sweep_replicas([a, b], n, 1 / 0.7)
+        ra.sweep(n, 1 / 0.7)
+        rb.sweep(n, 1 / 0.7)
+        assert_same(a.words(), ra, 64, f"replica 0 after {a.t}")
+        assert_same(b.words(), rb, 64, f"replica 1 after {b.t}")
+        assert np.array_equal(b.randoms(), rb.last_R)
+    with pytest.raises(sg.SGError):
+        a.set_ring(6)
+
+
+def test_mt19937_two_sweeps_across_twists(sg):
+    # 2 x 18 numbers per column per launch: 624-word blocks end inside launches
+    say("mt twists fused2")
+    L = 18
+    lat = sg.Lattice(L, 64, "mt19937", coupling_seed=1, spin_seed=9)
+    lat.set_kernel("fused2")
+    ref = oracle_for(L, 64, "mt19937", 1, 9)
+    lat.sweep(80, 0.6)
+    ref.sweep(80, 0.6)
+    assert np.array_equal(lat.randoms(), ref.last_R)
+    assert_same(lat.words(), ref, 64, "MT19937 L=18 after 80 sweeps, two per launch")
+
+
 def test_two_sweeps_L16_single_sample_every_second_sweep(sg):
     say("fused2 L16 1 sample 1000 sweeps")
     L, beta = 16, 1 / 0.7
@@ -245,9 +316,11 @@ def test_two_sweep_kernel_argument_checks(sg):
             lat.set_ring(bad)
     assert lat.kernel()[5] == 5  # default below L = 512
     mt = sg.Lattice(16, 64, "mt19937", coupling_seed=1, spin_seed=2)
-    with pytest.raises(sg.SGError) as e:
-        mt.set_kernel("fused2")
+    mt.set_kernel("fused2")
+    with pytest.raises(sg.SGError) as e:  # buffered draws: five planes in flight only
+        mt.set_ring(6)
     assert e.value.code == sg.SG_EINVAL
+    assert mt.kernel()[5] == 5
     small = sg.Lattice(6, 64, "minstd", coupling_seed=1, spin_seed=2)
     with pytest.raises(sg.SGError):
         small.set_kernel("fused2", 3, 3, 0)
@@ -286,7 +359,7 @@ def test_parisi_rapuano_device_numbers_and_forward_moves(sg):
     c.sweep(3, 0.9)
     assert np.array_equal(c.words(), a.words())
     with pytest.raises(sg.SGError):
-        c.set_kernel("fused2")
+        c.set_ring(6)
 
 
 # ---------------------------------------------------------------------------
@@ -547,16 +620,16 @@ def test_autotune_leaves_state_and_parity(sg, prng):
     rb.sweep(2, beta)
     wa, wb = a.words(), b.words()
     shape, ms = sg.autotune([a, b], reps=2)
-    assert shape[0] in (("fused", "fused2") if prng == "minstd" else ("fused",))
+    assert shape[0] in ("fused", "fused2")
     assert a.kernel()[:5] == shape and b.kernel()[:5] == shape
     assert shape[1] > 0 and shape[2] > 0 and ms > 0
     assert a.t == 2 and b.t == 2
     assert np.array_equal(a.words(), wa) and np.array_equal(b.words(), wb)
     again, ms2 = sg.autotune([a, b], reps=2)
     assert again == shape and ms2 < 0  # taken from the cache
-    for _ in range(3):
-        sg.sweep_replicas([a, b], 1, beta)
-        ra.sweep(1, beta)
-        rb.sweep(1, beta)
+    for n in (1, 2, 3):
+        sg.sweep_replicas([a, b], n, beta)
+        ra.sweep(n, beta)
+        rb.sweep(n, beta)
     assert_same(a.words(), ra, 64, "after autotune, replica 0")
     assert_same(b.words(), rb, 64, "after autotune, replica 1")
