@@ -52,17 +52,19 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes_per_site(prng: str, replicas: int) -> int:
+def algorithmic_bytes_per_site(prng: str, replicas: int, sweeps_per_launch: int = 1) -> int:
     """Bytes one fused sweep launch must move per lattice site.
 
     Couplings: 3 words read once for all replicas (24 B).  Per replica: the spin
-    word read and written (16 B); with MT19937 also the draw read from the
-    buffer the fill kernel wrote (4 B), as with Parisi-Rapuano.  MINSTD draws are computed from the site
-    and the sweep, nothing is read for them.  The MT19937 fill kernel's own state
-    traffic is not part of the sweep kernel.  A two-sweep launch must move the
-    same bytes: it reads and writes every word once for both sweeps.
+    word read and written (16 B); with MT19937 or Parisi-Rapuano also the draw of
+    every sweep of the launch, read from the buffer the fill kernel wrote (4 B
+    each).  MINSTD draws are computed from the site and the sweep, nothing is read
+    for them.  The fill kernel's own state traffic is not part of the sweep kernel.
+    A two-sweep launch reads and writes every spin and coupling word once for both
+    sweeps.
     """
-    return 24 + replicas * (16 + (4 if prng in ("mt19937", "parisi_rapuano") else 0))
+    draws = 4 * sweeps_per_launch if prng in ("mt19937", "parisi_rapuano") else 0
+    return 24 + replicas * (16 + draws)
 
 
 def kernel_source_sha() -> str:
@@ -104,12 +106,11 @@ def run_gpu(args, wl):
             parts = args.tile.split(",")
             kind = parts[0] if not parts[0].isdigit() else "fused"
             nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
-            if kind == "fused2" and prng in ("mt19937", "parisi_rapuano"):
-                kind = "fused"  # the two-sweep kernel takes MINSTD and Philox lattices
+            buffered = prng in ("mt19937", "parisi_rapuano")
             for l in lats:
                 l.set_kernel(kind, *nums[:4])
                 if len(nums) > 4:
-                    l.set_ring(nums[4])
+                    l.set_ring(5 if buffered else nums[4])  # buffered draws: five planes in flight
         elif args.kernel == "auto":
             # pick the fused kernel and tile on these lattices, before the timed region
             shape, _ = sg.autotune(lats[:2], reps=5)
@@ -121,7 +122,7 @@ def run_gpu(args, wl):
         if shape is not None or args.tile:
             shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
         kind = shape[0] if shape else args.kernel
-        per_launch = 2 if (kind == "fused2" or (kind == "auto" and prng in ("minstd", "philox"))) and nsw % 2 == 0 else 1
+        per_launch = 2 if kind in ("fused2", "auto") and nsw % 2 == 0 else 1
 
         def step(ev=None):
             if ev is not None:
@@ -371,7 +372,7 @@ def main():
         del src, dst
     L, R = wl["L"], wl["replicas"]
     V = L**3
-    bps = algorithmic_bytes_per_site(wl["prng"], R)
+    bps = algorithmic_bytes_per_site(wl["prng"], R, main_res["sweeps_per_launch"])
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
     eq = achieved * main_res["sweeps_per_launch"]
     traffic = load_traffic(args.workload)
