@@ -491,7 +491,7 @@ __global__ void k_round_reset(int64_t *round_ctr)
 }
 
 // ===========================================================================
-// Two sweeps per launch (MINSTD).
+// Two sweeps per launch.
 //
 // The same z-march carries a second sweep two planes behind the first.  At step k
 // a lane does, on its pair half H = (y + k) & 1:

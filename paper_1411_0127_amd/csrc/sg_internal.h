@@ -365,7 +365,8 @@ hipError_t launch_sweep_sliced(const SweepArgs &a, uint64_t *S, const uint64_t *
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s);
-// Two sweeps (t and t+1) per launch, MINSTD only; replicas share one launch.
+// Two sweeps (t and t+1) per launch, every generator (buffered draws: a.rnd holds
+// both sweeps' numbers); replicas share one launch.
 bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk);
 void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk);
 // ring: planes in flight, 5 or 6 (0 = the default for the side, fused2_default_ring).
