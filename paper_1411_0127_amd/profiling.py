@@ -15,6 +15,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -23,11 +24,19 @@ SWEEP_KERNEL = "k_fused"
 COPY_KERNEL = "copyBuffer"
 
 
+def _code_only(src: str) -> str:
+    """The source without comments and blank lines: what the compiler sees."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def kernel_source_sha() -> str:
+    """Hash of the sweep kernels' code; counters taken on other code are stale."""
     h = hashlib.sha256()
     for f in ("kernels_sweep_fused.hip", "sg_internal.h"):
-        with open(os.path.join(ROOT, "paper_1411_0127_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1411_0127_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
