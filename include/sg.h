@@ -195,13 +195,14 @@ int sg_set_ring(sg_lattice *lat, int planes);
  * planes in flight of the two-sweep march (0 for the others). */
 int sg_get_kernel(const sg_lattice *lat, int out[6]);
 
-/* Autotune the fused kernels for n (1 or 2) lattices swept together (n = 2:
+/* Autotune the sweep kernel for n (1 or 2) lattices swept together (n = 2:
  * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
- * (SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or, but for the buffered
- * generators, 6 planes in flight) and tiles are timed with
+ * (SG_KERNEL_TWOPASS; SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or, but for
+ * the buffered generators, 6 planes in flight, over their tiles) are timed with
  * `reps` launches each on the lattices' own data without changing their state
- * (the launches read the current spins and write only the spare buffer; sweep
- * count and streams do not move), and compared by time per sweep.  The fastest
+ * (the launches read the current spins and write only the spare buffer, the
+ * in-place two-pass kernel a copy of the spins there; sweep count and streams do
+ * not move), and compared by time per sweep.  The fastest
  * is set on every lattice (as sg_set_kernel and sg_set_ring) and remembered for this device, L,
  * n and prng; a later call with the same key reuses it without timing unless
  * reps < 0 forces a new search.  best[5] (may be NULL) receives kind, tile_x,

@@ -61,11 +61,12 @@ void drop_graph(sg_batch *b)
 
 // Tile of a lattice inside a batch: its chosen (autotuned) tile or the default of
 // its kernel; z chunks of the whole column up to L = 256 and half of it above for
-// the two-sweep march, of up to 128 planes for the one-sweep march.  Lattices on the automatic or two-sweep kernel get two-sweep rounds
-// when the tile allows them.
+// the two-sweep march, of up to 128 planes for the one-sweep march.  Lattices on
+// any kernel but SG_KERNEL_FUSED get two-sweep rounds when the tile allows them
+// (a batch has no two-pass form: a lattice set to it takes the default march).
 int batch_tile(const sg_lattice *lat, BatchEntry &e)
 {
-    const bool want_two = lat->kernel == SG_KERNEL_AUTO || lat->kernel == SG_KERNEL_FUSED2;
+    const bool want_two = lat->kernel != SG_KERNEL_FUSED;
     int tx = 0, ty = 0, zc = 0;
     if ((lat->kernel == SG_KERNEL_FUSED || lat->kernel == SG_KERNEL_FUSED2) && lat->tile_x > 0) {
         tx = lat->tile_x;

@@ -257,9 +257,9 @@ def sweep_replicas(lats: Sequence[Lattice], n: int, beta: float):
 
 
 def autotune(lats: Sequence[Lattice], reps: int = 5):
-    """Pick the fastest fused kernel and tile for these lattices (1, or 2 replicas swept
+    """Pick the fastest sweep kernel and tile for these lattices (1, or 2 replicas swept
     together); returns ((kind, tile_x, tile_y, z_chunk, band), ms per sweep or -1 if taken
-    from the cache), kind being "fused" or "fused2"."""
+    from the cache), kind being "twopass", "fused" or "fused2"."""
     arr = (_p * len(lats))(*[l.handle for l in lats])
     best = np.zeros(5, dtype=np.int32)
     ms = _d()

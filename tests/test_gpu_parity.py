@@ -607,7 +607,7 @@ def test_L256_two_replicas_on_two_bit_planes(sg, prng):
             assert np.array_equal((w >> sh) & np.uint64(1), one.words()), f"replica {r} plane {j}"
 
 
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+@pytest.mark.parametrize("prng", ["minstd", "mt19937", "philox"])
 def test_autotune_leaves_state_and_parity(sg, prng):
     say("autotune", prng)
     L, beta = 32, 0.9
@@ -620,9 +620,9 @@ def test_autotune_leaves_state_and_parity(sg, prng):
     rb.sweep(2, beta)
     wa, wb = a.words(), b.words()
     shape, ms = sg.autotune([a, b], reps=2)
-    assert shape[0] in ("fused", "fused2")
+    assert shape[0] in ("twopass", "fused", "fused2")
     assert a.kernel()[:5] == shape and b.kernel()[:5] == shape
-    assert shape[1] > 0 and shape[2] > 0 and ms > 0
+    assert ms > 0 and (shape[0] == "twopass" or (shape[1] > 0 and shape[2] > 0))
     assert a.t == 2 and b.t == 2
     assert np.array_equal(a.words(), wa) and np.array_equal(b.words(), wb)
     again, ms2 = sg.autotune([a, b], reps=2)
