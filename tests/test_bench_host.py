@@ -1,0 +1,55 @@
+"""Host logic of bench.py, without a GPU: the one-GPU contract, the algorithmic
+bytes of each launch kind, the source check of the traffic record and the CPU
+baseline record."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+from conftest import ROOT
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_per_site():
+    b = load_bench()
+    # couplings 24 B once, spins 16 B per replica, buffered draws 4 B per replica and sweep
+    assert b.algorithmic_bytes_per_site("minstd", 1) == 40
+    assert b.algorithmic_bytes_per_site("minstd", 2) == 56
+    assert b.algorithmic_bytes_per_site("minstd", 2, 2) == 56  # two sweeps per launch move the same words
+    assert b.algorithmic_bytes_per_site("philox", 2) == 56
+    assert b.algorithmic_bytes_per_site("mt19937", 2) == 64
+    assert b.algorithmic_bytes_per_site("mt19937", 2, 2) == 72
+    assert b.algorithmic_bytes_per_site("parisi_rapuano", 1, 2) == 48
+
+
+def test_traffic_record_needs_the_current_kernel_source(monkeypatch):
+    b = load_bench()
+    with open(os.path.join(ROOT, "profiles", "traffic_sweep_fused_c1.json")) as f:
+        rec = json.load(f)
+    want = rec["hbm_bytes_per_launch"] if rec["kernel_source_sha"] == b.kernel_source_sha() else None
+    assert b.load_traffic("c1") == want
+    assert b.load_traffic("no-such-workload") is None
+    monkeypatch.setattr(b, "kernel_source_sha", lambda: "0" * 16)
+    assert b.load_traffic("c1") is None
+
+
+def test_cpu_baseline_record():
+    b = load_bench()
+    r = b.cpu_baseline(dict(b.WORKLOADS["c0"]), 0.2)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "ps/flip"
+    assert r["value"] > 0 and "L=16" in r["sample"]
