@@ -505,6 +505,45 @@ def test_overlap_rejects_different_couplings(sg):
 
 
 # ---------------------------------------------------------------------------
+# edge cases: sample counts between 1 and 64, empty calls, invalid arguments
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("S", [1, 7, 33, 63])
+@pytest.mark.parametrize("kernel", ["fused2", "fused", "twopass"])
+def test_partial_sample_counts(sg, S, kernel):
+    say("samples", S, kernel)
+    L = 10
+    lat = sg.Lattice(L, S, "minstd", coupling_seed=3, spin_seed=4)
+    lat.set_kernel(kernel)
+    ref = oracle_for(L, S, "minstd", 3, 4)
+    for n in (1, 2, 3):
+        lat.sweep(n, 0.8)
+        ref.sweep(n, 0.8)
+        assert_same(lat.words(), ref, S, f"{S} samples, {kernel}, after {lat.t} sweeps")
+    U, e = lat.energy()
+    assert U.shape == (S,) and np.array_equal(U, ref.unsatisfied())
+    assert np.array_equal(e, (2.0 * U - 3 * L**3) / L**3)
+    sp = lat.spins()  # int8 +-1 per sample and site, against the oracle's own spins
+    assert sp.shape == (S, L**3) and np.array_equal(sp, ref.s)
+
+
+def test_empty_calls_and_invalid_arguments(sg):
+    say("edge arguments")
+    lat = sg.Lattice(8, 64, "minstd", coupling_seed=1, spin_seed=2)
+    w = lat.words()
+    lat.sweep(0, 0.5)
+    sg.sweep_replicas([lat], 0, 0.5)
+    assert lat.t == 0 and np.array_equal(lat.words(), w)
+    for n, beta in ((1, float("nan")), (1, -0.1), (-1, 0.5)):
+        with pytest.raises(sg.SGError) as e:
+            lat.sweep(n, beta)
+        assert e.value.code == sg.SG_EINVAL
+    assert lat.t == 0 and np.array_equal(lat.words(), w)
+    for L, S in ((15, 64), (0, 64), (8, 0), (8, 65)):
+        with pytest.raises(sg.SGError):
+            sg.Lattice(L, S, "minstd")
+
+
+# ---------------------------------------------------------------------------
 # limits and properties
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kernel", ["fused", "twopass"])
