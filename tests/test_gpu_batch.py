@@ -80,6 +80,31 @@ def test_batch_matches_solo_and_oracle(env, graph):
     b.close()
 
 
+def test_batch_small_sides_and_kernel_choices(env):
+    """Sides below the two-sweep march's minimum take one-sweep rounds; a lattice set
+    to the two-pass kernel (which a batch has no form of) takes the default march, one
+    set to the one-sweep kernel one-sweep rounds.  Every result matches the oracle."""
+    sg, stream = env
+    say("batch small sides and kernels")
+    specs = [  # L, coupling seed, spin seed, beta, sweeps, kernel
+        (2, 41, 42, 0.7, 5, "auto"), (4, 43, 44, 0.9, 4, "auto"), (6, 45, 46, 1.1, 3, "auto"),
+        (16, 47, 48, 0.8, 5, "twopass"), (16, 49, 50, 0.8, 4, "fused"), (10, 51, 52, 1.3, 6, "fused2"),
+    ]
+    b = sg.Batch(16, 100000, stream)
+    lats = []
+    for (L, cs, ss, beta, n, kind) in specs:
+        lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
+        lat.set_kernel(kind)
+        b.add(lat, n, beta)
+        lats.append(lat)
+    b.run(1000, 2)
+    assert b.rounds_left() == (0, 0)
+    for lat, (L, cs, ss, beta, n, kind) in zip(lats, specs):
+        assert lat.t == n
+        assert np.array_equal(lat.words(), oracle_words(L, cs, ss, beta, n)), f"L={L} {kind}"
+    b.close()
+
+
 def test_batch_join_leave_in_chunks(env):
     sg, stream = env
     say("batch join/leave")
