@@ -25,13 +25,13 @@ inline int grid_for(int64_t n, int per_thread = 1)
     return (int)g;
 }
 
-__global__ void k_init_couplings(uint64_t *__restrict__ J, int64_t V, uint64_t key)
+__global__ void k_init_couplings(uint64_t *__restrict__ J, int64_t V, int64_t Vj, uint64_t key)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t n = 1ull + 3ull * (uint64_t)i;
         J[i] = sm_out(key, n);
-        J[V + i] = sm_out(key, n + 1);
-        J[2 * V + i] = sm_out(key, n + 2);
+        J[Vj + i] = sm_out(key, n + 1);
+        J[2 * Vj + i] = sm_out(key, n + 2);
     }
 }
 
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64
 hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_init_couplings, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, J, V, key);
+    hipLaunchKernelGGL(k_init_couplings, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, J, V, coupling_stride(L), key);
     return hipGetLastError();
 }
 

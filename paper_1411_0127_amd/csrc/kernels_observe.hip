@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_count_unsat(const uint64_t *__rest
                                                           uint64_t *__restrict__ partials)
 {
     const int64_t V = (int64_t)L * L * L;
+    const int64_t Vj = coupling_stride(L);
     const int64_t LL = (int64_t)L * L;
     VCounter vc;
     vc.clear();
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(kThreads) void k_count_unsat(const uint64_t *__rest
         const int64_t iy = (y + 1 == L) ? i - (int64_t)(L - 1) * L : i + L;
         const int64_t iz = (z + 1 == L) ? i - (V - LL) : i + LL;
         vc.add(J[i] ^ s ^ S[ix]);
-        vc.add(J[V + i] ^ s ^ S[iy]);
-        vc.add(J[2 * V + i] ^ s ^ S[iz]);
+        vc.add(J[Vj + i] ^ s ^ S[iy]);
+        vc.add(J[2 * Vj + i] ^ s ^ S[iz]);
     }
     block_flush(vc, partials);
 }

@@ -32,7 +32,8 @@ __device__ __forceinline__ int64_t cube_index(int L, int c, int64_t z, int64_t y
 }
 
 // nw cube arrays of V words (stride V) -> sliced: dst[k][c][V/2] for k < nw
-__global__ void k_to_sliced(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L, int nw)
+__global__ void k_to_sliced(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L, int nw,
+                            int64_t src_stride)
 {
     const int64_t V = (int64_t)L * L * L, half = V / 2, hx = L / 2;
     for (int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x; g < V; g += (int64_t)gridDim.x * kBlock) {
@@ -41,7 +42,7 @@ __global__ void k_to_sliced(const uint64_t *__restrict__ src, uint64_t *__restri
         const int64_t h = r % hx, row = r / hx, y = row % L, z = row / L;
         const int64_t i = cube_index(L, c, z, y, h);
         for (int k = 0; k < nw; ++k)
-            dst[k * V + g] = src[k * V + i];
+            dst[k * V + g] = src[k * src_stride + i];
     }
 }
 
@@ -105,10 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_twopass_sliced(uint64_t *__restrict_
 
 }  // namespace
 
-hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, hipStream_t s)
+hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, int64_t src_stride,
+                            hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_to_sliced, dim3(grid_for(V)), dim3(kBlock), 0, s, cube, sliced, L, nwords);
+    hipLaunchKernelGGL(k_to_sliced, dim3(grid_for(V)), dim3(kBlock), 0, s, cube, sliced, L, nwords, src_stride);
     return hipGetLastError();
 }
 

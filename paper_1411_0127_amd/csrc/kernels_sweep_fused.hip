@@ -117,9 +117,10 @@ __device__ __forceinline__ void load_plane(const FusedParams &p, int q, const Of
 #pragma unroll
     for (int r = 0; r < NREP; ++r)
         ld_pair(plane_rsrc(p.src[r], qo, pb), o.s, d.slo[r], d.shi[r]);
-    ld_pair(plane_rsrc(p.J, V * 8 + qo, pb), o.s, d.jylo, d.jyhi);
+    const int64_t Vj8 = coupling_stride(p.L) * 8;
+    ld_pair(plane_rsrc(p.J, Vj8 + qo, pb), o.s, d.jylo, d.jyhi);
     ld_pair(plane_rsrc(p.J, qo, pb), o.f, d.jxlo, d.jxhi);
-    ld_pair(plane_rsrc(p.J, 2 * V * 8 + qo, pb), o.f, d.jzlo, d.jzhi);
+    ld_pair(plane_rsrc(p.J, 2 * Vj8 + qo, pb), o.f, d.jzlo, d.jzhi);
 #pragma unroll
     for (int r = 0; r < NREP; ++r) {
         if (PRNG == SG_MT19937) {  // MINSTD draws are computed from the site, nothing to load
@@ -159,9 +160,10 @@ __device__ __forceinline__ void load_plane_at(const FusedParams &p, int64_t qo, 
     const int64_t V8 = LL8 * p.L;
     const uint32_t pb = (uint32_t)LL8;
     ld_pair(plane_rsrc(p.src[0], qo, pb), o.s, d.slo[0], d.shi[0]);
-    ld_pair(plane_rsrc(p.J, V8 + qo, pb), o.s, d.jylo, d.jyhi);
+    const int64_t Vj8 = coupling_stride(p.L) * 8;
+    ld_pair(plane_rsrc(p.J, Vj8 + qo, pb), o.s, d.jylo, d.jyhi);
     ld_pair(plane_rsrc(p.J, qo, pb), o.f, d.jxlo, d.jxhi);
-    ld_pair(plane_rsrc(p.J, 2 * V8 + qo, pb), o.f, d.jzlo, d.jzhi);
+    ld_pair(plane_rsrc(p.J, 2 * Vj8 + qo, pb), o.f, d.jzlo, d.jzhi);
     if (PRNG == SG_MT19937) {  // buffered draws of both sweeps, 4 bytes per site each
         const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[0], qo / 2, pb / 2), o.r, 0, 0);
         const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(p.rnd[0], V8 / 2 + qo / 2, pb / 2), o.r, 0, 0);

@@ -18,6 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, co
 {
     const int64_t LL = (int64_t)L * L;
     const int64_t V = LL * L;
+    const int64_t Vj = coupling_stride(L);
     const int64_t half = V / 2;
     const int hx = L >> 1;
     for (int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x; g < half; g += (int64_t)gridDim.x * kBlock) {
@@ -35,16 +36,16 @@ __global__ __launch_bounds__(kBlock) void k_twopass(uint64_t *__restrict__ S, co
         const int64_t izm = (z == 0) ? i + (V - LL) : i - LL;
         const uint64_t s = S[i];
         if (PRNG == SG_PHILOX) {
-            S[i] = flip_site_ps(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i],
-                                J[ixm], J[V + iym], J[2 * V + izm], (uint64_t)i, (uint64_t)t, (uint32_t)pkey,
+            S[i] = flip_site_ps(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[Vj + i], J[2 * Vj + i],
+                                J[ixm], J[Vj + iym], J[2 * Vj + izm], (uint64_t)i, (uint64_t)t, (uint32_t)pkey,
                                 (uint32_t)(pkey >> 32), T);
         } else {
             const uint32_t R =
                 (PRNG == SG_MINSTD)
                     ? minstd_jump(a, minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk)))
                     : rnd[i];
-            S[i] = flip_site(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[V + i], J[2 * V + i],
-                             J[ixm], J[V + iym], J[2 * V + izm], R, T);
+            S[i] = flip_site(s, S[ixp], S[iyp], S[izp], S[ixm], S[iym], S[izm], J[i], J[Vj + i], J[2 * Vj + i],
+                             J[ixm], J[Vj + iym], J[2 * Vj + izm], R, T);
         }
     }
 }

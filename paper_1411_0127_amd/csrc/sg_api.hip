@@ -67,26 +67,34 @@ int hip_fail(hipError_t e, const char *what)
     return SG_EDEVICE;
 }
 
+// Arrays of a lattice's buffer.  Each starts kSkew bytes past the end of the one
+// before: at power-of-two sides the arrays' sizes are powers of two, and the same
+// plane of every array would otherwise sit at the same low address bits, where the
+// planes a step reads and writes contend for the same memory channels.  With this
+// skew and the pad between the coupling arrays (coupling_stride), the L = 1024 sweep
+// measured 8-10% faster.
+constexpr size_t kSkew = 37 * 256;
+
 Carve carve(int L, int prng, bool own_J)
 {
     const size_t V = (size_t)L * L * L;
     Carve c{};
     size_t off = 0;
     c.spins0 = off;
-    off = align_up(off + 8 * V);
+    off = align_up(off + 8 * V) + kSkew;
     c.spins1 = off;
-    off = align_up(off + 8 * V);
+    off = align_up(off + 8 * V) + kSkew;
     c.J = off;
     if (own_J)
-        off = align_up(off + 24 * V);
+        off = align_up(off + 24 * (size_t)coupling_stride(L)) + kSkew;
     c.mt_state = off;
     if (prng == SG_MT19937)
-        off = align_up(off + (size_t)4 * kMtN * L * L);
+        off = align_up(off + (size_t)4 * kMtN * L * L) + kSkew;
     if (prng == SG_PARISI_RAPUANO)
-        off = align_up(off + (size_t)4 * 64 * L * L);
+        off = align_up(off + (size_t)4 * 64 * L * L) + kSkew;
     c.rbuf = off;
     if (buffered_draws(prng))  // draws of the two sweeps of a two-sweep launch
-        off = align_up(off + 8 * V);
+        off = align_up(off + 8 * V) + kSkew;
     c.scratch = off;
     off = align_up(off + 8 * ((size_t)kMaxReduceBlocks * 64 + 64));
     c.total = off;
@@ -373,9 +381,11 @@ int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host, uin
         return rc;
     }
     lat->coupling_seed = coupling_seed;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     if (J_host) {
-        e = hipMemcpyAsync(lat->J, J_host, (size_t)24 * lat->V, hipMemcpyHostToDevice, lat->stream);
+        for (int d = 0; d < 3 && e == hipSuccess; ++d)
+            e = hipMemcpyAsync(lat->J + d * coupling_stride(L), J_host + (size_t)d * lat->V, (size_t)8 * lat->V,
+                               hipMemcpyHostToDevice, lat->stream);
         lat->coupling_id = (g_coupling_id++) << 1;  // even: caller's couplings
         if (e == hipSuccess)
             e = hipStreamSynchronize(lat->stream);  // J_host is only borrowed
@@ -512,9 +522,9 @@ int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, s
     const int64_t V = lat->V;
     uint64_t *S = static_cast<uint64_t *>(work);
     uint64_t *K = S + V;
-    hipError_t e = launch_to_sliced(lat->spins[lat->cur], S, lat->L, 1, lat->stream);
+    hipError_t e = launch_to_sliced(lat->spins[lat->cur], S, lat->L, 1, lat->V, lat->stream);
     if (e == hipSuccess)
-        e = launch_to_sliced(lat->J, K, lat->L, 3, lat->stream);
+        e = launch_to_sliced(lat->J, K, lat->L, 3, coupling_stride(lat->L), lat->stream);
     if (e != hipSuccess)
         return hip_fail(e, "to sliced layout");
     for (int64_t k = 0; k < nsweeps; ++k) {
@@ -626,7 +636,10 @@ int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n)
         return fail(SG_EINVAL, "NULL argument");
     if (n != (size_t)(3 * lat->V))
         return fail(SG_EINVAL, "n must be 3 L^3");
-    hipError_t e = hipMemcpyAsync(out, lat->J, 8 * n, hipMemcpyDeviceToHost, lat->stream);
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < 3 && e == hipSuccess; ++d)
+        e = hipMemcpyAsync(out + (size_t)d * lat->V, lat->J + d * coupling_stride(lat->L), (size_t)8 * lat->V,
+                           hipMemcpyDeviceToHost, lat->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(lat->stream);
     return check_hip(e, "get couplings");

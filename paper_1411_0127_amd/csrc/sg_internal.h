@@ -85,6 +85,14 @@ struct Thresholds {
     uint64_t t4, t8, t12;
 };
 
+// Words from one coupling array to the next (J[x], J[y], J[z] of a lattice): L^3
+// and a pad.  At power-of-two sides L^3 words are a power of two, and the same
+// plane of the three arrays, which a sweep reads together, would otherwise sit at
+// the same low address bits and contend for the same memory channels.  The pad,
+// 64 KB + 256 bytes, measured best among the pads tried at L = 1024.
+constexpr int64_t kJPadWords = 8224;
+__host__ __device__ inline int64_t coupling_stride(int L) { return (int64_t)L * L * L + kJPadWords; }
+
 // v_bitop3_b32 (gfx950): any bitwise function of three words in one instruction.
 // Its 8-bit table is the function evaluated on the bit patterns 0xF0, 0xCC, 0xAA
 // standing for the first, second and third operand.
@@ -359,7 +367,9 @@ struct SweepArgs {
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
 // Colour-separated layout: conversion of nwords cube arrays (stride V), and a sweep
 // of one lattice (a.src[0] unused) on sliced spins S [2][V/2] and couplings K [3][2][V/2].
-hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, hipStream_t s);
+// nwords arrays of the cube layout, src_stride words apart, to the sliced layout
+hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, int64_t src_stride,
+                            hipStream_t s);
 hipError_t launch_from_sliced(const uint64_t *sliced, uint64_t *cube, int L, hipStream_t s);
 hipError_t launch_sweep_sliced(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s);
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
