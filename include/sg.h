@@ -186,8 +186,8 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t);
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
 /* Planes the two-sweep march keeps in flight (requested planes-2 steps ahead): 5 or
- * 6, or 0 for the default (6 from L = 512 up, 5 below; always 5 for the buffered
- * generators, which reject 6).  Reset by sg_set_kernel. */
+ * 6, or 0 for the default (5; the buffered generators reject 6).  Reset by
+ * sg_set_kernel. */
 int sg_set_ring(sg_lattice *lat, int planes);
 
 /* The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,

@@ -548,7 +548,7 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     jyuhi = S[kF2JyHi * nl + c.iym];
     // In-plane neighbour words of the four updates.  The five-plane form reads all of
     // them before any update (one LDS round trip per step); the six-plane form reads
-    // each update's words where they are used, which measured faster at L = 1024.
+    // each update's words where they are used (the autotuner times both forms).
     constexpr int kSlot[4] = {kF2OldBlue, kF2Red, kF2Blue, kF2Red2};
     uint64_t nb[4][3];
     if (!Fold) {
@@ -715,8 +715,8 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
         const uint32_t zk = minstd_plane_key((uint32_t)wrap(k), p.mk[0]);
         const uint32_t zk1 = zk_prev;  // key of plane k-1, from the previous step
         zk_prev = zk;
-        // six planes in flight (the large-lattice march) count with the fold form,
-        // which measured faster there; five with the shorter three-input form
+        // six planes in flight count with the fold form, five with the shorter
+        // three-input form; the autotuner times both
         constexpr bool kFold = NS == 6;
         fused2_step<PRNG, H, kFold>(p, c, lds, k, do_ab, do_br, do_bb, do_pub, A, B, C, cy, zk, zk1, (uint32_t)wrap(k),
                                     (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
@@ -1200,7 +1200,7 @@ void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk)
         }
 }
 
-int fused2_default_ring(int L) { return L >= 512 ? 6 : 5; }
+int fused2_default_ring(int) { return 5; }  // measured fastest at L = 256 .. 1024
 
 hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, int ring,
                                hipStream_t s)

@@ -780,7 +780,7 @@ int sg_get_kernel(const sg_lattice *lat, int out[6])
     out[2] = ty;
     out[3] = zc;
     out[4] = lat->band > 0 ? lat->band : 1;
-    out[5] = kind == 2 ? (lat->ring ? lat->ring : buffered_draws(lat->prng) ? 5 : fused2_default_ring(lat->L)) : 0;
+    out[5] = kind == 2 ? (lat->ring ? lat->ring : fused2_default_ring(lat->L)) : 0;
     return SG_OK;
 }
 

@@ -379,7 +379,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
 // both sweeps' numbers); replicas share one launch.
 bool fused2_shape_ok(int L, int tile_x, int tile_y, int z_chunk);
 void fused2_default_shape(int L, int &tile_x, int &tile_y, int &z_chunk);
-// ring: planes in flight, 5 or 6 (0 = the default for the side, fused2_default_ring).
+// ring: planes in flight, 5 or 6 (0 = the default, fused2_default_ring).
 hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, int ring,
                                hipStream_t s);
 int fused2_default_ring(int L);
