@@ -14,10 +14,14 @@
  *   flip mask ........................ Sec. 4
  *   psFlip ........................... Sec. 4.1
  *
- * Data layout on the device (one cubic lattice of side L, V = L^3 sites,
- * site index i = x + L*(y + L*z)):
+ * Data layout (one cubic lattice of side L, V = L^3 sites, site index
+ * i = x + L*(y + L*z)):
  *   spins     uint64 S[V]     bit j = sample j, 1 <=> sigma = +1 (Sec. 4 bit mapping)
  *   couplings uint64 J[3][V]  J[d][i] = bond (i, i + d^), d = x,y,z; bit j = 1 <=> J = -1
+ * Host arrays (sg_lattice_create's J_host, sg_get_couplings) are packed as above.  In
+ * the device buffer the three coupling arrays, like the other arrays of a lattice,
+ * are placed apart by a small skew beyond their length (so that the same plane of
+ * each does not fall on the same memory channels); the buffer's layout is private.
  * One sweep = every red site (x+y+z even) once, then every blue site once.
  *
  * Random streams (this library's convention; all keyed, so results do not depend
