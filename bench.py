@@ -47,7 +47,7 @@ WORKLOADS = {
                     "T uniform [0.6,1.4], sweeps 10^U(2,4) (times sweep_scale), admitted by HBM budget, "
                     "continuous batching, MINSTD"),
     # L=16 cube, 1 sample, energy after every sweep
-    "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=None,
+    "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=None, samples=1,
                desc="L=16 periodic cube, 1 sample, T=0.7, 1000 sweeps per step, MINSTD"),
 }
 
@@ -96,10 +96,11 @@ def run_gpu(args, wl):
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     L, R, beta, nsw = wl["L"], wl["replicas"], wl["beta"], args.sweeps or wl["sweeps"]
+    S = wl.get("samples", 64)  # coded samples per word; flips are counted for these only
     V = L**3
 
     def measure(prng):
-        base = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
+        base = sg.Lattice(L, S, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
         lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
         shape = None
         if args.tile:
@@ -159,7 +160,7 @@ def run_gpu(args, wl):
             energy_per_spin=[float(x) for x in last[0][1][:4]],
             tile=shape,
         )
-        flips = R * 64 * V * nsw
+        flips = R * S * V * nsw
         res["ps_per_flip"] = res["ms_per_step"] * 1e9 / flips
         res["sweep_ps_per_flip"] = (sum(sweep_ms) / args.steps) * 1e9 / flips
         for l in lats:
@@ -392,7 +393,7 @@ def main():
         "config": {
             "workload": wl["desc"],
             "L": L,
-            "samples_per_word": 64,
+            "samples_per_word": wl.get("samples", 64),
             "replicas": R,
             "sweeps_per_step": args.sweeps or wl["sweeps"],
             "prng": wl["prng"],
