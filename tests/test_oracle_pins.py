@@ -516,9 +516,11 @@ def test_per_sample_metropolis_reaches_the_gibbs_law_on_2x2x4(beta):
 
 # ---------------------------------------------------------------------------
 # Parisi-Rapuano (Sec. 3).  No independent implementation or published values of
-# its 32-bit words are at hand ("parity unpinned" for the full words): the pins are
-# the linear recurrence of the lowest bit, which follows from addition mod 2 (a
-# wrong lag breaks it), uniformity, and the Gibbs law of the dynamics it drives.
+# its 32-bit words are at hand.  The pins are the linear recurrence of the lowest
+# bit, which follows from addition mod 2 (a wrong lag breaks it); the words
+# recovered through the lag-61 output rule, which must add with carries bit by bit
+# (XOR in place of + breaks it, a wrong output lag too); uniformity; and the Gibbs
+# law of the dynamics it drives.
 # ---------------------------------------------------------------------------
 def test_parisi_rapuano_lowest_bit_obeys_the_lagged_xor_recurrence():
     seeds = si.pr_seeds(4, 11, 0)
@@ -530,6 +532,57 @@ def test_parisi_rapuano_lowest_bit_obeys_the_lagged_xor_recurrence():
         # the neighbouring lags do not hold
         assert not np.array_equal(b[n], b[n - 23] ^ b[n - 55])
         assert not np.array_equal(b[n], b[n - 24] ^ b[n - 54])
+
+
+def _pr_recover_x(seed, R):
+    """Undo the output rule R_n = x_n XOR x_{n-61}: starting from the 61 seed words
+    x_{-61} .. x_{-1}, x_n = R_n XOR x_{n-61} gives every later x_n from the numbers
+    alone.  Returns x_{-61} .. x_{N-1}."""
+    x = np.empty(61 + R.size, dtype=np.uint32)
+    x[:61] = seed
+    for n in range(R.size):
+        x[61 + n] = R[n] ^ x[n]
+    return x
+
+
+def test_parisi_rapuano_recovered_words_add_with_carries():
+    """The words recovered through the lag-61 output rule must obey the additive
+    recurrence bit by bit: bit 0 of x_n is the XOR of bit 0 of x_{n-24} and x_{n-55},
+    bit 1 adds the carry out of bit 0, and a ripple-carry adder written out with
+    boolean operations reproduces all 32 bits.  A generator that XORs instead of
+    adding fails the carry checks, and one whose output lag is not 61 makes the
+    recovered words fail even the lowest-bit recurrence."""
+    seeds = si.pr_seeds(4, 11, 0)
+    for c in (0, 6, 13):
+        R = oracle.pr_outputs(seeds[c], 5000)
+        x = _pr_recover_x(seeds[c], R)
+        n = np.arange(61, x.size)  # positions of x_0, x_1, ...
+        a, b, s = x[n - 24], x[n - 55], x[n]
+        bit = lambda w, k: ((w >> np.uint32(k)) & np.uint32(1)).astype(np.uint8)
+        assert np.array_equal(bit(s, 0), bit(a, 0) ^ bit(b, 0))
+        assert np.array_equal(bit(s, 1), bit(a, 1) ^ bit(b, 1) ^ (bit(a, 0) & bit(b, 0)))
+        carry = np.zeros(n.size, dtype=np.uint8)
+        for k in range(32):
+            ak, bk = bit(a, k), bit(b, k)
+            assert np.array_equal(bit(s, k), ak ^ bk ^ carry), k
+            carry = (ak & bk) | (carry & (ak ^ bk))
+        # the carries matter: XOR alone differs from the recovered words
+        assert (s != (a ^ b)).mean() > 0.7
+
+
+def test_parisi_rapuano_output_lag_is_61():
+    """The recovery above only closes at lag 61: undoing the output with lag 60 or
+    62 leaves words that break the lowest-bit recurrence."""
+    seeds = si.pr_seeds(4, 5, 1)
+    R = oracle.pr_outputs(seeds[3], 3000)
+    for lag in (60, 62):
+        x = np.empty(lag + R.size, dtype=np.uint32)
+        x[:lag] = np.resize(seeds[3], lag)
+        for k in range(R.size):
+            x[lag + k] = R[k] ^ x[k]
+        n = np.arange(lag + 61, x.size)
+        b0 = x & np.uint32(1)
+        assert not np.array_equal(b0[n], b0[n - 24] ^ b0[n - 55]), lag
 
 
 def test_parisi_rapuano_outputs_are_uniform_and_streams_differ():
