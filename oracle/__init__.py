@@ -57,7 +57,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.oc_gibbs.restype = ci
         L.oc_run.argtypes = [ci, ci, ci, ci, p, p, ci, p, i64, p, p]
         L.oc_run.restype = ci
+        L.oc_run_threads.argtypes = [ci, ci, ci, ci, p, p, ci, p, i64, p, p, ci]
+        L.oc_run_threads.restype = ci
         L.oc_philox4x32_10.argtypes = [p, p, p]
         L.oc_pr_sizeof.restype = i64
         L.oc_pr_init_many.argtypes = [i64, p, p]
@@ -202,6 +204,9 @@ class OracleLattice:
         self.J = np.ascontiguousarray(couplings_from_words(J_words, self.S))
         self.s = np.ascontiguousarray(spins_from_words(spin_words, self.S))
         self.t = 0
+        self._init_streams(stream_seeds)
+
+    def _init_streams(self, stream_seeds):
         L = lib()
         if self.prng == MINSTD:
             self.state = np.ascontiguousarray(np.asarray(stream_seeds, dtype=np.uint32).copy())
@@ -221,6 +226,33 @@ class OracleLattice:
             self.state = np.zeros(seeds.shape[0] * nbytes, dtype=np.uint8)
             L.oc_mt_init_many(seeds.shape[0], _ptr(self.state), _ptr(seeds))
         self.last_R = np.zeros(self.V, dtype=np.uint32)
+
+    @classmethod
+    def from_bits(cls, extents, J_bits, spin_bits, prng, stream_seeds):
+        """Lattice of S = len(spin_bits) samples given as bit planes: J_bits uint8
+        [S][3][V], spin_bits uint8 [S][V] (bit 1 <=> J = -1, s = +1, as in the
+        words).  The arrays are converted in place to the +-1 bytes the oracle
+        works on, so large lattices need no 64-bit words."""
+        self = cls.__new__(cls)
+        Lx, Ly, Lz = extents
+        assert Lx % 2 == 0 and Ly % 2 == 0 and Lz % 2 == 0, "extents must be even"
+        self.Lx, self.Ly, self.Lz = int(Lx), int(Ly), int(Lz)
+        self.V = self.Lx * self.Ly * self.Lz
+        J = np.ascontiguousarray(J_bits, dtype=np.uint8).view(np.int8)
+        s = np.ascontiguousarray(spin_bits, dtype=np.uint8).view(np.int8)
+        self.S = int(s.shape[0])
+        assert 1 <= self.S <= 64 and J.shape == (self.S, 3, self.V) and s.shape == (self.S, self.V)
+        for a in J:
+            a *= -2
+            a += 1  # bit 1 -> J = -1, bit 0 -> +1
+        for a in s:
+            a *= 2
+            a -= 1  # bit 1 -> s = +1, bit 0 -> -1
+        self.J, self.s = J, s
+        self.prng = int(prng)
+        self.t = 0
+        self._init_streams(stream_seeds)
+        return self
 
     def draws(self) -> np.ndarray:
         """Random numbers of the next sweep (advances the streams): uint32 [V], or
@@ -254,13 +286,19 @@ class OracleLattice:
             self.last_R = R
             self.t += 1
 
-    def run(self, n: int, beta: float, record: bool = False):
-        """n sweeps in one C call; returns U[t][j] after every sweep if ``record``."""
+    def run(self, n: int, beta: float, record: bool = False, threads: int = 1):
+        """n sweeps in one C call; returns U[t][j] after every sweep if ``record``.
+        threads > 1 spreads the draws over sites or columns and each colour pass
+        over planes (same result: sites of one colour are independent)."""
         n = int(n)
         T = thresholds(beta, self.prng)
         U = np.zeros((n, self.S), dtype=np.int64) if record else None
-        rc = lib().oc_run(self.Lx, self.Ly, self.Lz, self.S, _ptr(self.s), _ptr(self.J), self.prng,
-                          _ptr(self.state), n, _ptr(T), _ptr(U) if record else None)
+        if int(threads) > 1:
+            rc = lib().oc_run_threads(self.Lx, self.Ly, self.Lz, self.S, _ptr(self.s), _ptr(self.J), self.prng,
+                                      _ptr(self.state), n, _ptr(T), _ptr(U) if record else None, int(threads))
+        else:
+            rc = lib().oc_run(self.Lx, self.Ly, self.Lz, self.S, _ptr(self.s), _ptr(self.J), self.prng,
+                              _ptr(self.state), n, _ptr(T), _ptr(U) if record else None)
         if rc != 0:
             raise MemoryError("oracle run failed")
         self.t += n

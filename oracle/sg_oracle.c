@@ -21,6 +21,7 @@
  *     handed in by the caller; the generators that produce it are below.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -268,38 +269,48 @@ static inline int64_t idx(int Lx, int Ly, int x, int y, int z)
     return x + (int64_t)Lx * (y + (int64_t)Ly * z);
 }
 
+/* Update the sites of one colour in planes z0 .. z1-1.  Sites of one colour
+ * have no bond between them (checkerboard, Sec. 1), so the planes of a colour
+ * pass may be visited in any order, or split among threads, with the same
+ * result. */
+static void sweep_colour(int Lx, int Ly, int Lz, int8_t *s, const int8_t *J, const uint32_t *R,
+                         const uint64_t T[3], int colour, int z0, int z1)
+{
+    const int64_t V = (int64_t)Lx * Ly * Lz;
+    for (int z = z0; z < z1; ++z)
+        for (int y = 0; y < Ly; ++y)
+            for (int x = 0; x < Lx; ++x) {
+                if (((x + y + z) & 1) != colour)
+                    continue;
+                const int xp = (x + 1) % Lx, xm = (x + Lx - 1) % Lx;
+                const int yp = (y + 1) % Ly, ym = (y + Ly - 1) % Ly;
+                const int zp = (z + 1) % Lz, zm = (z + Lz - 1) % Lz;
+                const int64_t i = idx(Lx, Ly, x, y, z);
+                /* local field: the three bonds the site owns and the three
+                 * bonds its -d neighbours own towards it */
+                int h = J[0 * V + i] * s[idx(Lx, Ly, xp, y, z)]
+                      + J[1 * V + i] * s[idx(Lx, Ly, x, yp, z)]
+                      + J[2 * V + i] * s[idx(Lx, Ly, x, y, zp)]
+                      + J[0 * V + idx(Lx, Ly, xm, y, z)] * s[idx(Lx, Ly, xm, y, z)]
+                      + J[1 * V + idx(Lx, Ly, x, ym, z)] * s[idx(Lx, Ly, x, ym, z)]
+                      + J[2 * V + idx(Lx, Ly, x, y, zm)] * s[idx(Lx, Ly, x, y, zm)];
+                /* H = -sum J s_i s_k, so flipping s_i changes it by 2 s_i h */
+                const int dE = 2 * s[i] * h;
+                int accept;
+                if (dE <= 0)
+                    accept = 1;
+                else
+                    accept = (uint64_t)R[i] < T[dE / 4 - 1];
+                if (accept)
+                    s[i] = (int8_t)(-s[i]);
+            }
+}
+
 void oc_sweep(int Lx, int Ly, int Lz, int8_t *s, const int8_t *J, const uint32_t *R,
               const uint64_t T[3])
 {
-    const int64_t V = (int64_t)Lx * Ly * Lz;
     for (int colour = 0; colour < 2; ++colour)
-        for (int z = 0; z < Lz; ++z)
-            for (int y = 0; y < Ly; ++y)
-                for (int x = 0; x < Lx; ++x) {
-                    if (((x + y + z) & 1) != colour)
-                        continue;
-                    const int xp = (x + 1) % Lx, xm = (x + Lx - 1) % Lx;
-                    const int yp = (y + 1) % Ly, ym = (y + Ly - 1) % Ly;
-                    const int zp = (z + 1) % Lz, zm = (z + Lz - 1) % Lz;
-                    const int64_t i = idx(Lx, Ly, x, y, z);
-                    /* local field: the three bonds the site owns and the three
-                     * bonds its -d neighbours own towards it */
-                    int h = J[0 * V + i] * s[idx(Lx, Ly, xp, y, z)]
-                          + J[1 * V + i] * s[idx(Lx, Ly, x, yp, z)]
-                          + J[2 * V + i] * s[idx(Lx, Ly, x, y, zp)]
-                          + J[0 * V + idx(Lx, Ly, xm, y, z)] * s[idx(Lx, Ly, xm, y, z)]
-                          + J[1 * V + idx(Lx, Ly, x, ym, z)] * s[idx(Lx, Ly, x, ym, z)]
-                          + J[2 * V + idx(Lx, Ly, x, y, zm)] * s[idx(Lx, Ly, x, y, zm)];
-                    /* H = -sum J s_i s_k, so flipping s_i changes it by 2 s_i h */
-                    const int dE = 2 * s[i] * h;
-                    int accept;
-                    if (dE <= 0)
-                        accept = 1;
-                    else
-                        accept = (uint64_t)R[i] < T[dE / 4 - 1];
-                    if (accept)
-                        s[i] = (int8_t)(-s[i]);
-                }
+        sweep_colour(Lx, Ly, Lz, s, J, R, T, colour, 0, Lz);
 }
 
 /* Number of unsatisfied bonds U (bonds with -J s_i s_k = +1); the energy of
@@ -406,6 +417,144 @@ int oc_run(int Lx, int Ly, int Lz, int S, int8_t *s, const int8_t *J, int prng, 
             oc_sweep(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V, R + (prng == 2 ? (int64_t)j * V : 0), T);
             if (U)
                 U[t * S + j] = oc_unsatisfied(Lx, Ly, Lz, s + (int64_t)j * V, J + (int64_t)j * 3 * V);
+        }
+    }
+    free(R);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The same run spread over host threads, for timing the oracle on all cores. */
+/* Nothing is computed differently: the draws of a sweep are per site (MINSTD, */
+/* per-sample numbers) or per column (MT19937, Parisi-Rapuano), so ranges of   */
+/* sites or columns go to different threads; a colour pass is split by planes, */
+/* which is allowed because sites of one colour are independent (Sec. 1); the  */
+/* two colour passes and the sweeps stay in order.  The result equals oc_run's. */
+/* ------------------------------------------------------------------------- */
+typedef void (*range_fn)(void *ctx, int64_t lo, int64_t hi);
+typedef struct {
+    range_fn fn;
+    void *ctx;
+    int64_t lo, hi;
+} range_job;
+
+static void *range_main(void *p)
+{
+    range_job *j = (range_job *)p;
+    j->fn(j->ctx, j->lo, j->hi);
+    return NULL;
+}
+
+/* fn(ctx, lo, hi) over [0, n) in nthreads contiguous pieces; a piece whose
+ * thread cannot be started runs on the calling thread. */
+static void parallel_for(int nthreads, int64_t n, range_fn fn, void *ctx)
+{
+    enum { kMaxThreads = 256 };
+    if (nthreads > kMaxThreads)
+        nthreads = kMaxThreads;
+    if (nthreads > n)
+        nthreads = (int)n;
+    if (nthreads <= 1) {
+        fn(ctx, 0, n);
+        return;
+    }
+    pthread_t th[kMaxThreads];
+    range_job job[kMaxThreads];
+    int started[kMaxThreads];
+    for (int k = 0; k < nthreads; ++k) {
+        job[k].fn = fn;
+        job[k].ctx = ctx;
+        job[k].lo = n * k / nthreads;
+        job[k].hi = n * (k + 1) / nthreads;
+        started[k] = pthread_create(&th[k], NULL, range_main, &job[k]) == 0;
+        if (!started[k])
+            fn(ctx, job[k].lo, job[k].hi);
+    }
+    for (int k = 0; k < nthreads; ++k)
+        if (started[k])
+            pthread_join(th[k], NULL);
+}
+
+typedef struct {
+    int Lx, Ly, Lz, S, prng, colour;
+    int8_t *s;
+    const int8_t *J;
+    void *state;
+    const uint32_t *R;
+    uint32_t *Rout;
+    const uint64_t *T;
+    uint64_t key;
+    int64_t t;
+} run_ctx;
+
+static void draws_range(void *p, int64_t lo, int64_t hi)
+{
+    run_ctx *c = (run_ctx *)p;
+    const int64_t LL = (int64_t)c->Lx * c->Ly, V = LL * c->Lz;
+    if (c->prng == 0) { /* sites lo..hi-1 */
+        uint32_t *st = (uint32_t *)c->state;
+        for (int64_t i = lo; i < hi; ++i) {
+            st[i] = oc_minstd_next(st[i]);
+            c->Rout[i] = st[i];
+        }
+    } else if (c->prng == 1 || c->prng == 3) { /* columns lo..hi-1 */
+        for (int64_t col = lo; col < hi; ++col)
+            for (int z = 0; z < c->Lz; ++z)
+                c->Rout[z * LL + col] = c->prng == 1 ? oc_mt_next(&((oc_mt *)c->state)[col])
+                                                     : oc_pr_next(&((oc_pr *)c->state)[col]);
+    } else { /* per-sample numbers of sites lo..hi-1 */
+        uint32_t r[64];
+        for (int64_t i = lo; i < hi; ++i) {
+            sample_draws_n(c->key, i, c->t, c->S, r);
+            for (int j = 0; j < c->S; ++j)
+                c->Rout[(int64_t)j * V + i] = r[j];
+        }
+    }
+}
+
+static void colour_range(void *p, int64_t lo, int64_t hi)
+{
+    run_ctx *c = (run_ctx *)p;
+    sweep_colour(c->Lx, c->Ly, c->Lz, c->s, c->J, c->R, c->T, c->colour, (int)lo, (int)hi);
+}
+
+int oc_run_threads(int Lx, int Ly, int Lz, int S, int8_t *s, const int8_t *J, int prng, void *state,
+                   int64_t nsweeps, const uint64_t T[3], int64_t *U, int nthreads)
+{
+    const int64_t LL = (int64_t)Lx * Ly, V = LL * Lz;
+    uint32_t *R = (uint32_t *)malloc((size_t)V * (prng == 2 ? S : 1) * sizeof(uint32_t));
+    if (!R)
+        return -2;
+    run_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.Lx = Lx;
+    c.Ly = Ly;
+    c.Lz = Lz;
+    c.S = S;
+    c.prng = prng;
+    c.state = state;
+    c.Rout = R;
+    c.T = T;
+    for (int64_t t = 0; t < nsweeps; ++t) {
+        if (prng == 2) {
+            uint64_t *ks = (uint64_t *)state;
+            c.key = ks[0];
+            c.t = (int64_t)ks[1];
+            parallel_for(nthreads, V, draws_range, &c);
+            ks[1] += 1;
+        } else {
+            parallel_for(nthreads, (prng == 0) ? V : LL, draws_range, &c);
+        }
+        for (int j = 0; j < S; ++j) {
+            c.s = s + (int64_t)j * V;
+            c.J = J + (int64_t)j * 3 * V;
+            c.R = R + (prng == 2 ? (int64_t)j * V : 0);
+            for (int colour = 0; colour < 2; ++colour) {
+                c.colour = colour;
+                parallel_for(nthreads, Lz, colour_range, &c);
+            }
+            if (U)
+                U[t * S + j] = oc_unsatisfied(Lx, Ly, Lz, c.s, c.J);
         }
     }
     free(R);

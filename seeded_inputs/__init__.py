@@ -194,3 +194,73 @@ def gauge_words(L: int, gauge_seed: int) -> np.ndarray:
 
 def site_index(L: int, x, y, z):
     return np.asarray(x) + L * (np.asarray(y) + L * np.asarray(z))
+
+
+# ---------------------------------------------------------------------------
+# Bit planes at large sizes (planes.c: the same definitions in C, threaded), for
+# lattices whose 64-sample words do not fit in host memory (L = 1024: 24 GiB of
+# coupling words).  Built with gcc next to this file.
+# ---------------------------------------------------------------------------
+import ctypes as _ct
+import os as _os
+import subprocess as _sp
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_PSRC = _os.path.join(_HERE, "planes.c")
+_PLIB = _os.path.join(_HERE, "libsi_planes.so")
+_plib = None
+
+
+def build_planes(force: bool = True) -> str:
+    if force or not _os.path.exists(_PLIB):
+        tmp = _PLIB + ".tmp"
+        _sp.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", "-o", tmp, _PSRC])
+        _os.replace(tmp, _PLIB)
+    return _PLIB
+
+
+def _planes_lib():
+    global _plib
+    if _plib is None:
+        if not _os.path.exists(_PLIB) or _os.path.getmtime(_PLIB) < _os.path.getmtime(_PSRC):
+            build_planes()
+        lib = _ct.CDLL(_PLIB)
+        p = _ct.c_void_p
+        lib.si_coupling_bits.argtypes = [_ct.c_int64, _ct.c_uint64, p, _ct.c_int, p, _ct.c_int]
+        lib.si_spin_bits.argtypes = [_ct.c_int64, _ct.c_uint64, p, _ct.c_int, p, _ct.c_int]
+        lib.si_minstd_seeds.argtypes = [_ct.c_int, _ct.c_uint32, p, _ct.c_int]
+        _plib = lib
+    return _plib
+
+
+def _threads(threads):
+    return int(threads) if threads else max(1, min(16, _os.cpu_count() or 1))
+
+
+def coupling_bits(L: int, coupling_seed: int, planes, threads: int = 0) -> np.ndarray:
+    """uint8 [len(planes)][3][L^3]: bit p of every coupling word, for p in planes
+    (the same bits as coupling_words(L, coupling_seed) >> p & 1)."""
+    pl = np.ascontiguousarray(np.asarray(planes, dtype=np.int32))
+    V = L**3
+    bits = np.empty((pl.size, 3, V), dtype=np.uint8)
+    _planes_lib().si_coupling_bits(V, key(coupling_seed, TAG_J, 0), pl.ctypes.data, pl.size, bits.ctypes.data,
+                                   _threads(threads))
+    return bits
+
+
+def spin_bits(L: int, spin_seed: int, replica: int, planes, threads: int = 0) -> np.ndarray:
+    """uint8 [len(planes)][L^3]: bit p of every initial spin word."""
+    pl = np.ascontiguousarray(np.asarray(planes, dtype=np.int32))
+    V = L**3
+    bits = np.empty((pl.size, V), dtype=np.uint8)
+    _planes_lib().si_spin_bits(V, key(spin_seed, TAG_SPIN, replica), pl.ctypes.data, pl.size, bits.ctypes.data,
+                               _threads(threads))
+    return bits
+
+
+def minstd_seeds_threaded(L: int, spin_seed: int, replica: int, threads: int = 0) -> np.ndarray:
+    """minstd_seeds(L, spin_seed, replica), computed in C on several threads."""
+    s = np.empty(L**3, dtype=np.uint32)
+    _planes_lib().si_minstd_seeds(L, key(spin_seed, TAG_MINSTD, replica) & 0xFFFFFFFF, s.ctypes.data,
+                                  _threads(threads))
+    return s
