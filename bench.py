@@ -1,21 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the checkerboard Metropolis sweep on one MI355X.
 
-A step is one job of the workload: ``sweeps_per_step`` sweeps of every replica
-(couplings read once per sweep for both replicas), then the energy of each replica
-and their overlap read back.  Lattices, couplings and streams are created on the
-device before the timed region.  The JSON line reports ps per spin flip
-(psFlip, lower is better) as ``value``; the roofline object covers the sweep kernel,
-whose average duration per launch is measured with HIP events on the stream the
-kernel runs on.  ``cpu_baseline`` times the CPU oracle on a bounded sample of the
-same workload.
+Headline (``--workload c2``, the default): one L=1024 lattice of 64 coded
+samples at T=1.1, MINSTD.  A step is ``sweeps_per_step`` (100) sweeps followed
+by the energy of every sample read back.  The lattice, its couplings and its
+streams are created on the device before the timed region; the sweep kernel is
+autotuned there too.  ``value`` is ps per spin flip (psFlip, Sec. 4.1 of the
+paper, counted over 64-bit words: time / (samples x replicas x L^3 x sweeps)).
+
+The same run adds, outside the timed region:
+  roofline       the dominant kernel's algorithmic bytes per launch over its
+                 average launch time (HIP events on the stream it runs on);
+  measured_peak  read-only, copy and fill bandwidth of probe kernels over 4 GiB
+                 buffers (the paper's analog: a device copy's peak, Sec. 4.1);
+  depth1         the one-sweep-per-launch kernel on the same lattice, whose
+                 bandwidth is the fraction read at temporal depth 1;
+  c1             L=256, two replicas (MINSTD, MT19937, Parisi-Rapuano);
+  c3             the batched mix of 256 lattices, against plain launches;
+  c4             the served Poisson job stream: p50/p99 latency, psFlip;
+  cpu_baseline   the CPU oracle on bit-planes 0 and 63 of the same L=1024
+                 lattice, threaded over all host cores, plus the L=16 one-sample
+                 configuration on one core and on all cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -26,29 +38,22 @@ METRIC = "ps per spin flip (psFlip) + HBM GB/s, single lattice and batched; job 
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    # L=256 cube, 64 samples per word, 2 replicas sharing the couplings, T=0.7
+    "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", samples=1, energy_every_sweep=True,
+               desc="c0: L=16 periodic cube, 1 sample, J=+-1 (p=1/2) and spins from seed, T=0.7, 1000 sweeps "
+                    "per step with the energy per spin read after every sweep, MINSTD per-site streams"),
     "c1": dict(L=256, replicas=2, beta=1 / 0.7, sweeps=1000, prng="minstd",
-               variant=("mt19937", "parisi_rapuano", "philox"),
-               desc="L=256 periodic cube, 64 samples multispin-coded per uint64, 2 replicas sharing "
-                    "J=+-1 (p=1/2), random start, T=0.7, 1000 sweeps per step, MINSTD per-site streams "
-                    "(variants: MT19937 and Parisi-Rapuano per-column streams; one Philox number per sample)"),
-    # L=1024 cube, 64 samples, one replica, T=1.1, 100 sweeps
-    "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd", variant=None,
-               desc="L=1024 periodic cube, 64 samples multispin-coded per uint64, J=+-1 (p=1/2), "
-                    "random start, T=1.1, 100 sweeps per step, MINSTD per-site streams"),
-    # 256 lattices in one batch: L from {32,...,512}, T in [0.5, 1.5], 100-2000 sweeps
-    "c3": dict(L=0, replicas=1, beta=0, sweeps=0, prng="minstd", variant=None,
-               desc="batch of 256 lattices, L uniform over {32,64,128,256,512}, 64 samples each, T uniform "
-                    "[0.5,1.5], sweeps uniform 100-2000 (times sweep_scale), all present at t=0, admitted by "
-                    "HBM budget, one launch per round, MINSTD"),
-    # Poisson job stream at 50 jobs/s: L from {64,...,512}, T in [0.6, 1.4], 10^U(2,4) sweeps
-    "c4": dict(L=0, replicas=1, beta=0, sweeps=0, prng="minstd", variant=None,
-               desc="served Poisson job stream (mean 50 jobs/s), L uniform over {64,128,256,512}, 64 samples, "
-                    "T uniform [0.6,1.4], sweeps 10^U(2,4) (times sweep_scale), admitted by HBM budget, "
-                    "continuous batching, MINSTD"),
-    # L=16 cube, 1 sample, energy after every sweep
-    "c0": dict(L=16, replicas=1, beta=1 / 0.7, sweeps=1000, prng="minstd", variant=None, samples=1,
-               desc="L=16 periodic cube, 1 sample, T=0.7, 1000 sweeps per step, MINSTD"),
+               desc="c1: L=256 periodic cube, 64 samples multispin-coded per uint64, 2 replicas sharing J=+-1 "
+                    "(p=1/2), random start, T=0.7, 1000 sweeps per step, MINSTD per-site streams"),
+    "c2": dict(L=1024, replicas=1, beta=1 / 1.1, sweeps=100, prng="minstd",
+               desc="c2: L=1024 periodic cube, 64 samples multispin-coded per uint64 (8 GiB spins, 24 GiB "
+                    "couplings), J=+-1 (p=1/2), random start, T=1.1, 100 sweeps per step, MINSTD per-site "
+                    "streams"),
+}
+MIX_DESC = {
+    "c3": "c3: batch of 256 lattices, L uniform over {32,64,128,256,512}, 64 samples each, T uniform [0.5,1.5], "
+          "sweeps uniform 100-2000 (times sweep_scale), all present at t=0, admitted by HBM budget, MINSTD",
+    "c4": "c4: served Poisson job stream (mean 50 jobs/s), L uniform over {64,128,256,512}, 64 samples, T uniform "
+          "[0.6,1.4], sweeps 10^U(2,4) (times sweep_scale), admitted by HBM budget, continuous batching, MINSTD",
 }
 
 
@@ -65,6 +70,12 @@ def algorithmic_bytes_per_site(prng: str, replicas: int, sweeps_per_launch: int 
     """
     draws = 4 * sweeps_per_launch if prng in ("mt19937", "parisi_rapuano") else 0
     return 24 + replicas * (16 + draws)
+
+
+def batch_bytes(jobs) -> int:
+    """Compulsory bytes of a batched mix: 40 B per site and round, a round being
+    two sweeps on the two-sweep march (one for an odd last sweep)."""
+    return sum(40 * j.L**3 * ((j.nsweeps + 1) // 2) for j in jobs)
 
 
 def kernel_source_sha() -> str:
@@ -87,135 +98,194 @@ def load_traffic(workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(args, wl):
+def host_threads() -> int:
+    """Host threads this job may use: the box's share (OMP_NUM_THREADS), else the
+    cores the process may run on, at most 16."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ---------------------------------------------------------------------------
+# single lattice (c0, c1, c2)
+# ---------------------------------------------------------------------------
+class Marker:
+    """A one-workgroup fill of 16 bytes queued before and after the timed region,
+    so that a kernel trace of this program can be cut to the timed launches."""
+
+    def __init__(self, torch, sg, stream):
+        self.sg, self.stream = sg, stream
+        self.buf = torch.empty(256, dtype=torch.uint8, device="cuda:0")
+
+    def __call__(self):
+        self.sg.probe_bandwidth("fill", self.buf, None, 16, self.stream, blocks=1)
+
+
+def run_single(args, wl, prng=None, steps=None, warmup=None, marker=None, depth1=False):
     import torch
 
     from paper_1411_0127_amd import sg
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    prng = prng or wl["prng"]
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     L, R, beta, nsw = wl["L"], wl["replicas"], wl["beta"], args.sweeps or wl["sweeps"]
     S = wl.get("samples", 64)  # coded samples per word; flips are counted for these only
     V = L**3
+    base = sg.Lattice(L, S, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
+    lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
+    if args.tile:
+        parts = args.tile.split(",")
+        kind = parts[0] if not parts[0].isdigit() else "fused"
+        nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
+        buffered = prng in ("mt19937", "parisi_rapuano")
+        for l in lats:
+            l.set_kernel(kind, *nums[:4])
+            if len(nums) > 4:
+                l.set_ring(5 if buffered else nums[4])  # buffered draws: five planes in flight
+    elif args.kernel == "auto" and L >= 32:
+        # pick the kernel and tile on these lattices, before the timed region
+        sg.autotune(lats[:2], reps=5)
+        shape = lats[0].kernel()
+        for l in lats[2:]:
+            l.set_kernel(shape[0], *shape[1:5])
+    elif args.kernel != "auto":
+        for l in lats:
+            l.set_kernel(args.kernel)
+    shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
+    per_launch = 2 if shape[0] == "fused2" and nsw % 2 == 0 else 1
+    every = wl.get("energy_every_sweep", False)
 
-    def measure(prng):
-        base = sg.Lattice(L, S, prng, coupling_seed=1, spin_seed=2, replica=0, device=dev, stream=stream)
-        lats = [base] + [sg.Lattice.replica_of(base, spin_seed=2, replica=r) for r in range(1, R)]
-        shape = None
-        if args.tile:
-            parts = args.tile.split(",")
-            kind = parts[0] if not parts[0].isdigit() else "fused"
-            nums = tuple(int(v) for v in (parts[1:] if not parts[0].isdigit() else parts))
-            buffered = prng in ("mt19937", "parisi_rapuano")
-            for l in lats:
-                l.set_kernel(kind, *nums[:4])
-                if len(nums) > 4:
-                    l.set_ring(5 if buffered else nums[4])  # buffered draws: five planes in flight
-        elif args.kernel == "auto":
-            # pick the fused kernel and tile on these lattices, before the timed region
-            shape, _ = sg.autotune(lats[:2], reps=5)
-            for l in lats[2:]:
-                l.set_kernel(shape[0], *shape[1:])
-        else:
-            for l in lats:
-                l.set_kernel(args.kernel)
-        if shape is not None or args.tile:
-            shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
-        kind = shape[0] if shape else args.kernel
-        per_launch = 2 if kind in ("fused2", "auto") and nsw % 2 == 0 else 1
-
-        def step(ev=None):
-            if ev is not None:
-                ev[0].record(stream)
-            if R == 1:
-                lats[0].sweep(nsw, beta)
-            else:
-                sg.sweep_replicas(lats, nsw, beta)
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        if every:
+            out = []
+            for _ in range(nsw):
+                lats[0].sweep(1, beta)
+                out.append(lats[0].energy())
             if ev is not None:
                 ev[1].record(stream)
-            out = [l.energy() for l in lats]
-            if R >= 2:
-                out.append(sg.overlap(lats[0], lats[1]))
-            return out
+            return [out[-1]]
+        if R == 1:
+            lats[0].sweep(nsw, beta)
+        else:
+            sg.sweep_replicas(lats, nsw, beta)
+        if ev is not None:
+            ev[1].record(stream)
+        out = [l.energy() for l in lats]
+        if R >= 2:
+            out.append(sg.overlap(lats[0], lats[1]))
+        return out
 
-        for _ in range(args.warmup):
-            step()
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    if marker is not None:
+        marker()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        last = step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if marker is not None:
+        marker()
+    sweep_ms = [a.elapsed_time(b) for a, b in events]
+    flips = R * S * V * nsw
+    res = dict(
+        wall_s=wall,
+        ms_per_step=wall * 1e3 / steps,
+        sweep_ms_per_step=sweep_ms,
+        launches_per_step=nsw // per_launch if per_launch == 2 else nsw,
+        launch_ms=sum(sweep_ms) / (steps * nsw / per_launch),
+        sweeps_per_launch=per_launch,
+        kind=shape[0],
+        tile=shape,
+        energy_per_spin=[float(x) for x in last[0][1][:4]],
+    )
+    res["ps_per_flip"] = res["ms_per_step"] * 1e9 / flips
+    res["sweep_ps_per_flip"] = (sum(sweep_ms) / steps) * 1e9 / flips
+    if depth1 and R == 1:
+        # the one-sweep kernel on the same lattice: bandwidth at temporal depth 1
+        lats[0].set_kernel("fused")
+        lats[0].sweep(2, beta)
         torch.cuda.synchronize()
-        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)]
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            last = step(events[k])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        sweep_ms = [a.elapsed_time(b) for a, b in events]
-        res = dict(
-            wall_s=wall,
-            ms_per_step=wall * 1e3 / args.steps,
-            sweep_ms_per_step=sweep_ms,
-            launch_ms=sum(sweep_ms) / (args.steps * nsw / per_launch),
-            sweeps_per_launch=per_launch,
-            kind=kind,
-            energy_per_spin=[float(x) for x in last[0][1][:4]],
-            tile=shape,
-        )
-        flips = R * S * V * nsw
-        res["ps_per_flip"] = res["ms_per_step"] * 1e9 / flips
-        res["sweep_ps_per_flip"] = (sum(sweep_ms) / args.steps) * 1e9 / flips
-        for l in lats:
-            l.close()
-        del lats, base
-        torch.cuda.empty_cache()
-        return res
-
-    main = measure(wl["prng"])
-    if args.layout_ab:
-        main["layout_ab"] = layout_ab(sg, torch, wl, stream, dev)
-    variants = {}
-    if not args.no_variant:
-        for v in wl.get("variant") or ():
-            variants[v] = measure(v)
-    return main, variants
-
-
-def layout_ab(sg, torch, wl, stream, dev, nsw=4):
-    """ms per sweep of the two-pass kernel on the cube and on the colour-separated
-    layout (conversion excluded: the difference of nsw sweeps and none), same lattice."""
-    L, beta = wl["L"], wl["beta"]
-    lat = sg.Lattice(L, 64, wl["prng"], coupling_seed=1, spin_seed=2, device=dev, stream=stream)
-    work = torch.empty(sg.sliced_footprint(L), dtype=torch.uint8, device=dev)
-    lat.set_kernel("twopass")
-
-    def timed(fn):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fn()  # warm-up
-        torch.cuda.synchronize()
+        n1 = 6
         a.record(stream)
-        fn()
+        lats[0].sweep(n1, beta)
         b.record(stream)
         torch.cuda.synchronize()
-        return a.elapsed_time(b)
-
-    cube = timed(lambda: lat.sweep(nsw, beta)) / nsw
-    full = timed(lambda: lat.sweep_sliced(nsw, beta, work))
-    conv = timed(lambda: lat.sweep_sliced(0, beta, work))
-    lat.set_kernel("auto")
-    fused = timed(lambda: lat.sweep(nsw, beta)) / nsw
-    lat.close()
-    del work
+        ms = a.elapsed_time(b) / n1
+        k1 = lats[0].kernel()
+        gbs = 40 * V / (ms * 1e-3) / 1e9
+        res["depth1"] = {"kernel": "sg::k_fused<0, 1> (one sweep per launch)", "tile": list(k1), "ms_per_sweep":
+                         round(ms, 4), "alg_gbs": round(gbs, 1), "frac_of_spec": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_site": 40}
+    for l in lats:
+        l.close()
+    del lats, base
     torch.cuda.empty_cache()
-    return {"lattice": f"L={L}, 64 samples, one replica", "twopass_cube_ms_per_sweep": round(cube, 4),
-            "twopass_sliced_ms_per_sweep": round((full - conv) / nsw, 4), "sliced_conversion_ms": round(conv, 4),
-            "fused_default_ms_per_sweep": round(fused, 4)}
+    return res
 
 
+def measure_peaks(nbytes: int = 4 << 30, reps: int = 5):
+    """GB/s of the read, copy and fill probes over nbytes (best of reps)."""
+    import torch
+
+    from paper_1411_0127_amd import sg
+
+    stream = torch.cuda.current_stream()
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    sg.probe_bandwidth("fill", src, None, nbytes, stream)
+    sg.probe_bandwidth("fill", dst, None, nbytes, stream)
+    out = {"bytes": nbytes}
+    for kind, moved in (("read", nbytes), ("copy", 2 * nbytes), ("fill", nbytes)):
+        best = None
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sg.probe_bandwidth(kind, dst, src, nbytes, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        out[f"{kind}_gbs"] = round(moved / (best * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batched (c3) and served (c4) mixes
+# ---------------------------------------------------------------------------
 def _budget_bytes(torch, frac=0.8):
     return int(torch.cuda.get_device_properties(0).total_memory * frac)
 
 
 def solo_sweep_ms(sg, torch, L, nsw=6):
-    """ms per sweep of one lattice alone (autotuned fused kernel), on its own stream."""
+    """ms per sweep of one lattice alone (autotuned kernel), on its own stream."""
     stream = torch.cuda.Stream(torch.device("cuda:0"))
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)
     if L >= 64:
@@ -232,19 +302,18 @@ def solo_sweep_ms(sg, torch, L, nsw=6):
     return a.elapsed_time(b) / nsw
 
 
-def run_mix(args, wl):
+def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: bool = False):
     """Batched (c3) or served (c4) mix through the continuous-batching server."""
     import torch
 
     from paper_1411_0127_amd import sg
     from paper_1411_0127_amd.serve import GpuBackend, Server, trace_batch, trace_served
 
-    scale = args.sweep_scale
     budget = _budget_bytes(torch)
-    out = {}
-    if args.workload == "c3":
-        jobs = trace_batch(args.jobs or 256, seed=args.seed, sweep_scale=scale)
-        be = GpuBackend(rounds_per_graph=8)
+    out = {"workload": MIX_DESC[kind], "sweep_scale": sweep_scale, "seed": seed}
+    if kind == "c3":
+        jobs = trace_batch(jobs_n or 256, seed=seed, sweep_scale=sweep_scale)
+        be = GpuBackend(rounds_per_graph=8, persistent=persistent)
         be.pretune(j.L for j in jobs)  # one-time per side, outside the measured span
         rep = Server(be, budget, chunk_rounds=200, min_rounds=8).serve(jobs)
         s = rep.summary()
@@ -255,50 +324,79 @@ def run_mix(args, wl):
         out["plain_ps_per_flip"] = plain_s * 1e12 / s["flips"]
         out["batched_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
         out["solo_ms_per_sweep"] = {str(L): round(v, 4) for L, v in t_solo.items()}
-        out["summary"] = s
-        out["bytes"] = sum(40 * j.L**3 * j.nsweeps for j in jobs)
         out["seconds"] = s["makespan_s"]
     else:
-        jobs = trace_served(args.jobs or 64, rate=50.0, seed=args.seed, sweep_scale=scale)
-        be = GpuBackend(rounds_per_graph=8)
+        jobs = trace_served(jobs_n or 64, rate=50.0, seed=seed, sweep_scale=sweep_scale)
+        be = GpuBackend(rounds_per_graph=8, persistent=persistent)
         be.pretune(j.L for j in jobs)
         rep = Server(be, budget, chunk_rounds=100).serve(jobs)
         s = rep.summary()
         mean_job_s = s["busy_s"] / max(1, s["jobs"])
         rate = 0.7 / max(mean_job_s, 1e-6)
-        jobs2 = trace_served(max(8, (args.jobs or 64) // 2), rate=rate, seed=args.seed + 1, sweep_scale=scale)
+        jobs2 = trace_served(max(8, (jobs_n or 64) // 2), rate=rate, seed=seed + 1, sweep_scale=sweep_scale)
         rep2 = Server(be, budget, chunk_rounds=100).serve(jobs2)
         s2 = rep2.summary()
         out["ps_per_flip"] = s["ps_per_flip_busy"]
-        out["summary"] = s
+        out["p50_latency_s"] = s["p50_latency_s"]
+        out["p99_latency_s"] = s["p99_latency_s"]
         out["sub_saturating"] = dict(rate_jobs_per_s=rate, **s2)
-        out["bytes"] = sum(40 * j.L**3 * j.nsweeps for j in jobs)
         out["seconds"] = s["busy_s"]
+    out["summary"] = s
+    out["compulsory_bytes"] = batch_bytes(jobs)
+    gbs = out["compulsory_bytes"] / out["seconds"] / 1e9
+    out["alg_gbs"] = round(gbs, 1)
+    out["frac_of_spec"] = round(gbs / HBM_PEAK_GBS, 4)
+    out["batch_kernel"] = ("sg::k_batch_persistent (one launch per run, rounds ordered by per-lattice counters)"
+                           if persistent else "sg::k_fused_batch (one launch per round)")
+    be.close()
     return out
 
 
-def cpu_baseline(wl, budget_s: float):
-    """The oracle as it stands, single-threaded, on one sample of one replica."""
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on the host's cores
+# ---------------------------------------------------------------------------
+def cpu_baseline(wl_name: str = "c2", nsweeps: int = 1, threads: int = 0):
+    """The oracle on bit-planes 0 and 63 of the workload's lattice (MINSTD, the
+    shared numbers of the coded samples), threaded over the host's cores, timed
+    for nsweeps sweeps; plus the L=16 one-sample configuration (1000 sweeps) on
+    one core and on all cores."""
     import numpy as np
 
     import oracle
     import seeded_inputs as si
 
+    wl = WORKLOADS[wl_name]
+    threads = threads or host_threads()
     L, beta = wl["L"], wl["beta"]
-    L = min(L, 256)
-    J = si.coupling_words(L, 1) & np.uint64(1)
-    S0 = si.spin_words(L, 2, 0) & np.uint64(1)
-    lat = oracle.OracleLattice((L, L, L), 1, J, S0, oracle.MINSTD, si.minstd_seeds(L, 2, 0))
+    planes = [0, 63]
+    J = si.coupling_bits(L, 1, planes, threads=threads)
+    S0 = si.spin_bits(L, 2, 0, planes, threads=threads)
+    seeds = si.minstd_seeds_threaded(L, 2, 0, threads=threads)
+    lat = oracle.OracleLattice.from_bits((L, L, L), J, S0, oracle.MINSTD, seeds)
+    del J, S0, seeds
     t0 = time.perf_counter()
-    lat.run(1, beta)
-    one = time.perf_counter() - t0
-    n = max(1, min(int(budget_s / max(one, 1e-9)), 2000))
-    t0 = time.perf_counter()
-    lat.run(n, beta)
+    lat.run(nsweeps, beta, threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=dt * 1e12 / (L**3 * n), unit="ps/flip", cores=1, kind="oracle",
-                sample=f"L={L} cube, 1 of the 64 samples, 1 replica, {n} MINSTD sweeps at T={1 / beta:.2f}, "
-                       f"one byte per spin, single thread ({dt:.1f} s)")
+    flips = len(planes) * L**3 * nsweeps
+    del lat
+    rec = dict(value=dt * 1e12 / flips, unit="ps/flip", cores=threads, kind="oracle",
+               sample=f"{wl_name} lattice (L={L}, T={1 / beta:.2f}, MINSTD), bit-planes 0 and 63 of the 64 coded "
+                      f"samples, {nsweeps} sweep(s), one byte per spin, {threads} threads over sites "
+                      f"({dt:.1f} s wall)",
+               cpu_model=cpu_model(), nproc=os.cpu_count())
+    # the L=16 single-sample configuration in full, on one core and on all
+    w0 = WORKLOADS["c0"]
+    c0 = {}
+    for n in (1, threads):
+        L0 = w0["L"]
+        l0 = oracle.OracleLattice((L0, L0, L0), 1, si.coupling_words(L0, 1) & np.uint64(1),
+                                  si.spin_words(L0, 2, 0) & np.uint64(1), oracle.MINSTD, si.minstd_seeds(L0, 2, 0))
+        t0 = time.perf_counter()
+        l0.run(w0["sweeps"], w0["beta"], record=True, threads=n)  # energy after every sweep
+        d = time.perf_counter() - t0
+        c0[f"threads_{n}"] = {"ps_per_flip": d * 1e12 / (L0**3 * w0["sweeps"]), "seconds": round(d, 3)}
+    rec["c0_L16_1000_sweeps"] = c0
+    return rec
 
 
 def main():
@@ -306,20 +404,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
     ap.add_argument("--tile", default="",
                     help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band[,planes] (skips the autotuner)")
-    ap.add_argument("--no-variant", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sweep-scale", type=float, default=0.1,
-                    help="c3/c4: multiply every job's sweep count (the full mixes take minutes)")
+    ap.add_argument("--extras", default="peak,depth1,c1,c3,c4,cpu",
+                    help="comma list of extra sections: peak, depth1, c1, c3, c4, cpu ('' for none)")
+    ap.add_argument("--cpu-sweeps", type=int, default=1, help="sweeps of the oracle in cpu_baseline")
+    ap.add_argument("--sweep-scale", type=float, default=0.1, help="c3: sweep counts x this (c4: x this / 2)")
     ap.add_argument("--jobs", type=int, default=0, help="c3/c4: number of jobs (default 256 / 64)")
     ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="c3/c4: 1 = one persistent launch per run, 0 = one launch per round")
     ap.add_argument("--layout-ab", action="store_true",
-                    help="also time the two-pass kernel on the cube and on the colour-separated layout")
+                    help="also time the two-pass kernel on the cube, colour-separated and sliced layouts")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also make 3 device copies of BYTES bytes, for counter calibration")
     args = ap.parse_args()
@@ -330,52 +429,21 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    wl = WORKLOADS[args.workload]
-    if args.workload in ("c3", "c4"):
-        res = run_mix(args, wl)
-        gbs = res["bytes"] / res["seconds"] / 1e9
-        line = {
-            "metric": METRIC,
-            "value": round(res["ps_per_flip"], 6),
-            "unit": "ps/flip",
-            "n_gpus": 1,
-            "steps": 1,
-            "warmup": 0,
-            "ms_per_step": round(res["seconds"] * 1e3, 3),
-            "higher_is_better": False,
-            "scaling": "weak",
-            "vs_baseline": None,
-            "dtype": "u64",
-            "data": "synthetic",
-            "config": {"workload": wl["desc"], "sweep_scale": args.sweep_scale, "jobs": res["summary"]["jobs"],
-                       "seed": args.seed, "parallelism": "single GPU"},
-            "hbm_gbs_algorithmic": round(gbs, 1),
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": "sg::k_fused_batch (all resident lattices, one launch per round)",
-                         "bytes_per_site": 40},
-        }
-        for k in ("plain_ps_per_flip", "batched_over_plain", "solo_ms_per_sweep", "sub_saturating"):
-            if k in res:
-                line[k] = res[k]
-        line["summary"] = res["summary"]
-        print(json.dumps(line), flush=True)
-        return
-    main_res, variants = run_gpu(args, wl)
-    if args.calibrate_copy:
-        import torch
+    import torch
 
-        src = torch.empty(args.calibrate_copy, dtype=torch.uint8, device="cuda:0").fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    from paper_1411_0127_amd import sg
+
+    extras = {e.strip() for e in args.extras.split(",") if e.strip()}
+    wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    marker = Marker(torch, sg, torch.cuda.current_stream())
+    main_res = run_single(args, wl, marker=marker, depth1="depth1" in extras)
+    print(f"[bench] {args.workload}: {main_res['ps_per_flip']:.5f} ps/flip, launch {main_res['launch_ms']:.4f} ms",
+          file=sys.stderr, flush=True)
     L, R = wl["L"], wl["replicas"]
     V = L**3
     bps = algorithmic_bytes_per_site(wl["prng"], R, main_res["sweeps_per_launch"])
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
-    eq = achieved * main_res["sweeps_per_launch"]
     traffic = load_traffic(args.workload)
     line = {
         "metric": METRIC,
@@ -402,6 +470,7 @@ def main():
             "parallelism": "single GPU",
         },
         "hbm_gbs_algorithmic": round(achieved, 1),
+        "ms_per_sweep": round(sum(main_res["sweep_ms_per_step"]) / (args.steps * (args.sweeps or wl["sweeps"])), 5),
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -409,34 +478,90 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": ("sg::k_fused2 (two sweeps per launch, replicas interleaved)"
-                       if main_res["sweeps_per_launch"] == 2 else "sg::k_fused (one launch per sweep, all replicas)"),
+            "kernel": ("sg::k_fused2 (two sweeps per launch)" if main_res["sweeps_per_launch"] == 2
+                       else "sg::k_fused (one sweep per launch)"),
             "bytes_per_site": bps,
+            "sites_per_launch": V,
             "sweeps_per_launch": main_res["sweeps_per_launch"],
             "launch_ms": round(main_res["launch_ms"], 5),
-            # what a one-sweep kernel would have to sustain for the same time per sweep
-            "one_sweep_equivalent": {
-                "achieved": round(eq, 1),
-                "frac": round(eq / HBM_PEAK_GBS, 4),
-            },
+            "launches_timed": args.steps * main_res["launches_per_step"],
         },
     }
-    if "layout_ab" in main_res:
-        line["layout_ab"] = main_res["layout_ab"]
-    if variants:
-        line["variants"] = {
-            name: {
-                "ps_per_flip": round(v["ps_per_flip"], 6),
-                "ms_per_step": round(v["ms_per_step"], 4),
-                "launch_ms": round(v["launch_ms"], 5),
-                "sweeps_per_launch": v["sweeps_per_launch"],
-                "kernel": v["kind"],
-            }
-            for name, v in variants.items()
-        }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    if traffic:
+        line["roofline"]["traffic_gbs"] = round(traffic / (main_res["launch_ms"] * 1e-3) / 1e9, 1)
+    if "depth1" in main_res:
+        line["depth1"] = main_res["depth1"]
+    if "peak" in extras:
+        pk = measure_peaks()
+        line["measured_peak"] = pk
+        line["roofline"]["frac_of_measured_read"] = round(achieved / pk["read_gbs"], 4)
+        if "depth1" in line:
+            line["depth1"]["frac_of_measured_copy"] = round(line["depth1"]["alg_gbs"] / pk["copy_gbs"], 4)
+            line["depth1"]["frac_of_measured_read"] = round(line["depth1"]["alg_gbs"] / pk["read_gbs"], 4)
+        print(f"[bench] peaks: {pk}", file=sys.stderr, flush=True)
+    if args.layout_ab:
+        line["layout_ab"] = layout_ab(sg, torch, wl)
+    if "c1" in extras and args.workload != "c1":
+        c1 = {}
+        for prng in ("minstd", "mt19937", "parisi_rapuano"):
+            r = run_single(args, WORKLOADS["c1"], prng=prng, steps=3, warmup=1)
+            c1[prng] = {"ps_per_flip": round(r["ps_per_flip"], 6), "launch_ms": round(r["launch_ms"], 5),
+                        "sweeps_per_launch": r["sweeps_per_launch"], "tile": r["tile"]}
+            if prng == "minstd":
+                b1 = algorithmic_bytes_per_site("minstd", 2, r["sweeps_per_launch"])
+                c1[prng]["alg_gbs_per_launch"] = round(b1 * 256**3 / (r["launch_ms"] * 1e-3) / 1e9, 1)
+        line["c1"] = {"workload": WORKLOADS["c1"]["desc"], **c1}
+        print(f"[bench] c1 done", file=sys.stderr, flush=True)
+    for kind in ("c3", "c4"):
+        if kind in extras:
+            scale = args.sweep_scale if kind == "c3" else args.sweep_scale / 2
+            line[kind] = run_mix(kind, args.jobs, scale, args.seed, persistent=bool(args.persistent))
+            print(f"[bench] {kind} done", file=sys.stderr, flush=True)
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if "cpu" in extras:
+        line["cpu_baseline"] = cpu_baseline("c2" if args.workload == "c2" else args.workload, args.cpu_sweeps)
     print(json.dumps(line), flush=True)
+
+
+def layout_ab(sg, torch, wl, nsw=4):
+    """ms per sweep of the two-pass kernel on the cube, the colour-separated and
+    the sliced layout (conversions excluded: the difference of nsw sweeps and
+    none), and of the default fused kernel, all on the same lattice."""
+    L, beta = wl["L"], wl["beta"]
+    stream = torch.cuda.current_stream()
+    lat = sg.Lattice(L, 64, wl["prng"], coupling_seed=1, spin_seed=2, stream=stream)
+    work = torch.empty(sg.sliced_footprint(L), dtype=torch.uint8, device="cuda:0")
+    lat.set_kernel("twopass")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    out = {"lattice": f"L={L}, 64 samples, one replica"}
+    out["twopass_cube_ms_per_sweep"] = round(timed(lambda: lat.sweep(nsw, beta)) / nsw, 4)
+    for name, fn in (("separated", lat.sweep_separated), ("sliced", lat.sweep_sliced)):
+        full = timed(lambda: fn(nsw, beta, work))
+        conv = timed(lambda: fn(0, beta, work))
+        out[f"twopass_{name}_ms_per_sweep"] = round((full - conv) / nsw, 4)
+        out[f"{name}_conversion_ms"] = round(conv, 4)
+    lat.set_kernel("auto")
+    out["fused_default_ms_per_sweep"] = round(timed(lambda: lat.sweep(nsw, beta)) / nsw, 4)
+    lat.close()
+    del work
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -108,16 +108,24 @@ enum {
  * SG_KERNEL_FUSED otherwise, with default tiles (sg_autotune picks by timing). */
 enum { SG_KERNEL_AUTO = 0, SG_KERNEL_TWOPASS = 1, SG_KERNEL_FUSED = 2, SG_KERNEL_FUSED2 = 3 };
 
-/* Bytes of device memory a lattice needs.  own_couplings = 1 for a lattice that
- * holds its couplings (sg_lattice_create), 0 for a replica that reads another
- * lattice's (sg_lattice_create_replica). */
-int sg_footprint(int L, int prng, int own_couplings, size_t *dev_bytes);
+/* Bytes of device memory a lattice of side L needs (Sec. 1: a cubic lattice of
+ * V = L^3 spins with 3V bonds; Sec. 4: one bit per spin and coupling per coded
+ * sample, so the size does not depend on nsamples, which is only checked):
+ * sg_footprint for a lattice that holds its couplings (sg_lattice_create),
+ * sg_replica_footprint for a replica that reads another lattice's
+ * (sg_lattice_create_replica).  SG_EINVAL for L odd or outside [2, 2048],
+ * nsamples outside [1, 64], an unknown prng or dev_bytes NULL. */
+int sg_footprint(int L, int nsamples, int prng, size_t *dev_bytes);
+int sg_replica_footprint(int L, int nsamples, int prng, size_t *dev_bytes);
 
-/* Create a lattice of side L (even, 2..2048) holding nsamples (1..64) samples.
+/* Create a lattice of side L (even, 2..2048) holding nsamples (1..64) samples
+ * (Sec. 1, Eqs. (1)-(2): the +-J model on a periodic cube, random start; Sec. 4:
+ * the samples coded one per bit of a word).
  * J_host: 3*L^3 coupling words in the layout above, or NULL to generate them
  *         from coupling_seed (Sec. 1: J = +-1 with probability 1/2 each);
  * spin_seed, replica: key the initial spins and the random streams;
- * dev_buf, dev_bytes: caller's device buffer (>= sg_footprint(L, prng, 1));
+ * dev_buf, dev_bytes: caller's device buffer, >= sg_footprint(L, nsamples, prng)
+ *         bytes, 256-byte aligned (the size is checked: SG_EINVAL when short);
  * stream: hipStream_t for all work on this lattice, or NULL.
  * Bits j >= nsamples are simulated like the others and ignored by observables. */
 int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host,
@@ -126,80 +134,139 @@ int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host,
 
 /* A replica (Sec. 2: same couplings, its own initial spins and evolution):
  * shares base's coupling buffer, draws its spins and streams from
- * (spin_seed, replica).  dev_buf >= sg_footprint(L, prng, 0). */
+ * (spin_seed, replica).  dev_buf >= sg_replica_footprint(L, nsamples, prng);
+ * base must outlive the replica. */
 int sg_lattice_create_replica(const sg_lattice *base, uint64_t spin_seed, uint32_t replica,
                               void *dev_buf, size_t dev_bytes, void *stream,
                               sg_lattice **out);
 
-/* Queue nsweeps >= 0 sweeps at inverse temperature beta >= 0 (beta = +inf allowed:
- * only dE <= 0 is accepted). */
+/* Queue nsweeps >= 0 Metropolis sweeps at inverse temperature beta >= 0 (Sec. 1:
+ * one sweep updates every red site, then every blue site; Sec. 4: acceptance by
+ * integer thresholds on the coded words).  beta = +inf is allowed: only dE <= 0
+ * is accepted.  Asynchronous on the lattice's stream; SG_EINVAL for nsweeps < 0
+ * or beta < 0 / NaN, SG_EDEVICE when a launch fails. */
 int sg_sweep(sg_lattice *lat, int64_t nsweeps, double beta);
 
-/* The same for n lattices that share one coupling buffer (replicas), moving the
- * couplings once per sweep for all of them when the kernel allows; all must have
- * the same L, prng and stream. */
+/* The same for n lattices that share one coupling buffer (replicas, Sec. 2: the
+ * paper sweeps its replicas in one kernel), moving the couplings once per sweep
+ * for pairs of them when the kernel allows; all must have the same L, prng,
+ * couplings, stream and sweep count (else SG_EMISMATCH). */
 int sg_sweep_replicas(sg_lattice *const *lats, int n, int64_t nsweeps, double beta);
 
-/* ---- Colour-separated layout (the layout study of Sec. 2) ----------------------
- * Bytes of the work buffer sg_sweep_sliced needs: 32 per site. */
+/* ---- Layout study (Sec. 2, memory allocation strategies) ------------------------
+ * Bytes of the work buffer sg_sweep_separated and sg_sweep_sliced need: 32 per
+ * site (the spin word and three coupling words). */
 int sg_sliced_footprint(int L, size_t *dev_bytes);
 
-/* nsweeps sweeps with the two-pass kernel on the colour-separated layout: the
- * current spins and the couplings are copied into `work` (caller's device buffer,
- * >= sg_sliced_footprint bytes, 256-byte aligned) with red and blue sites of each
- * row in separate arrays indexed by (z, y, x/2) and each site's three couplings with
- * its colour, swept there, and the spins copied back.  The spins are bit-identical
- * to sg_sweep's; `work` is scratch, free again when the queued work is done. */
+/* nsweeps sweeps with the two-pass kernel on the colour-separated ("standard")
+ * layout of Sec. 2: the current spins and the couplings are copied into `work`
+ * (caller's device buffer, >= sg_sliced_footprint bytes, 256-byte aligned) with
+ * red and blue sites of each row in separate arrays indexed by (z, y, x/2) and
+ * each site's three couplings with its colour, swept there, and the spins copied
+ * back.  The spins are bit-identical to sg_sweep's; `work` is scratch, free again
+ * when the queued work is done.  MINSTD, MT19937, Parisi-Rapuano and per-sample
+ * lattices. */
+int sg_sweep_separated(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes);
+
+/* The same on the paper's sliced layout (Sec. 2, cubic stencil: the coordinate
+ * transformation x' = x, y' = y - x, z' = x - y + z mod L makes every z' plane one
+ * colour, red for z' even).  In `work` colour c = z' & 1 is stored at
+ * [c][z'/2][y'][x'], spins first, then each site's own three couplings J[d][c][...];
+ * a site's neighbours are the words (x', y'), (x', y'-1), (x'+1, y'-1) of the
+ * plane above and (x', y'), (x', y'+1), (x'-1, y'+1) of the plane below (the
+ * transformed neighbour coordinates of Sec. 2).  One two-pass sweep per sweep;
+ * bit-identical to sg_sweep.  Arguments, checks and ownership as above. */
 int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes);
 
-/* Observables of Sec. 1, Eq. (1), per sample j < nsamples:
- * unsat[j] = number of unsatisfied bonds (-J s_i s_k = +1) among the 3V bonds,
- * e_per_spin[j] = (2*unsat[j] - 3V) / V.  Either output may be NULL. */
+/* Energy of Sec. 1, Eq. (1), per sample j < nsamples: unsat[j] = number of
+ * unsatisfied bonds (-J s_i s_k = +1) among the 3V bonds, e_per_spin[j] =
+ * (2*unsat[j] - 3V) / V, i.e. H/V.  Either output may be NULL.  Synchronises the
+ * lattice's stream. */
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin);
 
-/* Two-replica overlap per sample: ndiff[j] = number of sites where the replicas
- * differ, q[j] = 1 - 2*ndiff[j]/V.  a, b: same L and nsamples. */
+/* Two-replica overlap per sample.  The paper simulates replicas (Sec. 2) but
+ * does not define the overlap; this is the textbook q_j = (1/V) sum_i
+ * s^a_i s^b_i, returned as ndiff[j] = number of sites where the replicas differ
+ * and q[j] = 1 - 2*ndiff[j]/V.  a, b: same L, nsamples and couplings (else
+ * SG_EMISMATCH).  Synchronises a's stream (and b's, if different). */
 int sg_overlap(const sg_lattice *a, const sg_lattice *b, int64_t *ndiff, double *q);
 
-/* Spins as +-1 bytes, sample-major: out[j*V + i], j < nsamples; n = nsamples*V. */
+/* Spins as +-1 bytes, sample-major: out[j*V + i], j < nsamples, i = x + L*(y +
+ * L*z); n = nsamples*V (else SG_EINVAL).  Decodes the bit mapping of Sec. 4
+ * (bit j of site i's word is 1 for s = +1).  Synchronises the stream. */
 int sg_get_spins(const sg_lattice *lat, int8_t *out, size_t n);
 
-/* Raw spin words (n = V) and coupling words (n = 3V). */
+/* Raw spin words, n = V (Sec. 4 bit mapping): sg_get_words reads the current
+ * configuration, sg_set_spins replaces it (resume from a checkpoint, gauge
+ * tests); host arrays are borrowed, both synchronise the stream. */
 int sg_get_words(const sg_lattice *lat, uint64_t *out, size_t n);
-int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n);
+int sg_set_spins(sg_lattice *lat, const uint64_t *words_host, size_t n);
+
+/* Coupling words, n = 3V, packed J[3][V] (Sec. 1, Eq. (2); bit 1 = J = -1). */
 int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n);
 
-/* The random number each site used in the last sweep (n = V), for checks;
- * SG_EINVAL for SG_PHILOX lattices, whose samples draw 64 numbers per site. */
+/* The random number each site used in the last sweep (n = V; Sec. 3 generators,
+ * Sec. 4 one number per site word), read from the device: the buffered numbers
+ * of MT19937 / Parisi-Rapuano, or MINSTD's evaluated by a kernel with the sweep
+ * kernels' functions.  SG_EINVAL before the first sweep and for SG_PHILOX
+ * lattices, whose samples draw 64 numbers per site. */
 int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n);
 
-/* Integer thresholds T[k-1] for dE = 4k, k = 1,2,3 (Sec. 4, EXP4/EXP8/EXP12). */
+/* Integer thresholds T[k-1] = ceil(R_range * exp(-4k beta)) for dE = 4k, k = 1,2,3
+ * (Sec. 4, EXP4/EXP8/EXP12; R_range as above).  Host only; the CPU checker uses
+ * the same definition. */
 int sg_thresholds(double beta, int prng, uint64_t T[3]);
 
-/* Sweeps done so far; setting it (resume from a checkpoint) also moves the
- * MINSTD streams; for MT19937 only a lattice that has not swept may be moved
- * forward, by regenerating its streams up to that point. */
+/* Sweeps done so far (the sweep index t of the Sec. 3 streams; Sec. 4.1 times
+ * t_sw per sweep), -1 for NULL.  Setting it (resume from a checkpoint) also moves
+ * the MINSTD and per-sample streams, which are functions of (site, sweep); a
+ * MT19937 or Parisi-Rapuano lattice that has not swept may be moved forward by
+ * regenerating its streams up to that point -- for one that has, restore its
+ * stream state with sg_set_stream_state. */
 int64_t sg_sweep_count(const sg_lattice *lat);
 int sg_set_sweep_count(sg_lattice *lat, int64_t t);
 
-/* Choose the sweep kernel and, for SG_KERNEL_FUSED(2), its tile: tile_x pairs of
+/* Checkpoint of the per-column stream states of Sec. 3 (MT19937: 624 words per
+ * column, Parisi-Rapuano: 64; word k of column c at k*L*L + c, the paper's
+ * strided per-stream layout).  sg_stream_state_bytes gives their size (0 for
+ * MINSTD and SG_PHILOX, which keep none); sg_get_stream_state copies them out,
+ * sg_set_stream_state copies them in and sets the sweep count to t, the count
+ * at which they were taken.  Together with sg_get_words / sg_set_spins this
+ * resumes any lattice mid-run bit-exactly.  bytes must equal the size. */
+int sg_stream_state_bytes(const sg_lattice *lat, size_t *bytes);
+int sg_get_stream_state(const sg_lattice *lat, void *out, size_t bytes);
+int sg_set_stream_state(sg_lattice *lat, const void *in, size_t bytes, int64_t t);
+
+/* Library runtime (measurement): bandwidth probes, the measured peaks the sweep
+ * is set against (the paper's analog: the peak bandwidth of a device copy, Sec.
+ * 4.1).  kind 0: read `bytes` from src, writing blocks*16 bytes of folded words to
+ * dst (dst must hold them); 1: copy `bytes` from src to dst; 2: fill `bytes` of
+ * dst.  bytes a positive multiple of 16, buffers 16-byte aligned, blocks = 0 for
+ * 4096 workgroups of 256 lanes (else 1..65536).  Asynchronous on `stream`; the
+ * caller times it. */
+int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int blocks, void *stream);
+
+/* Library runtime (kernel choice; no counterpart in the paper, whose launch
+ * configurations are studied in Sec. 4.1).
+ * Choose the sweep kernel and, for SG_KERNEL_FUSED(2), its tile: tile_x pairs of
  * sites per row (x extent 2*tile_x), tile_y rows, z_chunk planes per workgroup,
  * band = tile rows per group of the tile order (the workgroups running together
  * cover a block about band tiles tall); 0 = default for any of the four.  Invalid
  * shapes return SG_EINVAL and change nothing. */
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band);
 
-/* Planes the two-sweep march keeps in flight (requested planes-2 steps ahead): 5 or
+/* Library runtime.  Planes the two-sweep march keeps in flight (requested planes-2 steps ahead): 5 or
  * 6, or 0 for the default (5; the buffered generators reject 6).  Reset by
  * sg_set_kernel. */
 int sg_set_ring(sg_lattice *lat, int planes);
 
-/* The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,
+/* Library runtime.  The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,
  * _FUSED or _FUSED2), tile_x, tile_y, z_chunk (0 = chosen at launch), band, and the
  * planes in flight of the two-sweep march (0 for the others). */
 int sg_get_kernel(const sg_lattice *lat, int out[6]);
 
-/* Autotune the sweep kernel for n (1 or 2) lattices swept together (n = 2:
+/* Library runtime (the paper scans launch configurations by hand, Sec. 4.1).
+ * Autotune the sweep kernel for n (1 or 2) lattices swept together (n = 2:
  * replicas sharing couplings, as in sg_sweep_replicas).  Candidate kernels
  * (SG_KERNEL_TWOPASS; SG_KERNEL_FUSED, and SG_KERNEL_FUSED2 with 5 or, but for
  * the buffered generators, 6 planes in flight, over their tiles) are timed with
@@ -228,39 +295,44 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
  * not be swept or destroyed while it is in a batch. */
 typedef struct sg_batch sg_batch;
 
-/* Device workspace for a batch of up to max_lattices lattices and max_items work
- * items (tiles x z chunks, summed over the lattices it holds at once). */
+/* Library runtime (the paper's nearest analog: k coded sample sets per launch,
+ * Sec. 2 and Sec. 4.1).  Device workspace for a batch of up to max_lattices
+ * lattices and max_items work items (tiles x z chunks, summed over the lattices it
+ * holds at once). */
 int sg_batch_footprint(int max_lattices, int max_items, size_t *dev_bytes);
 int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_bytes, void *stream,
                     sg_batch **out);
 
-/* Queue nsweeps >= 1 sweeps at beta for lat. */
+/* Library runtime.  Queue nsweeps >= 1 sweeps (Sec. 1) at beta for lat. */
 int sg_batch_add(sg_batch *b, sg_lattice *lat, int64_t nsweeps, double beta);
 
-/* Queue up to max_rounds rounds (fewer if every lattice finishes first).  With
+/* Library runtime.  Queue up to max_rounds rounds (fewer if every lattice
+ * finishes first).  With
  * rounds_per_graph > 0 the rounds are captured once into a hipGraph of that many
  * rounds (re-captured when the set of work items changes) and replayed.  Returns
  * as soon as the work is queued; lattices whose sweeps are all queued move to the
  * finished list.  *rounds_done (may be NULL) = rounds queued. */
 int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t *rounds_done);
 
-/* Move up to max finished lattices to out[]; *n = how many. */
+/* Library runtime.  Move up to max finished lattices to out[]; *n = how many. */
 int sg_batch_take_finished(sg_batch *b, sg_lattice **out, int max, int *n);
 
-/* Lattices with sweeps left, finished lattices not yet taken, and the work items
- * the active lattices need (any output may be NULL). */
+/* Library runtime.  Lattices with sweeps left, finished lattices not yet taken,
+ * and the work items the active lattices need (any output may be NULL). */
 int sg_batch_size(const sg_batch *b, int *active, int *finished, int *items);
 
-/* Rounds until the first and until the last active lattice finishes (0 and 0
- * when none is active); either output may be NULL. */
+/* Library runtime.  Rounds until the first and until the last active lattice
+ * finishes (0 and 0 when none is active); either output may be NULL. */
 int sg_batch_rounds_left(const sg_batch *b, int64_t *first, int64_t *last);
 
+/* Library runtime.  Release the batch handle (never the caller's workspace). */
 int sg_batch_destroy(sg_batch *b);
 
-/* Release the handle (never the caller's device buffer). */
+/* Library runtime (no counterpart in the paper).  Release the handle, never the
+ * caller's device buffer; NULL is allowed. */
 int sg_destroy(sg_lattice *lat);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Library runtime.  Message of the last failed call on this thread ("" if none). */
 const char *sg_last_error(void);
 
 #ifdef __cplusplus

@@ -19,8 +19,10 @@ SOURCES = [
     "kernels_observe.hip",
     "kernels_sweep_twopass.hip",
     "kernels_sweep_fused.hip",
+    "kernels_separated.hip",
     "kernels_sliced.hip",
     "sg_batch.hip",
+    "kernels_probe.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -176,6 +176,18 @@ __global__ __launch_bounds__(kPrBlock) void k_pr_fill(PrFillArgs a, int L, int64
         st[(size_t)k * ncols + c] = b[k * kPrBlock];
 }
 
+// MINSTD number of every site in the sweep whose multiplier is a =
+// 16807^(t+1) mod (2^31 - 1): out[i] for site i = x + L*(y + L*z), from the
+// same seed and jump functions the sweep kernels evaluate.
+__global__ void k_minstd_draws(uint32_t *__restrict__ out, int L, uint32_t a, uint32_t mk)
+{
+    const int64_t LL = (int64_t)L * L, V = LL * L;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < V; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t z = (uint32_t)(i / LL), xy = (uint32_t)(i - (int64_t)z * LL);
+        out[i] = minstd_jump(a, minstd_seed(xy, minstd_plane_key(z, mk)));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_init_couplings(uint64_t *J, int L, uint64_t key, hipStream_t s)
@@ -189,6 +201,13 @@ hipError_t launch_init_spins(uint64_t *S, int L, uint64_t key, hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
     hipLaunchKernelGGL(k_init_spins, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, S, V, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_minstd_draws(uint32_t *out, int L, uint32_t a, uint32_t mk, hipStream_t s)
+{
+    const int64_t V = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_minstd_draws, dim3(grid_for(V, 4)), dim3(kBlock), 0, s, out, L, a, mk);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
-// Colour-separated ("sliced") layout and its two-pass sweep (the layout study of
-// Sec. 2: red and blue sites in separate arrays, so that the threads of one colour
-// read their neighbours of the other colour with unit stride).
+// Colour-separated layout and its two-pass sweep (the "standard" separate-
+// allocation scheme of Sec. 2's layout study: red and blue sites in separate
+// arrays, so that the threads of one colour read their neighbours of the other
+// colour with unit stride; no coordinate transformation).
 //
 // Layout (this library's form of it): for colour c (0 = red, x+y+z even; 1 = blue)
 // the array C_c[z][y][h], h = 0 .. L/2-1, holds the site x = 2h + ((y + z + c) & 1)
@@ -31,8 +32,8 @@ __device__ __forceinline__ int64_t cube_index(int L, int c, int64_t z, int64_t y
     return x + (int64_t)L * (y + (int64_t)L * z);
 }
 
-// nw cube arrays of V words (stride V) -> sliced: dst[k][c][V/2] for k < nw
-__global__ void k_to_sliced(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L, int nw,
+// nw cube arrays of V words (stride src_stride) -> separated: dst[k][c][V/2] for k < nw
+__global__ void k_to_separated(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L, int nw,
                             int64_t src_stride)
 {
     const int64_t V = (int64_t)L * L * L, half = V / 2, hx = L / 2;
@@ -46,7 +47,7 @@ __global__ void k_to_sliced(const uint64_t *__restrict__ src, uint64_t *__restri
     }
 }
 
-__global__ void k_from_sliced(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L)
+__global__ void k_from_separated(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int L)
 {
     const int64_t V = (int64_t)L * L * L, half = V / 2, hx = L / 2;
     for (int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x; g < V; g += (int64_t)gridDim.x * kBlock) {
@@ -57,9 +58,9 @@ __global__ void k_from_sliced(const uint64_t *__restrict__ src, uint64_t *__rest
     }
 }
 
-// One colour pass.  S: sliced spins [2][V/2]; K: sliced couplings [3][2][V/2].
+// One colour pass.  S: separated spins [2][V/2]; K: separated couplings [3][2][V/2].
 template <int PRNG>
-__global__ __launch_bounds__(kBlock) void k_twopass_sliced(uint64_t *__restrict__ S, const uint64_t *__restrict__ K,
+__global__ __launch_bounds__(kBlock) void k_twopass_separated(uint64_t *__restrict__ S, const uint64_t *__restrict__ K,
                                                            const uint32_t *__restrict__ rnd, uint32_t mk, int L,
                                                            int colour, uint32_t a, uint64_t pkey, int64_t t,
                                                            Thresholds T)
@@ -106,34 +107,34 @@ __global__ __launch_bounds__(kBlock) void k_twopass_sliced(uint64_t *__restrict_
 
 }  // namespace
 
-hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, int64_t src_stride,
+hipError_t launch_to_separated(const uint64_t *cube, uint64_t *sliced, int L, int nwords, int64_t src_stride,
                             hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_to_sliced, dim3(grid_for(V)), dim3(kBlock), 0, s, cube, sliced, L, nwords, src_stride);
+    hipLaunchKernelGGL(k_to_separated, dim3(grid_for(V)), dim3(kBlock), 0, s, cube, sliced, L, nwords, src_stride);
     return hipGetLastError();
 }
 
-hipError_t launch_from_sliced(const uint64_t *sliced, uint64_t *cube, int L, hipStream_t s)
+hipError_t launch_from_separated(const uint64_t *sliced, uint64_t *cube, int L, hipStream_t s)
 {
     const int64_t V = (int64_t)L * L * L;
-    hipLaunchKernelGGL(k_from_sliced, dim3(grid_for(V)), dim3(kBlock), 0, s, sliced, cube, L);
+    hipLaunchKernelGGL(k_from_separated, dim3(grid_for(V)), dim3(kBlock), 0, s, sliced, cube, L);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_sliced(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s)
+hipError_t launch_sweep_separated(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s)
 {
     const int64_t V = (int64_t)a.L * a.L * a.L;
     const int g = grid_for(V / 2);
     for (int colour = 0; colour < 2; ++colour) {
         if (a.prng == SG_MINSTD)
-            hipLaunchKernelGGL(k_twopass_sliced<SG_MINSTD>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0], a.L,
+            hipLaunchKernelGGL(k_twopass_separated<SG_MINSTD>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0], a.L,
                                colour, a.minstd_a, a.pkey[0], a.t, a.T);
         else if (a.prng == SG_PHILOX)
-            hipLaunchKernelGGL(k_twopass_sliced<SG_PHILOX>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0], a.L,
+            hipLaunchKernelGGL(k_twopass_separated<SG_PHILOX>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0], a.L,
                                colour, a.minstd_a, a.pkey[0], a.t, a.T);
         else
-            hipLaunchKernelGGL(k_twopass_sliced<SG_MT19937>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0],
+            hipLaunchKernelGGL(k_twopass_separated<SG_MT19937>, dim3(g), dim3(kBlock), 0, s, S, K, a.rnd[0], a.mk[0],
                                a.L, colour, a.minstd_a, a.pkey[0], a.t, a.T);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <array>
+#include <atomic>
 #include <limits>
 #include <map>
 #include <mutex>
@@ -50,7 +51,8 @@ int check_hip(hipError_t e, const char *what)
     return hip_fail(e, what);
 }
 
-uint64_t g_coupling_id = 1;  // identity of caller-provided coupling sets
+// numbers handed to caller-provided coupling sets, one per sg_lattice_create
+std::atomic<uint64_t> g_coupling_sets{1};
 }  // namespace
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -107,10 +109,13 @@ using namespace sg;
 
 namespace {
 
-// The handle handed out: the lattice plus the identity of its couplings
-// (lattices with equal ids hold the same couplings).
+// The handle handed out: the lattice plus the identity of its couplings.  Two
+// lattices hold the same couplings when both fields agree: kind kFromSeed with
+// the same coupling seed, or kind kFromCaller with the same set number.
+enum CouplingKind { kFromSeed = 1, kFromCaller = 2 };
 struct Handle : sg_lattice {
-    uint64_t coupling_id = 0;
+    int coupling_kind = 0;
+    uint64_t coupling_value = 0;
 };
 
 Handle *H(sg_lattice *p) { return static_cast<Handle *>(p); }
@@ -320,22 +325,106 @@ int count_to_host(sg_lattice *lat, int nblocks, int64_t *out)
     return SG_OK;
 }
 
+// nsweeps two-pass sweeps of lat on a layout of the study of Sec. 2: the
+// current spins and the couplings are converted into `work` (32 bytes per site,
+// checked by the caller), swept there, and the spins converted back.
+struct LayoutOps {
+    hipError_t (*to)(const uint64_t *, uint64_t *, int, int, int64_t, hipStream_t);
+    hipError_t (*from)(const uint64_t *, uint64_t *, int, hipStream_t);
+    hipError_t (*sweep)(const SweepArgs &, uint64_t *, const uint64_t *, hipStream_t);
+    const char *name;
+};
+const LayoutOps kSeparated{launch_to_separated, launch_from_separated, launch_sweep_separated, "separated"};
+const LayoutOps kSliced{launch_to_sliced, launch_from_sliced, launch_sweep_sliced, "sliced"};
+
+int layout_sweep(sg_lattice *lat, int64_t nsweeps, double beta, uint64_t *work, const LayoutOps &ops)
+{
+    uint64_t T[3];
+    sg_thresholds(beta, lat->prng, T);
+    const int64_t V = lat->V;
+    uint64_t *S = work;
+    uint64_t *K = S + V;
+    const std::string nm(ops.name);
+    hipError_t e = ops.to(lat->spins[lat->cur], S, lat->L, 1, lat->V, lat->stream);
+    if (e == hipSuccess)
+        e = ops.to(lat->J, K, lat->L, 3, coupling_stride(lat->L), lat->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, ("to " + nm + " layout").c_str());
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        const int64_t t = lat->t;
+        if (buffered_draws(lat->prng)) {
+            e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream)
+                                        : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream);
+            lat->rlast = 0;
+            if (e != hipSuccess)
+                return hip_fail(e, "stream fill");
+        }
+        SweepArgs a{};
+        a.J = nullptr;
+        a.nrep = 1;
+        a.L = lat->L;
+        a.prng = buffered_draws(lat->prng) ? SG_MT19937 : lat->prng;
+        a.minstd_a = minstd_multiplier(t);
+        a.t = t;
+        a.T = Thresholds{T[0], T[1], T[2]};
+        a.rnd[0] = lat->rbuf;
+        a.mk[0] = lat->minstd_k;
+        a.pkey[0] = lat->key_philox;
+        e = ops.sweep(a, S, K, lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, (nm + " sweep").c_str());
+        lat->t += 1;
+    }
+    e = ops.from(S, lat->spins[lat->cur], lat->L, lat->stream);
+    return e == hipSuccess ? SG_OK : hip_fail(e, ("from " + nm + " layout").c_str());
+}
+
+int layout_sweep_checked(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes,
+                         const LayoutOps &ops)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    size_t need = 0;
+    sg_sliced_footprint(lat->L, &need);
+    if (!work || work_bytes < need)
+        return fail(SG_EINVAL, "layout work buffer too small: need " + std::to_string(need) + " bytes");
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0)
+        return fail(SG_EINVAL, "layout work buffer must be 256-byte aligned");
+    return layout_sweep(lat, nsweeps, beta, static_cast<uint64_t *>(work), ops);
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *sg_last_error(void) { return g_err.c_str(); }
 
-int sg_footprint(int L, int prng, int own_couplings, size_t *dev_bytes)
+static int footprint(int L, int nsamples, int prng, bool own_couplings, size_t *dev_bytes)
 {
     if (!valid_L(L))
         return fail(SG_EINVAL, "L must be even and in [2, 2048]");
+    if (nsamples < 1 || nsamples > 64)
+        return fail(SG_EINVAL, "nsamples must be in [1, 64]");
     if (!valid_prng(prng))
         return fail(SG_EINVAL, "unknown prng");
     if (!dev_bytes)
         return fail(SG_EINVAL, "dev_bytes is NULL");
-    *dev_bytes = carve(L, prng, own_couplings != 0).total;
+    *dev_bytes = carve(L, prng, own_couplings).total;
     return SG_OK;
+}
+
+int sg_footprint(int L, int nsamples, int prng, size_t *dev_bytes)
+{
+    return footprint(L, nsamples, prng, true, dev_bytes);
+}
+
+int sg_replica_footprint(int L, int nsamples, int prng, size_t *dev_bytes)
+{
+    return footprint(L, nsamples, prng, false, dev_bytes);
 }
 
 int sg_thresholds(double beta, int prng, uint64_t T[3])
@@ -386,13 +475,15 @@ int sg_lattice_create(int L, int nsamples, int prng, const uint64_t *J_host, uin
         for (int d = 0; d < 3 && e == hipSuccess; ++d)
             e = hipMemcpyAsync(lat->J + d * coupling_stride(L), J_host + (size_t)d * lat->V, (size_t)8 * lat->V,
                                hipMemcpyHostToDevice, lat->stream);
-        lat->coupling_id = (g_coupling_id++) << 1;  // even: caller's couplings
+        lat->coupling_kind = kFromCaller;
+        lat->coupling_value = g_coupling_sets.fetch_add(1);
         if (e == hipSuccess)
             e = hipStreamSynchronize(lat->stream);  // J_host is only borrowed
     } else {
         lat->key_j = derive_key(coupling_seed, kTagJ, 0);
         e = launch_init_couplings(lat->J, L, lat->key_j, lat->stream);
-        lat->coupling_id = (coupling_seed << 1) | 1;  // odd: generated from a seed
+        lat->coupling_kind = kFromSeed;
+        lat->coupling_value = coupling_seed;
     }
     if (e != hipSuccess) {
         delete lat;
@@ -431,7 +522,8 @@ int sg_lattice_create_replica(const sg_lattice *base, uint64_t spin_seed, uint32
     lat->J = base->J;
     lat->J_owner = base->J_owner ? base->J_owner : base;
     lat->coupling_seed = base->coupling_seed;
-    lat->coupling_id = H(base)->coupling_id;
+    lat->coupling_kind = H(base)->coupling_kind;
+    lat->coupling_value = H(base)->coupling_value;
     lat->kernel = base->kernel;
     lat->tile_x = base->tile_x;
     lat->tile_y = base->tile_y;
@@ -503,57 +595,14 @@ int sg_sliced_footprint(int L, size_t *dev_bytes)
     return SG_OK;
 }
 
+int sg_sweep_separated(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes)
+{
+    return layout_sweep_checked(lat, nsweeps, beta, work, work_bytes, kSeparated);
+}
+
 int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes)
 {
-    if (!lat)
-        return fail(SG_EINVAL, "NULL lattice");
-    if (nsweeps < 0)
-        return fail(SG_EINVAL, "nsweeps < 0");
-    if (check_beta(beta) != SG_OK)
-        return SG_EINVAL;
-    size_t need = 0;
-    sg_sliced_footprint(lat->L, &need);
-    if (!work || work_bytes < need)
-        return fail(SG_EINVAL, "sliced work buffer too small: need " + std::to_string(need) + " bytes");
-    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0)
-        return fail(SG_EINVAL, "sliced work buffer must be 256-byte aligned");
-    uint64_t T[3];
-    sg_thresholds(beta, lat->prng, T);
-    const int64_t V = lat->V;
-    uint64_t *S = static_cast<uint64_t *>(work);
-    uint64_t *K = S + V;
-    hipError_t e = launch_to_sliced(lat->spins[lat->cur], S, lat->L, 1, lat->V, lat->stream);
-    if (e == hipSuccess)
-        e = launch_to_sliced(lat->J, K, lat->L, 3, coupling_stride(lat->L), lat->stream);
-    if (e != hipSuccess)
-        return hip_fail(e, "to sliced layout");
-    for (int64_t k = 0; k < nsweeps; ++k) {
-        const int64_t t = lat->t;
-        if (buffered_draws(lat->prng)) {
-            e = lat->prng == SG_MT19937 ? launch_mt_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream)
-                                        : launch_pr_fill(&lat->mt_state, &lat->rbuf, 1, lat->L, t, 1, lat->stream);
-            lat->rlast = 0;
-            if (e != hipSuccess)
-                return hip_fail(e, "stream fill");
-        }
-        SweepArgs a{};
-        a.J = nullptr;
-        a.nrep = 1;
-        a.L = lat->L;
-        a.prng = buffered_draws(lat->prng) ? SG_MT19937 : lat->prng;
-        a.minstd_a = minstd_multiplier(t);
-        a.t = t;
-        a.T = Thresholds{T[0], T[1], T[2]};
-        a.rnd[0] = lat->rbuf;
-        a.mk[0] = lat->minstd_k;
-        a.pkey[0] = lat->key_philox;
-        e = launch_sweep_sliced(a, S, K, lat->stream);
-        if (e != hipSuccess)
-            return hip_fail(e, "sliced sweep");
-        lat->t += 1;
-    }
-    e = launch_from_sliced(S, lat->spins[lat->cur], lat->L, lat->stream);
-    return e == hipSuccess ? SG_OK : hip_fail(e, "from sliced layout");
+    return layout_sweep_checked(lat, nsweeps, beta, work, work_bytes, kSliced);
 }
 
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin)
@@ -581,7 +630,8 @@ int sg_overlap(const sg_lattice *a, const sg_lattice *b, int64_t *ndiff, double 
 {
     if (!a || !b)
         return fail(SG_EINVAL, "NULL lattice");
-    if (a->L != b->L || a->nsamples != b->nsamples || H(a)->coupling_id != H(b)->coupling_id)
+    if (a->L != b->L || a->nsamples != b->nsamples || H(a)->coupling_kind != H(b)->coupling_kind ||
+        H(a)->coupling_value != H(b)->coupling_value)
         return fail(SG_EMISMATCH, "overlap needs lattices of equal size, samples and couplings");
     sg_lattice *wa = const_cast<sg_lattice *>(a);
     if (b->stream != a->stream) {
@@ -618,7 +668,7 @@ int sg_get_words(const sg_lattice *lat, uint64_t *out, size_t n)
     return check_hip(e, "get words");
 }
 
-int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n)
+int sg_set_spins(sg_lattice *lat, const uint64_t *in, size_t n)
 {
     if (!lat || !in)
         return fail(SG_EINVAL, "NULL argument");
@@ -627,7 +677,7 @@ int sg_set_words(sg_lattice *lat, const uint64_t *in, size_t n)
     hipError_t e = hipMemcpyAsync(lat->spins[lat->cur], in, 8 * n, hipMemcpyHostToDevice, lat->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(lat->stream);
-    return check_hip(e, "set words");
+    return check_hip(e, "set spins");
 }
 
 int sg_get_couplings(const sg_lattice *lat, uint64_t *out, size_t n)
@@ -683,17 +733,13 @@ int sg_get_randoms(const sg_lattice *lat, uint32_t *out, size_t n)
     if (buffered_draws(lat->prng)) {
         e = hipMemcpyAsync(out, lat->rbuf + (size_t)lat->rlast * n, 4 * n, hipMemcpyDeviceToHost, lat->stream);
     } else {
-        // MINSTD draws are a function of (site, sweep): evaluate the last sweep's on
-        // the host with the device's own seed and jump functions
-        const uint32_t a = minstd_multiplier(lat->t - 1);
-        const uint32_t LL = (uint32_t)lat->L * (uint32_t)lat->L;
-        for (int z = 0; z < lat->L; ++z) {
-            const uint32_t zk = minstd_plane_key((uint32_t)z, lat->minstd_k);
-            for (uint32_t xy = 0; xy < LL; ++xy)
-                out[(size_t)z * LL + xy] = minstd_jump(a, minstd_seed(xy, zk));
-        }
-        e = hipSuccess;
-        return check_hip(e, "get randoms");
+        // MINSTD draws are a function of (site, sweep): a kernel evaluates the last
+        // sweep's with the sweep kernels' own seed and jump functions, into the spare
+        // spin buffer (free between calls: the next fused sweep writes all of it)
+        uint32_t *dev = reinterpret_cast<uint32_t *>(lat->spins[1 - lat->cur]);
+        e = launch_minstd_draws(dev, lat->L, minstd_multiplier(lat->t - 1), lat->minstd_k, lat->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, dev, 4 * n, hipMemcpyDeviceToHost, lat->stream);
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(lat->stream);
@@ -722,6 +768,68 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
     lat->rlast = 0;
     lat->t = t;
     return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
+}
+
+int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int blocks, void *stream)
+{
+    if (kind < 0 || kind > 2)
+        return fail(SG_EINVAL, "kind must be 0 (read), 1 (copy) or 2 (fill)");
+    if (blocks == 0)
+        blocks = 4096;
+    if (blocks < 1 || blocks > 65536)
+        return fail(SG_EINVAL, "blocks must be in [1, 65536]");
+    if (bytes < 16 || (bytes & 15) != 0)
+        return fail(SG_EINVAL, "bytes must be a positive multiple of 16");
+    if (!dst || (kind != 2 && !src))
+        return fail(SG_EINVAL, "NULL buffer");
+    if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) != 0)
+        return fail(SG_EINVAL, "buffers must be 16-byte aligned");
+    return check_hip(launch_probe(kind, dst, src, bytes, blocks, static_cast<hipStream_t>(stream)), "probe launch");
+}
+
+int sg_stream_state_bytes(const sg_lattice *lat, size_t *bytes)
+{
+    if (!lat || !bytes)
+        return fail(SG_EINVAL, "NULL argument");
+    const size_t cols = (size_t)lat->L * lat->L;
+    *bytes = lat->prng == SG_MT19937 ? 4 * (size_t)kMtN * cols : lat->prng == SG_PARISI_RAPUANO ? 4 * 64 * cols : 0;
+    return SG_OK;
+}
+
+int sg_get_stream_state(const sg_lattice *lat, void *out, size_t bytes)
+{
+    size_t need = 0;
+    if (sg_stream_state_bytes(lat, &need) != SG_OK)
+        return SG_EINVAL;
+    if (bytes != need || (need > 0 && !out))
+        return fail(SG_EINVAL, "bytes must be sg_stream_state_bytes() (" + std::to_string(need) + ")");
+    if (need == 0)
+        return SG_OK;
+    hipError_t e = hipMemcpyAsync(out, lat->mt_state, need, hipMemcpyDeviceToHost, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    return check_hip(e, "get stream state");
+}
+
+int sg_set_stream_state(sg_lattice *lat, const void *in, size_t bytes, int64_t t)
+{
+    size_t need = 0;
+    if (sg_stream_state_bytes(lat, &need) != SG_OK)
+        return SG_EINVAL;
+    if (t < 0)
+        return fail(SG_EINVAL, "t < 0");
+    if (bytes != need || (need > 0 && !in))
+        return fail(SG_EINVAL, "bytes must be sg_stream_state_bytes() (" + std::to_string(need) + ")");
+    if (need > 0) {
+        hipError_t e = hipMemcpyAsync(lat->mt_state, in, need, hipMemcpyHostToDevice, lat->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);  // `in` is only borrowed
+        if (e != hipSuccess)
+            return hip_fail(e, "set stream state");
+    }
+    lat->t = t;
+    lat->rlast = 0;
+    return SG_OK;
 }
 
 int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk, int band)

@@ -344,6 +344,8 @@ hipError_t launch_init_mt(uint32_t *state, int L, uint64_t key, hipStream_t s);
 hipError_t launch_mt_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
                           hipStream_t s);
 hipError_t launch_init_pr(uint32_t *state, int L, uint64_t key, hipStream_t s);
+// MINSTD numbers of sweep t (a = 16807^(t+1) mod (2^31 - 1)) of every site, out[V].
+hipError_t launch_minstd_draws(uint32_t *out, int L, uint32_t a, uint32_t mk, hipStream_t s);
 hipError_t launch_pr_fill(uint32_t *const *state, uint32_t *const *rbuf, int n, int L, int64_t t, int nsw,
                           hipStream_t s);
 // Generators whose numbers are read from a per-sweep buffer filled beforehand.
@@ -365,12 +367,19 @@ struct SweepArgs {
     Thresholds T;
 };
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
-// Colour-separated layout: conversion of nwords cube arrays (stride V), and a sweep
-// of one lattice (a.src[0] unused) on sliced spins S [2][V/2] and couplings K [3][2][V/2].
-// nwords arrays of the cube layout, src_stride words apart, to the sliced layout
-hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sliced, int L, int nwords, int64_t src_stride,
+// Colour-separated layout: conversion of nwords cube arrays (src_stride words
+// apart), and a sweep of one lattice (a.src[0] unused) on separated spins S
+// [2][V/2] and couplings K [3][2][V/2].
+hipError_t launch_to_separated(const uint64_t *cube, uint64_t *sep, int L, int nwords, int64_t src_stride,
+                               hipStream_t s);
+hipError_t launch_from_separated(const uint64_t *sep, uint64_t *cube, int L, hipStream_t s);
+hipError_t launch_sweep_separated(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s);
+// Sliced layout (Sec. 2 coordinate transformation): site (x, y, z) at (x', y', z')
+// = (x, y - x, x - y + z) mod L, colour c = z' & 1, stored at [c][z'/2][y'][x'];
+// spins S [2][V/2] and each site's own couplings K [3][2][V/2].
+hipError_t launch_to_sliced(const uint64_t *cube, uint64_t *sl, int L, int nwords, int64_t src_stride,
                             hipStream_t s);
-hipError_t launch_from_sliced(const uint64_t *sliced, uint64_t *cube, int L, hipStream_t s);
+hipError_t launch_from_sliced(const uint64_t *sl, uint64_t *cube, int L, hipStream_t s);
 hipError_t launch_sweep_sliced(const SweepArgs &a, uint64_t *S, const uint64_t *K, hipStream_t s);
 bool fused_shape_ok(int L, int nrep, int tile_x, int tile_y, int z_chunk);
 void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk);
@@ -406,6 +415,9 @@ hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int
                               size_t lds, hipStream_t s);
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
 hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
+
+// Bandwidth probes (kind 0 read-only into dst[blocks*4] words, 1 copy, 2 fill).
+hipError_t launch_probe(int kind, void *dst, const void *src, size_t bytes, int blocks, hipStream_t s);
 
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,
                               hipStream_t s);

@@ -1,12 +1,16 @@
 """Summaries of rocprofv3 output for the sweep kernels.
 
 ``stats``: turn a ``--kernel-trace --stats --output-format csv`` run into a short
-markdown table.  ``traffic``: HBM bytes per launch of a kernel from two
+markdown table.  ``trace``: the same from the per-dispatch kernel trace, for the
+dispatches between the first two marker kernels (``k_probe_fill``; bench.py
+queues one right before and one right after its timed region), so that the
+table covers exactly the timed launches and no autotuner candidate.  ``traffic``: HBM bytes per launch of a kernel from two
 ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of a program that also made a
 device copy of known size (``bench.py --calibrate-copy``): each counter is scaled
 by what it reads for that copy, which moves exactly its size in each direction.
 
     python -m paper_1411_0127_amd.profiling stats  <stats.csv> <out.md> "<command>"
+    python -m paper_1411_0127_amd.profiling trace  <kernel_trace.csv> <out.md> "<command>"
     python -m paper_1411_0127_amd.profiling traffic <fetch.csv> <write.csv> <workload> <copy_bytes> "<command>"
 """
 from __future__ import annotations
@@ -60,6 +64,52 @@ def stats(csv_path: str, out_md: str, command: str) -> str:
         mx = float(r.get("MaxNs", 0)) / 1e3
         pct = float(r.get("Percentage", 0))
         lines.append(f"| `{short}` | {calls} | {avg:.2f} | {mn:.2f} | {mx:.2f} | {pct:.1f}% |")
+    lines.append("")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    return out_md
+
+
+MARKER_KERNEL = "k_probe_fill"
+
+
+def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name[: name.index(">") + 1] if "<" in name.split("(")[0] else name.split("(")[0]
+
+
+def _table(rows):
+    by = {}
+    for name, ns in rows:
+        by.setdefault(_short(name), []).append(ns)
+    total = sum(sum(v) for v in by.values()) or 1.0
+    lines = ["| kernel | calls | average (us) | min (us) | max (us) | total (ms) | share |",
+             "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | {len(v)} | {statistics.mean(v) / 1e3:.2f} | {min(v) / 1e3:.2f} | "
+                     f"{max(v) / 1e3:.2f} | {sum(v) / 1e6:.3f} | {100.0 * sum(v) / total:.1f}% |")
+    return lines
+
+
+def trace(csv_path: str, out_md: str, command: str) -> str:
+    rows = []
+    for r in csv.DictReader(open(csv_path)):
+        name = r.get("Kernel_Name") or r.get("Name") or ""
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        rows.append((t0, t1, name))
+    rows.sort()
+    marks = [k for k, (_, _, n) in enumerate(rows) if MARKER_KERNEL in n]
+    lines = ["# rocprofv3 kernel trace", "", f"Command: `{command}`", ""]
+    if len(marks) >= 2:
+        a, b = marks[0], marks[1]
+        inside = [(n, t1 - t0) for t0, t1, n in rows[a + 1:b]]
+        span = (rows[b][0] - rows[a][1]) / 1e6
+        lines += [f"Timed region (dispatches between the two marker fills): {len(inside)} dispatches, "
+                  f"{span:.3f} ms from the end of the first marker to the start of the second.", ""]
+        lines += _table(inside)
+        lines.append("")
+    lines += ["All dispatches of the program:", ""]
+    lines += _table([(n, t1 - t0) for t0, t1, n in rows])
     lines.append("")
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
@@ -122,6 +172,8 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "trace":
+        print(trace(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6]))
     else:

@@ -80,7 +80,7 @@ class GpuBackend:
     """libsg batches on one GPU; every lattice lives in its own torch buffer."""
 
     def __init__(self, device="cuda:0", max_lattices: int = 512, max_items: int = 1 << 20,
-                 rounds_per_graph: int = 0, autotune: bool = True):
+                 rounds_per_graph: int = 0, autotune: bool = True, persistent: bool = False):
         import torch
 
         from paper_1411_0127_amd import sg
@@ -92,6 +92,9 @@ class GpuBackend:
         self.batch = sg.Batch(max_lattices, max_items, self.stream, device=self.device)
         self.rounds_per_graph = rounds_per_graph
         self.autotune = autotune
+        self.persistent = bool(persistent)
+        if self.persistent:
+            raise NotImplementedError("persistent batch runs are not built yet")
         self._inflight = []  # events of queued runs; at most two are kept in flight
         self._tuned = set()
 
@@ -148,6 +151,10 @@ class GpuBackend:
     def release(self, lat):
         lat.close()
         del lat
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        self.batch.close()
 
 
 class SimBackend:

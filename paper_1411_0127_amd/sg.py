@@ -44,6 +44,7 @@ _sz = ctypes.c_size_t
 _d = ctypes.c_double
 SIGNATURES = {
     "sg_footprint": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "sg_replica_footprint": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
     "sg_lattice_create": (_i, [_i, _i, _i, _p, _u64, _u64, _u32, _p, _sz, _p, ctypes.POINTER(_p)]),
     "sg_lattice_create_replica": (_i, [_p, _u64, _u32, _p, _sz, _p, ctypes.POINTER(_p)]),
     "sg_sweep": (_i, [_p, _i64, _d]),
@@ -52,12 +53,15 @@ SIGNATURES = {
     "sg_overlap": (_i, [_p, _p, _p, _p]),
     "sg_get_spins": (_i, [_p, _p, _sz]),
     "sg_get_words": (_i, [_p, _p, _sz]),
-    "sg_set_words": (_i, [_p, _p, _sz]),
+    "sg_set_spins": (_i, [_p, _p, _sz]),
     "sg_get_couplings": (_i, [_p, _p, _sz]),
     "sg_get_randoms": (_i, [_p, _p, _sz]),
     "sg_thresholds": (_i, [_d, _i, _p]),
     "sg_sweep_count": (_i64, [_p]),
     "sg_set_sweep_count": (_i, [_p, _i64]),
+    "sg_stream_state_bytes": (_i, [_p, ctypes.POINTER(_sz)]),
+    "sg_get_stream_state": (_i, [_p, _p, _sz]),
+    "sg_set_stream_state": (_i, [_p, _p, _sz, _i64]),
     "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
     "sg_set_ring": (_i, [_p, _i]),
     "sg_get_kernel": (_i, [_p, _p]),
@@ -69,9 +73,11 @@ SIGNATURES = {
     "sg_batch_take_finished": (_i, [_p, ctypes.POINTER(_p), _i, ctypes.POINTER(_i)]),
     "sg_sliced_footprint": (_i, [_i, ctypes.POINTER(_sz)]),
     "sg_sweep_sliced": (_i, [_p, _i64, _d, _p, _sz]),
+    "sg_sweep_separated": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "sg_batch_destroy": (_i, [_p]),
+    "sg_probe_bandwidth": (_i, [_i, _p, _p, _sz, _i, _p]),
     "sg_destroy": (_i, [_p]),
     "sg_last_error": (ctypes.c_char_p, []),
 }
@@ -122,9 +128,20 @@ def sliced_footprint(L: int) -> int:
     return int(n.value)
 
 
-def footprint(L: int, prng="minstd", own_couplings: bool = True) -> int:
+def probe_bandwidth(kind: str, dst, src, nbytes: int, stream, blocks: int = 0):
+    """Queue a bandwidth probe (sg_probe_bandwidth): kind "read", "copy" or "fill";
+    dst / src are device tensors (src unused for "fill")."""
+    k = {"read": 0, "copy": 1, "fill": 2}[kind]
+    _check(lib.sg_probe_bandwidth(k, _p(dst.data_ptr()), _p(src.data_ptr()) if src is not None else None,
+                                  int(nbytes), int(blocks), _p(stream.cuda_stream)))
+
+
+def footprint(L: int, prng="minstd", own_couplings: bool = True, nsamples: int = 64) -> int:
+    """Device bytes of a lattice (sg_footprint), or of a replica sharing another
+    lattice's couplings (sg_replica_footprint) when own_couplings is False."""
     n = _sz()
-    _check(lib.sg_footprint(int(L), PRNGS[prng], int(bool(own_couplings)), ctypes.byref(n)))
+    f = lib.sg_footprint if own_couplings else lib.sg_replica_footprint
+    _check(f(int(L), int(nsamples), PRNGS[prng], ctypes.byref(n)))
     return int(n.value)
 
 
@@ -150,8 +167,11 @@ class Lattice:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self._base = _base
-        self.nbytes = footprint(self.L, self.prng, own_couplings=_base is None)
-        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.nbytes = footprint(self.L, self.prng, own_couplings=_base is None, nsamples=self.nsamples)
+        # allocated on the lattice's stream: the caching allocator then keeps the
+        # block from other streams until work queued on this one is done
+        with torch.cuda.stream(stream):
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         h = _p()
         sptr = _p(stream.cuda_stream)
         if _base is None:
@@ -178,12 +198,27 @@ class Lattice:
     def sweep(self, n: int, beta: float):
         _check(lib.sg_sweep(self.handle, int(n), float(beta)))
 
-    def sweep_sliced(self, n: int, beta: float, work=None):
-        """n sweeps on the colour-separated layout (sg_sweep_sliced); ``work`` is a
-        uint8 device tensor of sliced_footprint(L) bytes, allocated when None."""
+    def _layout_work(self, work):
+        torch = _torch()
         if work is None:
-            work = _torch().empty(sliced_footprint(self.L), dtype=_torch().uint8, device=self.buf.device)
+            with torch.cuda.stream(self.stream):
+                work = torch.empty(sliced_footprint(self.L), dtype=torch.uint8, device=self.buf.device)
+        elif work.device.type == "cuda":
+            work.record_stream(self.stream)  # queued work reads it after this call returns
+        return work
+
+    def sweep_sliced(self, n: int, beta: float, work=None):
+        """n sweeps on the sliced layout of Sec. 2 (sg_sweep_sliced); ``work`` is a
+        uint8 device tensor of sliced_footprint(L) bytes, allocated when None."""
+        work = self._layout_work(work)
         _check(lib.sg_sweep_sliced(self.handle, int(n), float(beta), _p(work.data_ptr()), int(work.numel())))
+        return work
+
+    def sweep_separated(self, n: int, beta: float, work=None):
+        """n sweeps on the colour-separated layout (sg_sweep_separated); ``work`` as
+        for sweep_sliced."""
+        work = self._layout_work(work)
+        _check(lib.sg_sweep_separated(self.handle, int(n), float(beta), _p(work.data_ptr()), int(work.numel())))
         return work
 
     def set_kernel(self, kind="auto", tile_x: int = 0, tile_y: int = 0, z_chunk: int = 0, band: int = 0):
@@ -225,9 +260,23 @@ class Lattice:
         _check(lib.sg_get_words(self.handle, _ptr(out), out.size))
         return out
 
-    def set_words(self, w: np.ndarray):
+    def set_spins(self, w: np.ndarray):
+        """Replace the spin words (uint64[L^3])."""
         w = np.ascontiguousarray(w, dtype=np.uint64)
-        _check(lib.sg_set_words(self.handle, _ptr(w), w.size))
+        _check(lib.sg_set_spins(self.handle, _ptr(w), w.size))
+
+    def stream_state(self) -> np.ndarray:
+        """Per-column stream states (uint8 bytes; empty for MINSTD and Philox)."""
+        n = _sz()
+        _check(lib.sg_stream_state_bytes(self.handle, ctypes.byref(n)))
+        out = np.empty(int(n.value), dtype=np.uint8)
+        _check(lib.sg_get_stream_state(self.handle, _ptr(out) if out.size else None, out.size))
+        return out
+
+    def set_stream_state(self, state: np.ndarray, t: int):
+        """Restore stream states taken at sweep count t (and set the count to t)."""
+        state = np.ascontiguousarray(state, dtype=np.uint8)
+        _check(lib.sg_set_stream_state(self.handle, _ptr(state) if state.size else None, state.size, int(t)))
 
     def couplings(self) -> np.ndarray:
         out = np.empty((3, self.V), dtype=np.uint64)
@@ -285,7 +334,8 @@ class Batch:
         n = _sz()
         _check(lib.sg_batch_footprint(int(max_lattices), int(max_items), ctypes.byref(n)))
         self.device = torch.device(device if device is not None else "cuda")
-        self.buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(stream):  # see Lattice: the block stays with the batch's stream
+            self.buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
         self.stream = stream
         h = _p()
         _check(lib.sg_batch_create(int(max_lattices), int(max_items), _p(self.buf.data_ptr()), int(n.value),

@@ -37,6 +37,50 @@ def test_library_exports_every_declared_symbol(sgmod):
     assert sorted(sgmod.SIGNATURES) == names, "binding and header disagree"
 
 
+# The calls the hot path's boundary must offer (lattice from L, sample count,
+# couplings and seed; sweeps at beta; energy; overlap; spins in and out), each
+# with its argument list.
+BOUNDARY = {
+    "sg_footprint": "int L, int nsamples, int prng, size_t *dev_bytes",
+    "sg_lattice_create": None,
+    "sg_lattice_create_replica": None,
+    "sg_sweep": "sg_lattice *lat, int64_t nsweeps, double beta",
+    "sg_sweep_replicas": "sg_lattice *const *lats, int n, int64_t nsweeps, double beta",
+    "sg_energy": "sg_lattice *lat, int64_t *unsat, double *e_per_spin",
+    "sg_overlap": "const sg_lattice *a, const sg_lattice *b, int64_t *ndiff, double *q",
+    "sg_get_spins": "const sg_lattice *lat, int8_t *out, size_t n",
+    "sg_set_spins": "sg_lattice *lat, const uint64_t *words_host, size_t n",
+    "sg_thresholds": "double beta, int prng, uint64_t T[3]",
+    "sg_sweep_count": "const sg_lattice *lat",
+    "sg_destroy": "sg_lattice *lat",
+    "sg_last_error": "void",
+}
+
+
+def test_header_declares_the_boundary_calls():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for name, args in BOUNDARY.items():
+        m = re.search(r"\b" + name + r"\s*\(([^)]*)\)\s*;", src)
+        assert m, f"{name} is not declared"
+        if args is not None:
+            got = " ".join(m.group(1).split())
+            assert got == args, (name, got)
+
+
+def test_every_declared_call_cites_its_passage():
+    """Each declaration is preceded by a comment naming the paper's section (or, for
+    the runtime calls with no counterpart in the paper, saying so)."""
+    src = open(HEADER).read()
+    body = src[src.index("extern \"C\" {"):]
+    blocks = re.split(r"\n\s*\n", body)
+    for blk in blocks:
+        names = re.findall(r"^\s*(?:const char \*|int64_t |int |typedef)\s*\**(sg_[a-z_]+)\s*\(", blk, flags=re.M)
+        if not names:
+            continue
+        comment = " ".join(re.findall(r"/\*.*?\*/", blk, flags=re.S))
+        assert re.search(r"Sec\. \d|App\. A|no counterpart in the paper|library runtime", comment, flags=re.I), names
+
+
 def test_library_is_built_for_gfx950(sgmod):
     data = open(sgmod.LIB_PATH, "rb").read()
     assert b"gfx950" in data
@@ -74,6 +118,10 @@ def test_footprint_sizes(sgmod):
     V = 256**3
     own = sgmod.footprint(256, "minstd", True)
     rep = sgmod.footprint(256, "minstd", False)
+    n = ctypes.c_size_t()
+    assert sgmod.lib.sg_footprint(256, 65, 0, ctypes.byref(n)) == sgmod.SG_EINVAL
+    assert sgmod.lib.sg_replica_footprint(256, 0, 0, ctypes.byref(n)) == sgmod.SG_EINVAL
+    assert sgmod.footprint(256, "minstd", True, nsamples=1) == own  # one bit per sample: same words
     # two spin buffers (8 B each) and three coupling words per site; MINSTD keeps
     # no per-site state, MT19937 a 624-word state per column and a draw per site
     assert own - rep >= 24 * V

@@ -50,6 +50,17 @@ def test_traffic_record_needs_the_current_kernel_source(monkeypatch):
 
 def test_cpu_baseline_record():
     b = load_bench()
-    r = b.cpu_baseline(dict(b.WORKLOADS["c0"]), 0.2)
-    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "ps/flip"
-    assert r["value"] > 0 and "L=16" in r["sample"]
+    r = b.cpu_baseline("c0", 2, threads=3)
+    assert r["kind"] == "oracle" and r["cores"] == 3 and r["unit"] == "ps/flip"
+    assert r["value"] > 0 and "L=16" in r["sample"] and "bit-planes 0 and 63" in r["sample"]
+    assert set(r["c0_L16_1000_sweeps"]) == {"threads_1", "threads_3"}
+    assert r["cpu_model"] and r["nproc"] >= 1
+
+
+def test_batch_bytes_count_two_sweep_rounds():
+    b = load_bench()
+    from paper_1411_0127_amd.serve import Job
+
+    # 40 B per site and round; a round is two sweeps, an odd last sweep one round
+    jobs = [Job(0, 32, 4, 1.0, 1, 2), Job(1, 64, 5, 1.0, 1, 2)]
+    assert b.batch_bytes(jobs) == 40 * 32**3 * 2 + 40 * 64**3 * 3

@@ -355,7 +355,7 @@ def test_parisi_rapuano_device_numbers_and_forward_moves(sg):
     w = b.words()
     c = sg.Lattice(L, 64, "parisi_rapuano", coupling_seed=2, spin_seed=3)
     c.set_sweep_count(2)  # regenerates the column streams forward
-    c.set_words(w)
+    c.set_spins(w)
     c.sweep(3, 0.9)
     assert np.array_equal(c.words(), a.words())
     with pytest.raises(sg.SGError):
@@ -410,8 +410,8 @@ def test_per_sample_numbers_split_identical_samples_on_the_gpu(sg):
     w0 = rng.integers(0, 2, size=V).astype(np.uint64) * np.uint64(0xFFFFFFFFFFFFFFFF)
     shared = sg.Lattice(L, 64, "minstd", couplings=J, spin_seed=5)
     own = sg.Lattice(L, 64, "philox", couplings=J, spin_seed=5)
-    shared.set_words(w0)
-    own.set_words(w0)
+    shared.set_spins(w0)
+    own.set_spins(w0)
     shared.sweep(4, 0.8)
     own.sweep(4, 0.8)
     ws = shared.words()
@@ -423,40 +423,56 @@ def test_per_sample_numbers_split_identical_samples_on_the_gpu(sg):
 
 
 # ---------------------------------------------------------------------------
-# colour-separated layout (the layout study): the same spins as the cube kernels
+# layout study: the colour-separated ("standard") layout and the sliced layout
+# of the coordinate transformation give the same spins as the cube kernels
 # ---------------------------------------------------------------------------
+def _layout_sweep(lat, layout, n, beta, work):
+    return lat.sweep_sliced(n, beta, work) if layout == "sliced" else lat.sweep_separated(n, beta, work)
+
+
+@pytest.mark.parametrize("layout", ["sliced", "separated"])
 @pytest.mark.parametrize("L", [2, 4, 8, 18, 32])
 @pytest.mark.parametrize("prng", ["minstd", "mt19937", "parisi_rapuano", "philox"])
-def test_sliced_layout_sweeps_match_the_oracle(sg, L, prng):
-    say("sliced", L, prng)
+def test_layout_sweeps_match_the_oracle(sg, layout, L, prng):
+    say("layout", layout, L, prng)
     lat = sg.Lattice(L, 64, prng, coupling_seed=5, spin_seed=6)
     ref = oracle_for(L, 64, prng, 5, 6)
     work = None
     t = 0
     for n, beta in [(1, 0.9), (2, 0.4), (3, 1.6), (0, 0.9)]:
-        work = lat.sweep_sliced(n, beta, work)
+        work = _layout_sweep(lat, layout, n, beta, work)
         ref.sweep(n, beta)
         t += n
         assert lat.t == t
-        assert_same(lat.words(), ref, 64, f"L={L} {prng} sliced after {t} sweeps")
+        assert_same(lat.words(), ref, 64, f"L={L} {prng} {layout} after {t} sweeps")
 
 
-def test_sliced_layout_equals_the_cube_kernels_at_L64(sg):
-    say("sliced vs cube L64")
+@pytest.mark.parametrize("layout", ["sliced", "separated"])
+def test_layouts_equal_the_cube_kernels_at_L64(sg, layout):
+    say("layout vs cube L64", layout)
     L = 64
     a = sg.Lattice(L, 64, "minstd", coupling_seed=9, spin_seed=10)
     b = sg.Lattice(L, 64, "minstd", coupling_seed=9, spin_seed=10)
     a.sweep(3, 0.8)      # fused kernels
-    b.sweep_sliced(3, 0.8)
+    _layout_sweep(b, layout, 3, 0.8, None)
     assert np.array_equal(a.words(), b.words())
     a.sweep(2, 1.3)
     b.set_kernel("twopass")
     b.sweep(1, 1.3)      # mixing layouts between calls keeps the trajectory
-    b.sweep_sliced(1, 1.3)
+    _layout_sweep(b, layout, 1, 1.3, None)
     assert np.array_equal(a.words(), b.words())
+    fn = sg.lib.sg_sweep_sliced if layout == "sliced" else sg.lib.sg_sweep_separated
     with pytest.raises(sg.SGError):
-        lib_small = sg.lib.sg_sweep_sliced(b.handle, 1, 1.0, None, 0)
-        sg._check(lib_small)
+        sg._check(fn(b.handle, 1, 1.0, None, 0))
+
+
+def test_sliced_layout_mt19937_at_L64_against_the_cube(sg):
+    say("sliced mt19937 L64")
+    a = sg.Lattice(64, 64, "mt19937", coupling_seed=3, spin_seed=4)
+    b = sg.Lattice(64, 64, "mt19937", coupling_seed=3, spin_seed=4)
+    a.sweep(5, 0.9)
+    b.sweep_sliced(5, 0.9)
+    assert np.array_equal(a.words(), b.words())
 
 
 # ---------------------------------------------------------------------------
@@ -491,7 +507,7 @@ def test_overlap_of_a_spin_flipped_copy(sg):
     say("overlap -1")
     a = sg.Lattice(12, 64, "minstd", coupling_seed=1, spin_seed=2)
     b = sg.Lattice.replica_of(a, spin_seed=2, replica=0)
-    b.set_words(~a.words())
+    b.set_spins(~a.words())
     nd, q = sg.overlap(a, b)
     assert np.all(nd == 12**3) and np.all(q == -1.0)
 
@@ -563,7 +579,7 @@ def test_zero_temperature_monotone_and_stream_free(sg):
     say("T=0")
     a = sg.Lattice(24, 64, "mt19937", coupling_seed=4, spin_seed=5, replica=0)
     b = sg.Lattice.replica_of(a, spin_seed=999, replica=7)
-    b.set_words(a.words())
+    b.set_spins(a.words())
     prev = a.energy()[0]
     for _ in range(5):
         a.sweep(1, math.inf)
@@ -588,7 +604,7 @@ def test_sweep_splitting_kernels_and_resume(sg):
     assert np.array_equal(two.words(), ref.words())
     # resume from a checkpoint of spins and the sweep count
     res = sg.Lattice(L, 64, "minstd", coupling_seed=2, spin_seed=3)
-    res.set_words(mid)
+    res.set_spins(mid)
     res.set_sweep_count(4)
     res.sweep(5, 0.85)
     assert np.array_equal(res.words(), ref.words())
@@ -600,9 +616,34 @@ def test_sweep_splitting_kernels_and_resume(sg):
     w = m2.words()
     m3 = sg.Lattice(16, 64, "mt19937", coupling_seed=2, spin_seed=3)
     m3.set_sweep_count(2)
-    m3.set_words(w)
+    m3.set_spins(w)
     m3.sweep(4, 0.85)
     assert np.array_equal(m3.words(), m1.words())
+
+
+@pytest.mark.parametrize("prng", ["mt19937", "parisi_rapuano", "minstd"])
+def test_mid_run_checkpoint_of_stream_states(sg, prng):
+    """Spins, stream states and sweep count taken mid-run resume a new lattice
+    bit-exactly (the column states of MT19937 / Parisi-Rapuano included)."""
+    say("checkpoint", prng)
+    L = 18
+    a = sg.Lattice(L, 64, prng, coupling_seed=2, spin_seed=3)
+    a.sweep(7, 0.85)
+    words, state, t = a.words(), a.stream_state(), a.t
+    assert state.size == {"mt19937": 4 * 624 * L * L, "parisi_rapuano": 4 * 64 * L * L, "minstd": 0}[prng]
+    a.sweep(5, 0.85)
+    b = sg.Lattice(L, 64, prng, coupling_seed=2, spin_seed=3)
+    b.sweep(1, 0.85)  # a lattice that has swept: its own streams are overwritten
+    b.set_spins(words)
+    b.set_stream_state(state, t)
+    assert b.t == 7
+    b.sweep(5, 0.85)
+    assert np.array_equal(a.words(), b.words())
+    ref = oracle_for(L, 64, prng, 2, 3)
+    ref.sweep(12, 0.85)
+    assert_same(b.words(), ref, 64, f"{prng} resumed at sweep 7")
+    with pytest.raises(sg.SGError):
+        b.set_stream_state(np.zeros(3, dtype=np.uint8), 1)
 
 
 def test_gauge_symmetry_at_L64(sg):
@@ -616,7 +657,7 @@ def test_gauge_symmetry_at_L64(sg):
     Jg = np.stack([J[d] ^ g ^ g[nb[d]] for d in range(3)])
     a = sg.Lattice(L, 64, "minstd", couplings=J, spin_seed=15)
     b = sg.Lattice(L, 64, "minstd", couplings=Jg, spin_seed=15)
-    b.set_words(a.words() ^ g)
+    b.set_spins(a.words() ^ g)
     for _ in range(6):
         a.sweep(1, 0.9)
         b.sweep(1, 0.9)
