@@ -415,7 +415,7 @@ def main():
     ap.add_argument("--sweep-scale", type=float, default=0.1, help="c3: sweep counts x this (c4: x this / 2)")
     ap.add_argument("--jobs", type=int, default=0, help="c3/c4: number of jobs (default 256 / 64)")
     ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
-    ap.add_argument("--persistent", type=int, default=0,
+    ap.add_argument("--persistent", type=int, default=1,
                     help="c3/c4: 1 = one persistent launch per run, 0 = one launch per round")
     ap.add_argument("--layout-ab", action="store_true",
                     help="also time the two-pass kernel on the cube, colour-separated and sliced layouts")

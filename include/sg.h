@@ -285,14 +285,17 @@ int sg_autotune(sg_lattice *const *lats, int n, int reps, int best[5], double *m
  * A batch holds lattices of any sizes (one replica each, SG_MINSTD, all on the
  * batch's stream, which must not be the legacy default stream when graphs are
  * used), each with its own inverse temperature and sweep count.  A run queues
- * rounds; a round advances every lattice that has sweeps left, all of them in one
- * launch (one work item per fused tile and z chunk of every lattice): by two
- * sweeps for a lattice on SG_KERNEL_AUTO or SG_KERNEL_FUSED2 whose tile allows
- * the two-sweep march (one for its odd last sweep), else by one.  The spins of
- * each lattice after n sweeps are bit-identical to n calls of sg_sweep on it
- * alone.  Lattices join with sg_batch_add and leave when their sweeps are done
- * (sg_batch_take_finished); both take effect at run boundaries.  A lattice must
- * not be swept or destroyed while it is in a batch. */
+ * rounds; a round advances every lattice that has sweeps left (one work item per
+ * fused tile and z chunk of every lattice): by two sweeps for a lattice on
+ * SG_KERNEL_AUTO or SG_KERNEL_FUSED2 whose tile allows the two-sweep march (one
+ * for its odd last sweep), else by one.  By default a run is one persistent launch
+ * that takes (round, item) entries from a queue and starts a lattice's round as
+ * soon as that lattice's previous round is done (sg_batch_set_persistent); the
+ * other form launches once per round.  The spins of each lattice after n sweeps
+ * are bit-identical to n calls of sg_sweep on it alone.  Lattices join with
+ * sg_batch_add and leave when their sweeps are done (sg_batch_take_finished);
+ * both take effect at run boundaries.  A lattice must not be swept or destroyed
+ * while it is in a batch. */
 typedef struct sg_batch sg_batch;
 
 /* Library runtime (the paper's nearest analog: k coded sample sets per launch,
@@ -313,6 +316,18 @@ int sg_batch_add(sg_batch *b, sg_lattice *lat, int64_t nsweeps, double beta);
  * as soon as the work is queued; lattices whose sweeps are all queued move to the
  * finished list.  *rounds_done (may be NULL) = rounds queued. */
 int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t *rounds_done);
+
+/* Library runtime.  on = 1: each run is one persistent launch (the default);
+ * on = 0: one launch per round.  spin_cap bounds the polls (about 1 us each) a
+ * workgroup of a persistent run makes while it waits for a lattice's previous
+ * round; past it the run gives up, every workgroup leaves, and sg_batch_check
+ * reports SG_EDEVICE (0 = the default, 2^22).  Takes effect at the next run. */
+int sg_batch_set_persistent(sg_batch *b, int on, uint32_t spin_cap);
+
+/* Library runtime.  Synchronise the batch's stream and report whether every
+ * persistent run queued so far completed (SG_OK) or gave up waiting
+ * (SG_EDEVICE: the lattices of that run hold no valid state). */
+int sg_batch_check(sg_batch *b);
 
 /* Library runtime.  Move up to max finished lattices to out[]; *n = how many. */
 int sg_batch_take_finished(sg_batch *b, sg_lattice **out, int max, int *n);

@@ -831,24 +831,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
     fused2_march<PRNG, NS>(p, xcd_item(blockIdx.x, gridDim.x), lds, Ring2Steps<NS>{});
 }
 
-// Many lattices per launch ("round").  Work items of all lattices are numbered
-// consecutively; item_lat maps an item to its lattice.  A lattice with two-sweep
-// rounds does sweeps 2r and 2r+1 of its run in round r (only 2r when that is its
-// last), otherwise sweep r; it takes part while that first sweep is below its
-// sweep count for this run.  Its current spins are buffer c0 ^ (r & 1).  The
-// round number is read from device memory, so a captured graph of rounds replays
-// without new arguments.
-__global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *__restrict__ E,
-                                                             const uint32_t *__restrict__ item_lat, int nitems,
-                                                             const int64_t *__restrict__ round_ctr)
+// One work item of a batch round: item `local` (tile and z chunk) of lattice e in
+// round r of the current run.  A lattice with two-sweep rounds does sweeps 2r and
+// 2r+1 of its run in round r (only 2r when that is its last), otherwise sweep r;
+// it takes part while that first sweep is below its sweep count for this run.
+// Its current spins are buffer c0 ^ (r & 1).
+__device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int local, uint64_t *lds)
 {
-    extern __shared__ uint64_t lds[];
-    const int item = xcd_group_item(blockIdx.x);
-    if (item >= nitems)
-        return;
-    const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
-    const BatchEntry &e = E[li];
-    const int64_t r = *round_ctr;
     const int64_t s0 = e.two ? 2 * r : r;  // first sweep of this round, counted from the run's start
     if (s0 >= e.nsweeps)
         return;
@@ -885,15 +874,126 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
         p.WO[0] = e.WO0;
         p.WO[1] = e.WO1;
         p.a2 = minstd_power(e.t0 + s0 + 1);
-        fused2_march<SG_MINSTD, kRing2Batch>(p, item - e.item0, lds, Ring2Steps<kRing2Batch>{});
+        fused2_march<SG_MINSTD, kRing2Batch>(p, local, lds, Ring2Steps<kRing2Batch>{});
     } else {
         p.EX = e.TXp + 2;
         p.EY = e.TY + 4;
         p.WE = e.WE;
         p.WO[0] = p.WO[1] = 0;
         p.a2 = 0;
-        fused_march<SG_MINSTD, 1>(p, item - e.item0, lds, std::make_integer_sequence<int, Ring<1>::value>{});
+        fused_march<SG_MINSTD, 1>(p, local, lds, std::make_integer_sequence<int, Ring<1>::value>{});
     }
+}
+
+// Many lattices per launch ("round").  Work items of all lattices are numbered
+// consecutively; item_lat maps an item to its lattice.  The round number is read
+// from device memory, so a captured graph of rounds replays without new
+// arguments.
+__global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *__restrict__ E,
+                                                             const uint32_t *__restrict__ item_lat, int nitems,
+                                                             const int64_t *__restrict__ round_ctr)
+{
+    extern __shared__ uint64_t lds[];
+    const int item = xcd_group_item(blockIdx.x);
+    if (item >= nitems)
+        return;
+    const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
+    const BatchEntry &e = E[li];
+    batch_item(e, *round_ctr, item - e.item0, lds);
+}
+
+// All rounds of a run in one launch.  The work of the run is a queue of
+// (round, item) pairs in round-major order: round r holds the items of the
+// lattices still active in it, which the host numbers first (lattices sorted by
+// the rounds they need), so its items are 0 .. cum[r+1] - cum[r] - 1.  Each
+// workgroup takes the next queue entry with an atomic counter, waits until its
+// lattice has finished the previous round (done[lattice] counts the lattice's
+// finished items in this run, so round r may start once it reaches r x items),
+// runs the item, makes its stores visible to the device and counts it done.
+//
+// Progress: an entry waits only for entries of an earlier round, which sit
+// earlier in the queue and so were taken by workgroups already running; the
+// earliest unfinished entry therefore never waits, whether or not all
+// workgroups are resident.  The wait is bounded all the same: past spin_cap
+// polls (or once another workgroup has given up) the workgroup sets *error and
+// leaves, and every waiting workgroup then leaves too, so the grid always
+// drains; the host reports the error.
+struct PersistentArgs {
+    const BatchEntry *E;
+    const uint32_t *item_lat;
+    const uint64_t *cum;   // [nrounds + 1], cum[0] = 0
+    int nrounds;
+    unsigned long long *queue;
+    uint32_t *done;        // per lattice
+    uint32_t *error;
+    uint32_t spin_cap;
+};
+
+__global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs a)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ unsigned long long s_k;
+    __shared__ uint32_t s_ok;
+    const uint64_t total = a.cum[a.nrounds];
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_k = atomicAdd(a.queue, 1ull);
+        __syncthreads();
+        const uint64_t k = s_k;
+        if (k >= total)
+            break;
+        // round of entry k: the largest r with cum[r] <= k
+        int lo = 0, hi = a.nrounds;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.cum[mid] <= k)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int item = (int)(k - a.cum[lo]);
+        const int li = __builtin_amdgcn_readfirstlane((int)a.item_lat[item]);
+        const BatchEntry &e = a.E[li];
+        if (threadIdx.x == 0) {
+            const uint32_t need = (uint32_t)lo * (uint32_t)e.nitems;
+            uint32_t polls = 0;
+            uint32_t ok = 1;
+            while (__hip_atomic_load(&a.done[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    ++polls > a.spin_cap) {
+                    __hip_atomic_fetch_or(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(32);
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok)
+            break;
+        // the previous round's words, written on any XCD, are visible from here on
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        batch_item(e, lo, item - e.item0, lds);
+        // this item's stores reach the device before it is counted; the barrier
+        // also keeps the next item's LDS writes after every wave's last read
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&a.done[li], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Clears the queue, the error flag and the per-lattice counters of a run.
+__global__ void k_persistent_reset(unsigned long long *queue, uint32_t *error, uint32_t *done, int nlat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *queue = 0ull;
+        *error = 0u;
+    }
+    for (int j = i; j < nlat; j += gridDim.x * blockDim.x)
+        done[j] = 0u;
 }
 
 }  // namespace
@@ -1067,6 +1167,34 @@ hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int
     if (grid > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_fused_batch, dim3((unsigned)grid), dim3(kMaxThreads), lds, s, E, item_lat, nitems, round_ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(const BatchEntry *E, const uint32_t *item_lat, const uint64_t *cum, int nrounds,
+                                   unsigned long long *queue, uint32_t *done, uint32_t *error, int nlat,
+                                   uint32_t spin_cap, size_t lds, int64_t total_items, hipStream_t s)
+{
+    if (nrounds < 1 || total_items < 1)
+        return hipSuccess;
+    if (lds > (size_t)max_lds_bytes())
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_persistent_reset, dim3(std::max(1, std::min(64, (nlat + 255) / 256))), dim3(256), 0, s,
+                       queue, error, done, nlat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // as many workgroups as can be resident at once (progress does not depend on
+    // it, see k_batch_persistent), at most one per queue entry
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_persistent, kMaxThreads, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, total_items);
+    PersistentArgs a{E, item_lat, cum, nrounds, queue, done, error, spin_cap};
+    hipLaunchKernelGGL(k_batch_persistent, dim3((unsigned)grid), dim3(kMaxThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -1,11 +1,18 @@
 // Batch runtime of libsg: many lattices of different sizes, temperatures and
 // sweep counts advanced together.  Each round advances every lattice that still
-// has sweeps to do, all of them in one launch of k_fused_batch (one work item per
-// tile and z chunk of every lattice): by two sweeps on the two-sweep march (one
-// for an odd last sweep), else by one.  Rounds run eagerly or replay a captured
-// hipGraph of `rounds_per_graph` rounds; the round number lives in device memory
-// so the graph needs no new arguments.  Lattices join and leave between runs: a
-// serving loop admits and retires at those boundaries.
+// has sweeps to do (one work item per tile and z chunk of every lattice): by two
+// sweeps on the two-sweep march (one for an odd last sweep), else by one.
+//
+// Two forms of a run.  Persistent (the default): all rounds of the run in one
+// launch of k_batch_persistent, whose workgroups take (round, item) entries from
+// a queue and start a lattice's round as soon as that lattice's previous round is
+// done, so lattices never wait for each other; with rounds_per_graph > 0 the
+// launch (and the reset of its counters) is captured once into a hipGraph and
+// replayed while the run's shape stays the same.  Per round: one launch of
+// k_fused_batch per round, eagerly or from a captured graph of rounds_per_graph
+// rounds (the round number lives in device memory, so the graph needs no new
+// arguments).  Lattices join and leave between runs: a serving loop admits and
+// retires at those boundaries.
 //
 // Every site update is the same arithmetic as a sweep of the lattice alone, with
 // the same keyed streams, so a lattice's spins after n sweeps do not depend on
@@ -28,6 +35,15 @@ struct sg_batch {
     sg::BatchEntry *d_entries = nullptr;
     uint32_t *d_item_lat = nullptr;
     int64_t *d_round = nullptr;
+    // persistent runs: queue counter, error flag, per-lattice counters, round table
+    unsigned long long *d_queue = nullptr;
+    uint32_t *d_error = nullptr;
+    uint32_t *d_done = nullptr;
+    uint64_t *d_cum = nullptr;
+    bool persistent = true;
+    uint32_t spin_cap = 1u << 22;
+    std::vector<uint64_t> h_cum;
+    std::vector<int> order;  // job indices in layout order (persistent: by rounds left, descending)
     std::vector<Job> jobs;
     std::vector<sg_lattice *> finished;
     std::vector<sg::BatchEntry> h_entries;
@@ -40,6 +56,9 @@ struct sg_batch {
     hipGraphExec_t exec = nullptr;
     int graph_rounds = 0, graph_items = -1;
     size_t graph_lds = 0;
+    bool graph_persistent = false;
+    uint64_t graph_total = 0;  // persistent graph: queue entries and lattices it was captured for
+    int graph_lat = 0;
 };
 
 namespace sg {
@@ -57,7 +76,11 @@ void drop_graph(sg_batch *b)
     b->graph = nullptr;
     b->graph_rounds = 0;
     b->graph_items = -1;
+    b->graph_total = 0;
 }
+
+// Rounds one persistent launch covers at most (size of the device round table).
+constexpr int kMaxPersistentRounds = 4096;
 
 // Tile of a lattice inside a batch: its chosen (autotuned) tile or the default of
 // its kernel; z chunks of the whole column up to L = 256 and half of it above for
@@ -96,7 +119,13 @@ int build_layout(sg_batch *b)
     b->h_item_lat.clear();
     size_t lds = 0;
     int items = 0;
-    for (size_t j = 0; j < b->jobs.size(); ++j) {
+    if (b->order.size() != b->jobs.size()) {
+        b->order.resize(b->jobs.size());
+        for (size_t j = 0; j < b->jobs.size(); ++j)
+            b->order[j] = (int)j;
+    }
+    for (size_t o = 0; o < b->order.size(); ++o) {
+        const size_t j = (size_t)b->order[o];
         BatchEntry &e = b->h_entries[j];
         const int rc = batch_tile(b->jobs[j].lat, e);
         if (rc != SG_OK)
@@ -133,7 +162,8 @@ int sg_batch_footprint(int max_lattices, int max_items, size_t *dev_bytes)
 {
     if (max_lattices < 1 || max_items < 1 || !dev_bytes)
         return fail(SG_EINVAL, "bad batch size");
-    *dev_bytes = align256(sizeof(BatchEntry) * (size_t)max_lattices) + align256(4 * (size_t)max_items) + 256;
+    *dev_bytes = align256(sizeof(BatchEntry) * (size_t)max_lattices) + align256(4 * (size_t)max_items) + 256 +
+                 align256(4 * (size_t)max_lattices) + align256(8 * (size_t)(kMaxPersistentRounds + 1)) + 256;
     return SG_OK;
 }
 
@@ -161,6 +191,12 @@ int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_b
     b->d_item_lat = reinterpret_cast<uint32_t *>(p);
     p += align256(4 * (size_t)max_items);
     b->d_round = reinterpret_cast<int64_t *>(p);
+    b->d_queue = reinterpret_cast<unsigned long long *>(p + 64);
+    b->d_error = reinterpret_cast<uint32_t *>(p + 128);
+    p += 256;
+    b->d_done = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * (size_t)max_lattices);
+    b->d_cum = reinterpret_cast<uint64_t *>(p);
     *out = b;
     return SG_OK;
 }
@@ -198,6 +234,26 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
     if (b->jobs.empty() || max_rounds == 0)
         return SG_OK;
     int rc = SG_OK;
+    if (b->persistent) {
+        // lattices in order of the rounds they still need, most first: the ones
+        // active in a round are then a prefix of the layout
+        std::vector<int64_t> need(b->jobs.size());
+        for (size_t j = 0; j < b->jobs.size(); ++j) {
+            BatchEntry e{};
+            rc = batch_tile(b->jobs[j].lat, e);
+            if (rc != SG_OK)
+                return rc;
+            need[j] = rounds_for(e, b->jobs[j].left);
+        }
+        std::vector<int> order(b->jobs.size());
+        for (size_t j = 0; j < order.size(); ++j)
+            order[j] = (int)j;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return need[x] > need[y]; });
+        if (order != b->order) {
+            b->order = order;
+            b->layout_dirty = true;
+        }
+    }
     if (b->layout_dirty) {
         rc = build_layout(b);
         if (rc != SG_OK)
@@ -207,6 +263,8 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
     for (size_t j = 0; j < b->jobs.size(); ++j)
         R = std::max(R, rounds_for(b->h_entries[j], b->jobs[j].left));
     R = std::min(R, max_rounds);
+    if (b->persistent)
+        R = std::min<int64_t>(R, kMaxPersistentRounds);
     // per-run lattice state: sweep count, current buffer, sweeps in this run
     for (size_t j = 0; j < b->jobs.size(); ++j) {
         BatchEntry &e = b->h_entries[j];
@@ -231,15 +289,80 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_item_lat, b->h_item_lat.data(), 4 * b->h_item_lat.size(), hipMemcpyHostToDevice,
                            b->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !b->persistent)
         e = launch_round_reset(b->d_round, b->stream);
     if (e != hipSuccess)
         return hip_fail(e, "batch setup");
 
     int64_t done = 0;
     const int G = rounds_per_graph;
-    if (G > 0 && R >= G) {
-        if (!b->exec || b->graph_rounds != G || b->graph_items != b->nitems || b->graph_lds != b->lds) {
+    if (b->persistent) {
+        // round table: entries before round r, counting the items of the lattices
+        // still active in each round (a prefix of the layout)
+        b->h_cum.assign((size_t)R + 1, 0);
+        size_t act = b->order.size();
+        uint64_t items_act = (uint64_t)b->nitems;
+        for (int64_t r = 0; r < R; ++r) {
+            while (act > 0) {
+                const size_t j = (size_t)b->order[act - 1];
+                const BatchEntry &en = b->h_entries[j];
+                if (rounds_for(en, en.nsweeps) > r)
+                    break;
+                items_act -= (uint64_t)en.nitems;
+                --act;
+            }
+            b->h_cum[(size_t)r + 1] = b->h_cum[(size_t)r] + items_act;
+        }
+        e = hipMemcpyAsync(b->d_cum, b->h_cum.data(), 8 * b->h_cum.size(), hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch round table");
+        auto record = [&]() -> hipError_t {
+            return launch_batch_persistent(b->d_entries, b->d_item_lat, b->d_cum, (int)R, b->d_queue, b->d_done,
+                                           b->d_error, (int)b->jobs.size(), b->spin_cap, b->lds,
+                                           (int64_t)b->h_cum.back(), b->stream);
+        };
+        if (G > 0) {
+            // the launch reads everything that changes between runs from device
+            // memory, so one captured graph serves every run of the same shape
+            if (!b->exec || !b->graph_persistent || b->graph_rounds != (int)R || b->graph_total != b->h_cum.back() ||
+                b->graph_lds != b->lds || b->graph_items != b->nitems || b->graph_lat != (int)b->jobs.size()) {
+                drop_graph(b);
+                e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess)
+                    return hip_fail(e, "begin capture");
+                const hipError_t le = record();
+                hipGraph_t graph = nullptr;
+                e = hipStreamEndCapture(b->stream, &graph);
+                if (le != hipSuccess) {
+                    if (graph)
+                        (void)hipGraphDestroy(graph);
+                    return hip_fail(le, "persistent batch launch");
+                }
+                if (e != hipSuccess)
+                    return hip_fail(e, "end capture");
+                b->graph = graph;
+                e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    drop_graph(b);
+                    return hip_fail(e, "graph instantiate");
+                }
+                b->graph_persistent = true;
+                b->graph_rounds = (int)R;
+                b->graph_total = b->h_cum.back();
+                b->graph_lat = (int)b->jobs.size();
+                b->graph_lds = b->lds;
+                b->graph_items = b->nitems;
+            }
+            e = hipGraphLaunch(b->exec, b->stream);
+        } else {
+            e = record();
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "persistent batch launch");
+        done = R;
+    } else if (G > 0 && R >= G) {
+        if (!b->exec || b->graph_persistent || b->graph_rounds != G || b->graph_items != b->nitems ||
+            b->graph_lds != b->lds) {
             drop_graph(b);
             e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess)
@@ -261,6 +384,7 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
                 drop_graph(b);
                 return hip_fail(e, "graph instantiate");
             }
+            b->graph_persistent = false;
             b->graph_rounds = G;
             b->graph_items = b->nitems;
             b->graph_lds = b->lds;
@@ -290,11 +414,42 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
         else
             keep.push_back(job);
     }
-    if (keep.size() != b->jobs.size())
+    if (keep.size() != b->jobs.size()) {
         b->layout_dirty = true;
+        b->order.clear();
+    }
     b->jobs.swap(keep);
     if (rounds_done)
         *rounds_done = done;
+    return SG_OK;
+}
+
+int sg_batch_set_persistent(sg_batch *b, int on, uint32_t spin_cap)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    if (on != 0 && on != 1)
+        return fail(SG_EINVAL, "on must be 0 or 1");
+    if ((on != 0) != b->persistent)
+        drop_graph(b);
+    b->persistent = on != 0;
+    b->spin_cap = spin_cap == 0 ? (1u << 22) : spin_cap;
+    return SG_OK;
+}
+
+int sg_batch_check(sg_batch *b)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    uint32_t err = 0;
+    hipError_t e = hipMemcpyAsync(&err, b->d_error, 4, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch check");
+    if (err != 0)
+        return fail(SG_EDEVICE, "a persistent batch run gave up waiting for a round (spin limit reached); the "
+                                "lattices of that run are not valid");
     return SG_OK;
 }
 

@@ -413,6 +413,11 @@ bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk,
 size_t fused_batch_lds_bytes(const BatchEntry &e);
 hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
                               size_t lds, hipStream_t s);
+// All rounds of a run in one launch (see k_batch_persistent): cum[r] = queue
+// entries before round r, item_lat in the order of lattices sorted by rounds left.
+hipError_t launch_batch_persistent(const BatchEntry *E, const uint32_t *item_lat, const uint64_t *cum, int nrounds,
+                                   unsigned long long *queue, uint32_t *done, uint32_t *error, int nlat,
+                                   uint32_t spin_cap, size_t lds, int64_t total_items, hipStream_t s);
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
 hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
 

@@ -77,10 +77,11 @@ def trace_served(n: int, rate: float, seed: int, sizes=(64, 128, 256, 512), temp
 # Backends
 # ---------------------------------------------------------------------------
 class GpuBackend:
-    """libsg batches on one GPU; every lattice lives in its own torch buffer."""
+    """libsg batches on one GPU; every lattice lives in its own torch buffer.  A run
+    is one persistent launch (persistent=True) or one launch per round."""
 
     def __init__(self, device="cuda:0", max_lattices: int = 512, max_items: int = 1 << 20,
-                 rounds_per_graph: int = 0, autotune: bool = True, persistent: bool = False):
+                 rounds_per_graph: int = 0, autotune: bool = True, persistent: bool = True):
         import torch
 
         from paper_1411_0127_amd import sg
@@ -93,8 +94,7 @@ class GpuBackend:
         self.rounds_per_graph = rounds_per_graph
         self.autotune = autotune
         self.persistent = bool(persistent)
-        if self.persistent:
-            raise NotImplementedError("persistent batch runs are not built yet")
+        self.batch.set_persistent(self.persistent)
         self._inflight = []  # events of queued runs; at most two are kept in flight
         self._tuned = set()
 
@@ -145,7 +145,8 @@ class GpuBackend:
         return self.batch.take_finished()
 
     def result(self, lat):
-        U, e = lat.energy()  # synchronises the stream up to this lattice's last round
+        self.batch.check()  # synchronises the stream; raises if a persistent run gave up
+        U, e = lat.energy()
         return {"unsat": U, "e": e}
 
     def release(self, lat):

@@ -77,6 +77,8 @@ SIGNATURES = {
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "sg_batch_destroy": (_i, [_p]),
+    "sg_batch_set_persistent": (_i, [_p, _i, _u32]),
+    "sg_batch_check": (_i, [_p]),
     "sg_probe_bandwidth": (_i, [_i, _p, _p, _sz, _i, _p]),
     "sg_destroy": (_i, [_p]),
     "sg_last_error": (ctypes.c_char_p, []),
@@ -324,7 +326,8 @@ def overlap(a: Lattice, b: Lattice):
 
 
 class Batch:
-    """Lattices of mixed sizes advanced together, one launch per round (sg_batch_*).
+    """Lattices of mixed sizes advanced together (sg_batch_*): one persistent launch
+    per run by default, or one launch per round.
 
     The lattices must be MINSTD single replicas created on ``stream``; use a
     non-default stream when rounds are replayed from graphs."""
@@ -342,6 +345,14 @@ class Batch:
                                    _p(stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
         self._members = {}  # handle value -> Lattice, keeps them alive while queued
+
+    def set_persistent(self, on: bool = True, spin_cap: int = 0):
+        """One persistent launch per run (True, the default) or one launch per round."""
+        _check(lib.sg_batch_set_persistent(self.handle, int(bool(on)), int(spin_cap)))
+
+    def check(self):
+        """Synchronise and raise if a persistent run gave up waiting."""
+        _check(lib.sg_batch_check(self.handle))
 
     def add(self, lat: Lattice, nsweeps: int, beta: float):
         _check(lib.sg_batch_add(self.handle, lat.handle, int(nsweeps), float(beta)))

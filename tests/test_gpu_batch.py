@@ -1,6 +1,7 @@
 """Batched sweeps (sg_batch_*): every lattice of a mixed batch must end bit-identical
 to the same lattice swept alone, and small ones to the oracle; graph replays are
-checked one by one against eager runs."""
+checked one by one against eager runs.  Both forms of a run are covered: one
+persistent launch per run (the default) and one launch per round."""
 import sys
 
 import numpy as np
@@ -53,11 +54,21 @@ def oracle_words(L, cs, ss, beta, n):
     return ref.words()
 
 
+MODES = ["persistent", "per_round"]
+
+
+def make_batch(sg, stream, mode, max_lat=16, max_items=100000):
+    b = sg.Batch(max_lat, max_items, stream)
+    b.set_persistent(mode == "persistent")
+    return b
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("graph", [0, 2, 3])
-def test_batch_matches_solo_and_oracle(env, graph):
+def test_batch_matches_solo_and_oracle(env, graph, mode):
     sg, stream = env
-    say("batch", graph)
-    b = sg.Batch(16, 100000, stream)
+    say("batch", graph, mode)
+    b = make_batch(sg, stream, mode)
     lats = []
     for (L, cs, ss, beta, n) in JOBS:
         lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
@@ -69,6 +80,7 @@ def test_batch_matches_solo_and_oracle(env, graph):
     done = b.run(1000, graph)
     assert done == last
     assert b.rounds_left() == (0, 0)
+    b.check()
     fin = b.take_finished()
     assert sorted(id(x) for x in fin) == sorted(id(x) for x in lats)
     for lat, (L, cs, ss, beta, n) in zip(lats, JOBS):
@@ -80,17 +92,18 @@ def test_batch_matches_solo_and_oracle(env, graph):
     b.close()
 
 
-def test_batch_small_sides_and_kernel_choices(env):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_small_sides_and_kernel_choices(env, mode):
     """Sides below the two-sweep march's minimum take one-sweep rounds; a lattice set
     to the two-pass kernel (which a batch has no form of) takes the default march, one
     set to the one-sweep kernel one-sweep rounds.  Every result matches the oracle."""
     sg, stream = env
-    say("batch small sides and kernels")
+    say("batch small sides and kernels", mode)
     specs = [  # L, coupling seed, spin seed, beta, sweeps, kernel
         (2, 41, 42, 0.7, 5, "auto"), (4, 43, 44, 0.9, 4, "auto"), (6, 45, 46, 1.1, 3, "auto"),
         (16, 47, 48, 0.8, 5, "twopass"), (16, 49, 50, 0.8, 4, "fused"), (10, 51, 52, 1.3, 6, "fused2"),
     ]
-    b = sg.Batch(16, 100000, stream)
+    b = make_batch(sg, stream, mode)
     lats = []
     for (L, cs, ss, beta, n, kind) in specs:
         lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
@@ -99,16 +112,18 @@ def test_batch_small_sides_and_kernel_choices(env):
         lats.append(lat)
     b.run(1000, 2)
     assert b.rounds_left() == (0, 0)
+    b.check()
     for lat, (L, cs, ss, beta, n, kind) in zip(lats, specs):
         assert lat.t == n
         assert np.array_equal(lat.words(), oracle_words(L, cs, ss, beta, n)), f"L={L} {kind}"
     b.close()
 
 
-def test_batch_join_leave_in_chunks(env):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_join_leave_in_chunks(env, mode):
     sg, stream = env
-    say("batch join/leave")
-    b = sg.Batch(16, 100000, stream)
+    say("batch join/leave", mode)
+    b = make_batch(sg, stream, mode)
     pending = list(JOBS)
     live = {}
     rnd = 0
@@ -129,10 +144,11 @@ def test_batch_join_leave_in_chunks(env):
     b.close()
 
 
-def test_graph_replays_one_by_one(env):
+@pytest.mark.parametrize("mode", MODES)
+def test_graph_replays_one_by_one(env, mode):
     sg, stream = env
-    say("graph replays")
-    b = sg.Batch(4, 100000, stream)
+    say("graph replays", mode)
+    b = make_batch(sg, stream, mode, max_lat=4)
     specs = [(16, 31, 32, 0.9), (32, 33, 34, 1.1), (24, 35, 36, 0.6)]
     lats = []
     for (L, cs, ss, beta) in specs:
@@ -146,12 +162,88 @@ def test_graph_replays_one_by_one(env):
             solo.sweep(4, beta)
             lat.energy()  # eager work and a synchronisation between replays
             assert np.array_equal(lat.words(), solo.words()), f"replay {rep} L={L}"
+    b.check()
+    b.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_large_sides_with_tuned_tiles(env, mode):
+    """One lattice each of L = 64, 128, 256 and 512 with the autotuned tiles the
+    benchmark uses (pretuned as the server does), odd sweep counts, and runs replayed
+    from a graph at least twice: two z chunks of the two-sweep march at L = 512,
+    four of the one-sweep march for a lattice set to it at L = 256.  Each lattice
+    must equal the same lattice swept alone, L = 64 also the oracle."""
+    sg, stream = env
+    from paper_1411_0127_amd.serve import GpuBackend
+
+    say("batch large sides", mode)
+    be = GpuBackend(max_lattices=8, max_items=200000, rounds_per_graph=2, persistent=(mode == "persistent"))
+    be.pretune([64, 128, 256, 512])
+    specs = [  # L, coupling seed, spin seed, beta, sweeps, kernel
+        (64, 61, 62, 0.9, 7, None), (128, 63, 64, 1.1, 5, None), (256, 65, 66, 0.7, 9, None),
+        (512, 67, 68, 1.3, 5, None), (256, 69, 70, 1.0, 5, "fused"),
+    ]
+    b = make_batch(sg, be.stream, mode, max_lat=8, max_items=200000)
+    lats = []
+    for (L, cs, ss, beta, n, kind) in specs:
+        lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=be.stream)
+        if kind is None:
+            sg.autotune([lat], reps=3)  # cache hit: the pretuned shape
+        else:
+            lat.set_kernel(kind)
+        b.add(lat, n, beta)
+        lats.append(lat)
+    runs = 0
+    while b.rounds_left()[1] > 0:
+        b.run(2, 2)  # two-round runs: the graph of a run shape is replayed
+        runs += 1
+    assert runs >= 3
+    b.check()
+    for lat, (L, cs, ss, beta, n, kind) in zip(lats, specs):
+        assert lat.t == n
+        w = lat.words()
+        solo = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=be.stream)
+        if kind is None:
+            sg.autotune([solo], reps=3)
+        solo.sweep(n, beta)
+        assert np.array_equal(w, solo.words()), f"L={L} {kind} vs solo"
+        solo.close()
+        if L == 64:
+            assert np.array_equal(w, oracle_words(L, cs, ss, beta, n)), "L=64 vs oracle"
+        lat.close()
+    b.close()
+    be.close()
+
+
+def test_persistent_wait_limit_is_reported(env):
+    """A spin limit of one poll, forced from the host, makes a persistent run give
+    up at its first wait for a previous round: every workgroup leaves, the kernel
+    ends normally and sg_batch_check reports the failure."""
+    sg, stream = env
+    say("persistent wait limit")
+    b = make_batch(sg, stream, "persistent", max_lat=2)
+    b.set_persistent(True, spin_cap=1)
+    lat = sg.Lattice(16, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)
+    b.add(lat, 40, 1.0)  # twenty rounds of one work item each, every one waiting for the last
+    b.run(100, 0)
+    with pytest.raises(sg.SGError) as e:
+        b.check()
+    assert e.value.code == sg.SG_EDEVICE
+    # the batch keeps working with the default limit
+    b.set_persistent(True)
+    lat2 = sg.Lattice(16, 64, "minstd", coupling_seed=5, spin_seed=6, stream=stream)
+    b.add(lat2, 6, 1.0)
+    b.run(100, 0)
+    b.check()
+    assert np.array_equal(lat2.words(), oracle_words(16, 5, 6, 1.0, 6))
     b.close()
 
 
 def test_batch_argument_checks(env):
     sg, stream = env
     b = sg.Batch(1, 1000, stream)
+    with pytest.raises(sg.SGError):
+        sg._check(sg.lib.sg_batch_set_persistent(b.handle, 2, 0))
     lat = sg.Lattice(8, 64, "minstd", stream=stream)
     with pytest.raises(sg.SGError):
         b.add(lat, 0, 1.0)

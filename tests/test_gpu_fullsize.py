@@ -141,3 +141,80 @@ def test_beyond_two_to_the_31_sites():
     centers = [(L - 1, L - 1, L - 1), (0, L - 1, L - 1), (L - 2, 0, L - 1), (L // 2, L - 1, L - 2), (17, 33, L - 1)]
     centers += [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(25)]
     window_check(L, "minstd", 4, 5, 0, words, n, beta, centers)
+
+
+# ---------------------------------------------------------------------------
+# Whole bit-planes against the oracle at the full sizes: sample 0 and sample 63
+# of every site, the oracle running those two samples (they share the site's
+# numbers) threaded over the host's cores.
+# ---------------------------------------------------------------------------
+def _threads():
+    import os
+
+    env = os.environ.get("OMP_NUM_THREADS")
+    return int(env) if env and env.isdigit() and int(env) > 0 else max(1, min(16, os.cpu_count() or 1))
+
+
+def _planes_oracle(L, prng, cseed, sseed, replica):
+    planes = [0, 63]
+    seeds = (si.minstd_seeds_threaded(L, sseed, replica, _threads()) if prng == "minstd"
+             else si.mt_seeds(L, sseed, replica))
+    return oracle.OracleLattice.from_bits((L, L, L), si.coupling_bits(L, cseed, planes, _threads()),
+                                          si.spin_bits(L, sseed, replica, planes, _threads()),
+                                          oracle.MINSTD if prng == "minstd" else oracle.MT19937, seeds)
+
+
+def _assert_planes(words, ref, what, chunk=1 << 26):
+    for k, p in enumerate((0, 63)):
+        sh = np.uint64(p)
+        for a in range(0, words.size, chunk):
+            got = ((words[a:a + chunk] >> sh) & np.uint64(1)).astype(np.int8) * 2 - 1
+            if not np.array_equal(got, ref.s[k, a:a + chunk]):
+                bad = a + int(np.flatnonzero(got != ref.s[k, a:a + chunk])[0])
+                raise AssertionError(f"{what}: plane {p} differs, first at site {bad}")
+
+
+@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
+def test_L256_two_replicas_bit_planes_at_10_and_100_sweeps(prng):
+    """The L=256 two-replica configuration as the benchmark runs it (autotuned,
+    both replicas in one call), planes 0 and 63 of both replicas against the
+    oracle after 10 and after 100 sweeps."""
+    from paper_1411_0127_amd import sg
+
+    say("L256 bit planes 10/100", prng)
+    L, beta = 256, 1 / 0.7
+    a = sg.Lattice(L, 64, prng, coupling_seed=1, spin_seed=2, replica=0)
+    b = sg.Lattice.replica_of(a, spin_seed=2, replica=1)
+    sg.autotune([a, b], reps=2)
+    refs = [_planes_oracle(L, prng, 1, 2, r) for r in (0, 1)]
+    done = 0
+    for upto in (10, 100):
+        sg.sweep_replicas([a, b], upto - done, beta)
+        for lat, ref, r in ((a, refs[0], 0), (b, refs[1], 1)):
+            ref.run(upto - done, beta, threads=_threads())
+            _assert_planes(lat.words(), ref, f"{prng} replica {r} after {upto} sweeps")
+        done = upto
+    a.close()
+    b.close()
+
+
+def test_L1024_bit_planes_after_four_sweeps():
+    """The L=1024 configuration as the benchmark runs it (autotuned two-sweep
+    launches), planes 0 and 63 of all 2^30 sites against the oracle after four
+    sweeps."""
+    import torch
+
+    from paper_1411_0127_amd import sg
+
+    say("L1024 bit planes")
+    L, beta, n = 1024, 1 / 1.1, 4
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=1, spin_seed=2)
+    sg.autotune([lat], reps=2)
+    lat.sweep(n, beta)
+    words = lat.words()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ref = _planes_oracle(L, "minstd", 1, 2, 0)
+    ref.run(n, beta, threads=_threads())
+    _assert_planes(words, ref, f"L=1024 after {n} sweeps")
