@@ -170,6 +170,10 @@ def run_single(args, wl, prng=None, steps=None, warmup=None, marker=None, depth1
     elif args.kernel != "auto":
         for l in lats:
             l.set_kernel(args.kernel)
+    if args.pace:
+        every, slack = (int(v) for v in args.pace.split(","))
+        for l in lats:
+            l.set_pacing(every, slack)
     shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
     per_launch = 2 if shape[0] == "fused2" and nsw % 2 == 0 else 1
     every = wl.get("energy_every_sweep", False)
@@ -409,6 +413,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
     ap.add_argument("--tile", default="",
                     help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band[,planes] (skips the autotuner)")
+    ap.add_argument("--pace", default="", help="every,slack: pacing of the two-sweep march (default off)")
     ap.add_argument("--extras", default="peak,depth1,c1,c3,c4,cpu",
                     help="comma list of extra sections: peak, depth1, c1, c3, c4, cpu ('' for none)")
     ap.add_argument("--cpu-sweeps", type=int, default=1, help="sweeps of the oracle in cpu_baseline")

@@ -55,7 +55,16 @@ struct FusedParams {
     uint64_t pkey[2];    // per-sample numbers (SG_PHILOX): key per replica
     int64_t t;           // sweep index of the (first) sweep of this launch
     Thresholds T;
+    // pacing of the two-sweep march (pace_every = 0: off): every pace_every steps a
+    // workgroup counts itself on its group's counter (kPaceGroup consecutive work
+    // items, which run together on one XCD) and waits, a bounded time, until the
+    // group's slowest member is at most pace_slack counts behind
+    uint32_t *pace_ctr;
+    int pace_every, pace_slack, nitems;
+    int pace_grp, pace_members;  // set per work item
 };
+
+constexpr int kPaceGroup = 32;
 
 template <int NREP>
 struct Plane {
@@ -480,6 +489,13 @@ __device__ __forceinline__ uint32_t minstd_power(int64_t t)
     return (uint32_t)result;
 }
 
+__global__ void k_pace_reset(uint32_t *ctr, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        ctr[i] = 0u;
+}
+
 __global__ void k_round_advance(int64_t *round_ctr)
 {
     if (threadIdx.x == 0)
@@ -642,6 +658,24 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     }
 }
 
+// Pacing: count this workgroup's `paced`-th mark on its group's counter, then
+// poll (a bounded number of times: pacing only shapes timing, no result depends on
+// it) until every member of the group has made at least paced - pace_slack marks.
+__device__ __forceinline__ void pace_wait(const FusedParams &p, int paced)
+{
+    uint32_t *ctr = p.pace_ctr + p.pace_grp;
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int behind = paced - p.pace_slack;
+    if (behind <= 0)
+        return;
+    const uint32_t want = (uint32_t)behind * (uint32_t)p.pace_members;
+    for (int polls = 0; polls < 64; ++polls) {
+        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want)
+            return;
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
 // Planes in flight for the two-sweep march (a plane is requested NS-2 steps before
 // the step that first reads it): 5 or 6, chosen per lattice; batches use 5.
 constexpr int kRing2Batch = 5;
@@ -697,6 +731,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     __syncthreads();
 
     int k = kfirst;
+    int since = 0, paced = 0;  // pacing: steps since the last count, counts made
     uint32_t zk_prev = minstd_plane_key((uint32_t)wrap(kfirst - 1), p.mk[0]);
     // One step with ring slots (A, B, C) = planes (k-1, k, k+1); A's slot receives
     // plane k+NS-1 at the end.
@@ -724,6 +759,12 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
             const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
             st_pair(plane_rsrc(p.dst[0], q_store, (uint32_t)LL8), do_bb ? o_st : kOOB, wlo, whi);
             q_store = q_store + LL8 == V8 ? 0 : q_store + LL8;
+        }
+        if (p.pace_every > 0 && do_pub && ++since == p.pace_every) {
+            since = 0;
+            ++paced;
+            if (threadIdx.x == 0)
+                pace_wait(p, paced);  // the barrier below holds the other waves meanwhile
         }
         if (do_pub)
             __syncthreads();
@@ -758,6 +799,8 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     const int rep = item % pp.nrep;
     const int tile = item / pp.nrep;
     FusedParams p = pp;
+    p.pace_grp = item / kPaceGroup;
+    p.pace_members = min(kPaceGroup, pp.nitems - p.pace_grp * kPaceGroup);
     p.src[0] = pp.src[rep];
     p.dst[0] = pp.dst[rep];
     p.rnd[0] = pp.rnd[rep];
@@ -867,6 +910,9 @@ __device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int l
     p.pkey[0] = p.pkey[1] = 0;
     p.a = minstd_power(e.t0 + s0);
     p.T = Thresholds{e.t4, e.t8, e.t12};
+    p.pace_ctr = nullptr;
+    p.pace_every = p.pace_slack = 0;
+    p.nitems = e.nitems;
     if (deep) {
         p.EX = e.TXp + 4;
         p.EY = e.TY + 8;
@@ -1261,6 +1307,8 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.WE = fused_waves_even(tile_x, tile_y);
     p.WO[0] = p.WO[1] = 0;
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
+    p.pace_ctr = nullptr;
+    p.pace_every = p.pace_slack = 0;
     const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
     if (threads > max_threads(a.nrep) || lds > (size_t)max_lds_bytes())
@@ -1391,6 +1439,20 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
+    p.nitems = (int)blocks;
+    p.pace_ctr = a.pace_ctr;
+    p.pace_every = a.pace_ctr ? a.pace_every : 0;
+    p.pace_slack = a.pace_slack;
+    if (p.pace_every > 0) {
+        const int64_t groups = (blocks + kPaceGroup - 1) / kPaceGroup;
+        if (groups > a.pace_ctr_words)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_pace_reset, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, a.pace_ctr,
+                           (int)groups);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     void *args[] = {&p};
     return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)threads), args, lds, s);
     
