@@ -669,6 +669,7 @@ __device__ __forceinline__ void pace_wait(const FusedParams &p, int paced)
     if (behind <= 0)
         return;
     const uint32_t want = (uint32_t)behind * (uint32_t)p.pace_members;
+#pragma unroll 1
     for (int polls = 0; polls < 64; ++polls) {
         if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want)
             return;
