@@ -174,11 +174,11 @@ def _assert_planes(words, ref, what, chunk=1 << 26):
                 raise AssertionError(f"{what}: plane {p} differs, first at site {bad}")
 
 
-@pytest.mark.parametrize("prng", ["minstd", "mt19937"])
-def test_L256_two_replicas_bit_planes_at_10_and_100_sweeps(prng):
+@pytest.mark.parametrize("prng,checkpoints", [("minstd", (10, 100, 1000)), ("mt19937", (10, 100))])
+def test_L256_two_replicas_bit_planes_at_10_100_1000_sweeps(prng, checkpoints):
     """The L=256 two-replica configuration as the benchmark runs it (autotuned,
     both replicas in one call), planes 0 and 63 of both replicas against the
-    oracle after 10 and after 100 sweeps."""
+    oracle after 10, 100 and (MINSTD) 1000 sweeps."""
     from paper_1411_0127_amd import sg
 
     say("L256 bit planes 10/100", prng)
@@ -188,7 +188,7 @@ def test_L256_two_replicas_bit_planes_at_10_and_100_sweeps(prng):
     sg.autotune([a, b], reps=2)
     refs = [_planes_oracle(L, prng, 1, 2, r) for r in (0, 1)]
     done = 0
-    for upto in (10, 100):
+    for upto in checkpoints:
         sg.sweep_replicas([a, b], upto - done, beta)
         for lat, ref, r in ((a, refs[0], 0), (b, refs[1], 1)):
             ref.run(upto - done, beta, threads=_threads())
