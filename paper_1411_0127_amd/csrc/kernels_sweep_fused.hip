@@ -976,58 +976,86 @@ struct PersistentArgs {
     uint32_t spin_cap;
 };
 
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs a)
 {
     extern __shared__ uint64_t lds[];
-    __shared__ unsigned long long s_k;
-    __shared__ uint32_t s_ok;
+    // what wave 0 hands the workgroup for one entry: round, item, lattice, go on
+    __shared__ int s_round, s_item, s_lat;
+    __shared__ uint32_t s_go;
     const uint64_t total = a.cum[a.nrounds];
+    // Control flow here is uniform per wave: wave 0 does the hand-off with all its
+    // lanes (lane 0 alone is told apart by the amount it adds to a counter, never by
+    // a branch), and every decision is taken on readfirstlane values.  A branch on
+    // the lane id around this loop's back edge lets the compiler split the loop so
+    // that the other lanes reach the next barrier ahead of lane 0's counter updates.
+    const bool wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
+    const uint32_t one = (threadIdx.x & 63) == 0 ? 1u : 0u;
     for (;;) {
-        if (threadIdx.x == 0)
-            s_k = atomicAdd(a.queue, 1ull);
-        __syncthreads();
-        const uint64_t k = s_k;
-        if (k >= total)
-            break;
-        // round of entry k: the largest r with cum[r] <= k
-        int lo = 0, hi = a.nrounds;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.cum[mid] <= k)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const int item = (int)(k - a.cum[lo]);
-        const int li = __builtin_amdgcn_readfirstlane((int)a.item_lat[item]);
-        const BatchEntry &e = a.E[li];
-        if (threadIdx.x == 0) {
-            const uint32_t need = (uint32_t)lo * (uint32_t)e.nitems;
-            uint32_t polls = 0;
-            uint32_t ok = 1;
-            while (__hip_atomic_load(&a.done[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                    ++polls > a.spin_cap) {
-                    __hip_atomic_fetch_or(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
+        if (wave0) {
+            const uint64_t k = uniform64(atomicAdd(a.queue, (unsigned long long)one));
+            uint32_t go = k < total ? 1u : 0u;
+            int lo = 0, item = 0, li = 0;
+            if (go) {
+                // round of entry k: the largest r with cum[r] <= k
+                int hi = a.nrounds;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (uniform64(a.cum[mid]) <= k)
+                        lo = mid;
+                    else
+                        hi = mid;
                 }
-                __builtin_amdgcn_s_sleep(32);
+                item = (int)(k - uniform64(a.cum[lo]));
+                li = __builtin_amdgcn_readfirstlane((int)a.item_lat[item]);
+                const uint32_t need =
+                    (uint32_t)lo * (uint32_t)__builtin_amdgcn_readfirstlane((int)a.E[li].nitems);
+                uint32_t polls = 0;
+                for (;;) {
+                    const uint32_t d = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&a.done[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (d >= need)
+                        break;
+                    const uint32_t err = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (err != 0u || ++polls > a.spin_cap) {
+                        __hip_atomic_fetch_or(a.error, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        go = 0u;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(32);
+                }
             }
-            s_ok = ok;
+            // every lane of the wave writes the same values
+            s_round = lo;
+            s_item = item;
+            s_lat = li;
+            s_go = go;
         }
         __syncthreads();
-        if (!s_ok)
+        const uint32_t go = __builtin_amdgcn_readfirstlane(s_go);
+        const int lo = __builtin_amdgcn_readfirstlane(s_round);
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        const int li = __builtin_amdgcn_readfirstlane(s_lat);
+        if (go == 0u)
             break;
+        const BatchEntry &e = a.E[li];
         // the previous round's words, written on any XCD, are visible from here on
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         batch_item(e, lo, item - e.item0, lds);
         // this item's stores reach the device before it is counted; the barrier
-        // also keeps the next item's LDS writes after every wave's last read
+        // also keeps the next entry's LDS writes (the march's and wave 0's) after
+        // every wave's last read
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&a.done[li], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (wave0)
+            __hip_atomic_fetch_add(&a.done[li], one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

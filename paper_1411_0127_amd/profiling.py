@@ -7,7 +7,8 @@ queues one right before and one right after its timed region), so that the
 table covers exactly the timed launches and no autotuner candidate.  ``traffic``: HBM bytes per launch of a kernel from two
 ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of a program that also made a
 device copy of known size (``bench.py --calibrate-copy``): each counter is scaled
-by what it reads for that copy, which moves exactly its size in each direction.
+by what it reads for that copy, which moves exactly its size in each direction;
+only the sweep dispatches between the two marker fills count.
 
     python -m paper_1411_0127_amd.profiling stats  <stats.csv> <out.md> "<command>"
     python -m paper_1411_0127_amd.profiling trace  <kernel_trace.csv> <out.md> "<command>"
@@ -116,18 +117,31 @@ def trace(csv_path: str, out_md: str, command: str) -> str:
     return out_md
 
 
-def _per_dispatch(path: str, counter: str):
-    vals = {}
+def _per_dispatch(path: str, counter: str, timed_only: bool = False):
+    """Counter value per dispatch, by kernel name.  With timed_only, only the
+    dispatches between the first two marker fills (the timed region) count."""
+    rows = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        rows.append((int(r.get("Dispatch_Id") or 0), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort(key=lambda t: t[0])
+    if timed_only:
+        marks = [k for k, (_, n, _) in enumerate(rows) if MARKER_KERNEL in n]
+        if len(marks) >= 2:
+            rows = rows[marks[0] + 1:marks[1]]
+    vals = {}
+    for _, name, v in rows:
+        vals.setdefault(name, []).append(v)
     return vals
 
 
 def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str) -> str:
     f = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w = _per_dispatch(write_csv, "WRITE_SIZE")
+    # the sweep launches of the timed region only (no autotuner candidate)
+    ft = _per_dispatch(fetch_csv, "FETCH_SIZE", timed_only=True)
+    wt = _per_dispatch(write_csv, "WRITE_SIZE", timed_only=True)
 
     def pick(d, key):
         ks = [k for k in d if key in k]
@@ -135,9 +149,9 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
             raise SystemExit(f"no {key} dispatches in the counter file")
         return [v for k in ks for v in d[k]]
 
-    sweep_f = pick(f, SWEEP_KERNEL)
-    sweep_w = pick(w, SWEEP_KERNEL)
-    names = sorted({k for k in f if SWEEP_KERNEL in k})
+    sweep_f = pick(ft, SWEEP_KERNEL)
+    sweep_w = pick(wt, SWEEP_KERNEL)
+    names = sorted({k for k in ft if SWEEP_KERNEL in k})
     short = sorted({n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0] for n in names})
     copy_f = max(pick(f, COPY_KERNEL))
     copy_w = max(pick(w, COPY_KERNEL))
