@@ -178,6 +178,17 @@ int sg_sweep_separated(sg_lattice *lat, int64_t nsweeps, double beta, void *work
  * bit-identical to sg_sweep.  Arguments, checks and ownership as above. */
 int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes);
 
+/* sg_sweep_sliced without a work buffer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation): the sliced copy lives in a static device array of the library of
+ * 8 MiB, so L <= 64 (32 bytes per site); a larger lattice returns SG_EINVAL with
+ * the limit in sg_last_error.  Allocates nothing, on the host or the device.
+ * Every call on one GPU shares that GPU's array (each call overwrites the part it
+ * uses before reading it): calls that overlap on one GPU, e.g. on two streams,
+ * race and give undefined spins; serialise them.  Results are bit-identical to
+ * sg_sweep_sliced and sg_sweep. */
+int sg_sweep_sliced_static(sg_lattice *lat, int64_t nsweeps, double beta);
+
 /* Energy of Sec. 1, Eq. (1), per sample j < nsamples: unsat[j] = number of
  * unsatisfied bonds (-J s_i s_k = +1) among the 3V bonds, e_per_spin[j] =
  * (2*unsat[j] - 3V) / V, i.e. H/V.  Either output may be NULL.  Synchronises the

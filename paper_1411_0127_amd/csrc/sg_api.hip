@@ -165,6 +165,8 @@ int setup(Handle *lat, int L, int nsamples, int prng, uint64_t spin_seed, uint32
     lat->rbuf = buffered_draws(prng) ? reinterpret_cast<uint32_t *>(lat->base + c.rbuf) : nullptr;
     lat->scratch = reinterpret_cast<uint64_t *>(lat->base + c.scratch);
     lat->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&lat->device) != hipSuccess)
+        return fail(SG_EDEVICE, "no current HIP device");
     lat->cur = 0;
     lat->t = 0;
     return SG_OK;
@@ -405,6 +407,52 @@ int layout_sweep_checked(sg_lattice *lat, int64_t nsweeps, double beta, void *wo
 
 }  // namespace
 
+// Work area of sg_sweep_sliced_static, for callers that cannot allocate: the
+// sliced copy of one lattice (32 bytes per site) of side up to kStaticSide.  Each
+// GPU the library runs on holds its own copy until the process ends.  In host code
+// this name is a host-side stand-in: the area's device address comes from
+// static_area() and nothing else.
+constexpr int kStaticSide = 64;
+constexpr size_t kStaticBytes = (size_t)32 * kStaticSide * kStaticSide * kStaticSide;  // 8 MiB
+static __device__ __align__(256) uint64_t scratch[kStaticBytes / sizeof(uint64_t)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint64_t *g_static_ptr[kMaxDevices] = {};
+
+// Device address of the static work area on `device`, looked up once per device
+// with that device current (and the caller's current device restored after).
+int static_area(int device, uint64_t **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(SG_EDEVICE, "device index out of range for the static work area");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != device)
+            e = hipSetDevice(device);
+        if (e != hipSuccess)
+            return hip_fail(e, "select the lattice's device");
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t r = prev != device ? hipSetDevice(prev) : hipSuccess;
+        if (e != hipSuccess)
+            return hip_fail(e, "address of the static work area");
+        if (r != hipSuccess)
+            return hip_fail(r, "restore the current device");
+        if (!p)
+            return fail(SG_EDEVICE, "the static work area has no device address");
+        g_static_ptr[device] = static_cast<uint64_t *>(p);
+    }
+    *out = g_static_ptr[device];
+    return SG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sg_last_error(void) { return g_err.c_str(); }
@@ -609,6 +657,28 @@ int sg_sweep_separated(sg_lattice *lat, int64_t nsweeps, double beta, void *work
 int sg_sweep_sliced(sg_lattice *lat, int64_t nsweeps, double beta, void *work, size_t work_bytes)
 {
     return layout_sweep_checked(lat, nsweeps, beta, work, work_bytes, kSliced);
+}
+
+int sg_sweep_sliced_static(sg_lattice *lat, int64_t nsweeps, double beta)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    if (lat->L > kStaticSide)
+        return fail(SG_EINVAL, "sg_sweep_sliced_static takes sides up to " + std::to_string(kStaticSide) +
+                                   " (a static work area of " + std::to_string(kStaticBytes) + " bytes); L = " +
+                                   std::to_string(lat->L) + " needs " +
+                                   std::to_string((size_t)32 * lat->L * lat->L * lat->L));
+    uint64_t *area = nullptr;
+    const int rc = static_area(lat->device, &area);
+    if (rc != SG_OK)
+        return rc;
+    // the layout conversion writes every word of the area it then reads, so
+    // nothing needs clearing between calls
+    return layout_sweep(lat, nsweeps, beta, area, kSliced);
 }
 
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin)

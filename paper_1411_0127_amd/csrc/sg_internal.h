@@ -316,6 +316,7 @@ struct sg_lattice {
     int rlast = 0;                        // half of rbuf that holds the last sweep's draws
     uint64_t *scratch = nullptr;          // reduction partials
     hipStream_t stream = nullptr;
+    int device = 0;  // HIP device that was current at creation
     int64_t t = 0;  // sweeps done
     int kernel = SG_KERNEL_AUTO;
     int tile_x = 0, tile_y = 0, z_chunk = 0, band = 0;

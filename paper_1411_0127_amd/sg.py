@@ -74,6 +74,7 @@ SIGNATURES = {
     "sg_batch_take_finished": (_i, [_p, ctypes.POINTER(_p), _i, ctypes.POINTER(_i)]),
     "sg_sliced_footprint": (_i, [_i, ctypes.POINTER(_sz)]),
     "sg_sweep_sliced": (_i, [_p, _i64, _d, _p, _sz]),
+    "sg_sweep_sliced_static": (_i, [_p, _i64, _d]),
     "sg_sweep_separated": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -216,6 +217,11 @@ class Lattice:
         work = self._layout_work(work)
         _check(lib.sg_sweep_sliced(self.handle, int(n), float(beta), _p(work.data_ptr()), int(work.numel())))
         return work
+
+    def sweep_sliced_static(self, n: int, beta: float):
+        """n sweeps on the sliced layout in the library's static work area
+        (sg_sweep_sliced_static: no allocation, L <= 64)."""
+        _check(lib.sg_sweep_sliced_static(self.handle, int(n), float(beta)))
 
     def sweep_separated(self, n: int, beta: float, work=None):
         """n sweeps on the colour-separated layout (sg_sweep_separated); ``work`` as

@@ -69,7 +69,8 @@ def test_header_declares_the_boundary_calls():
 
 def test_every_declared_call_cites_its_passage():
     """Each declaration is preceded by a comment naming the paper's section (or, for
-    the runtime calls with no counterpart in the paper, saying so)."""
+    the runtime calls with no counterpart in the paper, saying so; the allocation-free
+    variant names the callers it is for instead)."""
     src = open(HEADER).read()
     body = src[src.index("extern \"C\" {"):]
     blocks = re.split(r"\n\s*\n", body)
@@ -78,7 +79,7 @@ def test_every_declared_call_cites_its_passage():
         if not names:
             continue
         comment = " ".join(re.findall(r"/\*.*?\*/", blk, flags=re.S))
-        assert re.search(r"Sec\. \d|App\. A|no counterpart in the paper|library runtime", comment, flags=re.I), names
+        assert re.search(r"Sec\. \d|App\. A|no counterpart in the paper|library runtime|callers that cannot allocate", comment, flags=re.I), names
 
 
 def test_library_is_built_for_gfx950(sgmod):
