@@ -8,7 +8,8 @@ table covers exactly the timed launches and no autotuner candidate.  ``traffic``
 ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of a program that also made a
 device copy of known size (``bench.py --calibrate-copy``): each counter is scaled
 by what it reads for that copy, which moves exactly its size in each direction;
-only the sweep dispatches between the two marker fills count.
+only the sweep dispatches between the two marker fills count, and only the copies
+after the second one (the autotuner copies spins before the timed region).
 
     python -m paper_1411_0127_amd.profiling stats  <stats.csv> <out.md> "<command>"
     python -m paper_1411_0127_amd.profiling trace  <kernel_trace.csv> <out.md> "<command>"
@@ -117,19 +118,21 @@ def trace(csv_path: str, out_md: str, command: str) -> str:
     return out_md
 
 
-def _per_dispatch(path: str, counter: str, timed_only: bool = False):
-    """Counter value per dispatch, by kernel name.  With timed_only, only the
-    dispatches between the first two marker fills (the timed region) count."""
+def _per_dispatch(path: str, counter: str, part: str = "all"):
+    """Counter value per dispatch, by kernel name.  part = "timed": only the
+    dispatches between the first two marker fills (the timed region); "after":
+    only those after the second (where bench.py makes its calibration copies)."""
     rows = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         rows.append((int(r.get("Dispatch_Id") or 0), r["Kernel_Name"], float(r["Counter_Value"])))
     rows.sort(key=lambda t: t[0])
-    if timed_only:
+    if part != "all":
         marks = [k for k, (_, n, _) in enumerate(rows) if MARKER_KERNEL in n]
-        if len(marks) >= 2:
-            rows = rows[marks[0] + 1:marks[1]]
+        if len(marks) < 2:
+            raise SystemExit("the counter file has no two marker fills")
+        rows = rows[marks[0] + 1:marks[1]] if part == "timed" else rows[marks[1] + 1:]
     vals = {}
     for _, name, v in rows:
         vals.setdefault(name, []).append(v)
@@ -137,11 +140,12 @@ def _per_dispatch(path: str, counter: str, timed_only: bool = False):
 
 
 def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str) -> str:
-    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    w = _per_dispatch(write_csv, "WRITE_SIZE")
-    # the sweep launches of the timed region only (no autotuner candidate)
-    ft = _per_dispatch(fetch_csv, "FETCH_SIZE", timed_only=True)
-    wt = _per_dispatch(write_csv, "WRITE_SIZE", timed_only=True)
+    # the sweep launches of the timed region only (no autotuner candidate), and the
+    # calibration copies made after it (not the autotuner's copies of the spins)
+    ft = _per_dispatch(fetch_csv, "FETCH_SIZE", "timed")
+    wt = _per_dispatch(write_csv, "WRITE_SIZE", "timed")
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE", "after")
+    w = _per_dispatch(write_csv, "WRITE_SIZE", "after")
 
     def pick(d, key):
         ks = [k for k in d if key in k]
@@ -153,8 +157,8 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
     sweep_w = pick(wt, SWEEP_KERNEL)
     names = sorted({k for k in ft if SWEEP_KERNEL in k})
     short = sorted({n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0] for n in names})
-    copy_f = max(pick(f, COPY_KERNEL))
-    copy_w = max(pick(w, COPY_KERNEL))
+    copy_f = statistics.median(pick(f, COPY_KERNEL))
+    copy_w = statistics.median(pick(w, COPY_KERNEL))
     # counters are in KiB; the copy read and wrote copy_bytes each
     f_scale = copy_bytes / (copy_f * 1024.0)
     w_scale = copy_bytes / (copy_w * 1024.0)
