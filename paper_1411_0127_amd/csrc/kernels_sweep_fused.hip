@@ -454,8 +454,8 @@ __device__ __forceinline__ int xcd_item(int b, int nb) { return (nb % 8 == 0) ? 
 // different sides): groups of kBatchGroup consecutive items are dealt to the XCDs
 // round robin, so every XCD gets a similar share of long and short items while the
 // items running together on one XCD stay neighbours.  The grid is a multiple of
-// 8 * kBatchGroup; this is a bijection of [0, grid).
-constexpr int kBatchGroup = 32;
+// kBatchQueues * kBatchGroup; this is a bijection of [0, grid).
+static_assert(kBatchQueues == 8, "blocks are dealt to the 8 XCDs round robin");
 __device__ __forceinline__ int xcd_group_item(int b)
 {
     const int x = b & 7, k = b >> 3;
@@ -949,28 +949,34 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
     batch_item(e, *round_ctr, item - e.item0, lds);
 }
 
-// All rounds of a run in one launch.  The work of the run is a queue of
-// (round, item) pairs in round-major order: round r holds the items of the
-// lattices still active in it, which the host numbers first (lattices sorted by
-// the rounds they need), so its items are 0 .. cum[r+1] - cum[r] - 1.  Each
-// workgroup takes the next queue entry with an atomic counter, waits until its
-// lattice has finished the previous round (done[lattice] counts the lattice's
-// finished items in this run, so round r may start once it reaches r x items),
-// runs the item, makes its stores visible to the device and counts it done.
+// All rounds of a run in one launch.  The work of the run is a set of (round,
+// item) entries, one queue per XCD: round r holds the items of the lattices still
+// active in it, which the host numbers first (lattices sorted by the rounds they
+// need), so its items are 0 .. n_r - 1, and they are dealt to the queues in groups
+// of kBatchGroup as the per-round launch deals them to the XCDs (group g to queue
+// g mod 8).  Each queue lists its entries in round-major order.  Workgroup b
+// starts on queue b mod 8, i.e. on the queue of the XCD it runs on, and moves to
+// the next queue once that one is empty.  It takes the next entry with an atomic
+// counter, waits until the entry's lattice has finished the previous round
+// (done[lattice] counts the lattice's finished items in this run, so round r may
+// start once it reaches r x items), runs the item, makes its stores visible to the
+// device and counts it done.
 //
-// Progress: an entry waits only for entries of an earlier round, which sit
-// earlier in the queue and so were taken by workgroups already running; the
-// earliest unfinished entry therefore never waits, whether or not all
-// workgroups are resident.  The wait is bounded all the same: past spin_cap
-// polls (or once another workgroup has given up) the workgroup sets *error and
-// leaves, and every waiting workgroup then leaves too, so the grid always
-// drains; the host reports the error.
+// Progress: an entry waits only for entries of an earlier round.  In its queue
+// those come first, so a workgroup holds an entry of round r only once every
+// entry of that queue's earlier rounds has been taken; an entry of an earlier
+// round is therefore either taken (by a running workgroup) or first in line in its
+// queue, which its home workgroups (and any workgroup whose own queue ran empty)
+// take next.  The wait is bounded all the same: past spin_cap polls (or once
+// another workgroup has given up) the workgroup sets *error and leaves, and every
+// waiting workgroup then leaves too, so the grid always drains; the host reports
+// the error.
 struct PersistentArgs {
     const BatchEntry *E;
     const uint32_t *item_lat;
-    const uint64_t *cum;   // [nrounds + 1], cum[0] = 0
+    const uint64_t *cum;   // [kBatchQueues][nrounds + 1], cum[q][0] = 0
     int nrounds;
-    unsigned long long *queue;
+    unsigned long long *queue;  // [kBatchQueues]
     uint32_t *done;        // per lattice
     uint32_t *error;
     uint32_t spin_cap;
@@ -989,7 +995,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
     // what wave 0 hands the workgroup for one entry: round, item, lattice, go on
     __shared__ int s_round, s_item, s_lat;
     __shared__ uint32_t s_go;
-    const uint64_t total = a.cum[a.nrounds];
     // Control flow here is uniform per wave: wave 0 does the hand-off with all its
     // lanes (lane 0 alone is told apart by the amount it adds to a counter, never by
     // a branch), and every decision is taken on readfirstlane values.  A branch on
@@ -997,22 +1002,36 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
     // that the other lanes reach the next barrier ahead of lane 0's counter updates.
     const bool wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
     const uint32_t one = (threadIdx.x & 63) == 0 ? 1u : 0u;
+    const int stride = a.nrounds + 1;
+    int q = (int)(blockIdx.x % kBatchQueues);  // current queue (wave 0's copy is the one used)
+    int qleft = kBatchQueues;                  // queues not yet found empty
     for (;;) {
         if (wave0) {
-            const uint64_t k = uniform64(atomicAdd(a.queue, (unsigned long long)one));
-            uint32_t go = k < total ? 1u : 0u;
+            uint32_t go = 0u;
             int lo = 0, item = 0, li = 0;
-            if (go) {
-                // round of entry k: the largest r with cum[r] <= k
-                int hi = a.nrounds;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (uniform64(a.cum[mid]) <= k)
-                        lo = mid;
-                    else
-                        hi = mid;
+            while (qleft > 0) {
+                const uint64_t *cq = a.cum + (size_t)q * stride;
+                const uint64_t total = uniform64(cq[a.nrounds]);
+                const uint64_t k = uniform64(atomicAdd(a.queue + q, (unsigned long long)one));
+                if (k < total) {
+                    // round of entry k: the largest r with cq[r] <= k
+                    int hi = a.nrounds;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (uniform64(cq[mid]) <= k)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    const int j = (int)(k - uniform64(cq[lo]));
+                    item = (q + kBatchQueues * (j / kBatchGroup)) * kBatchGroup + j % kBatchGroup;
+                    go = 1u;
+                    break;
                 }
-                item = (int)(k - uniform64(a.cum[lo]));
+                q = (q + 1) % kBatchQueues;
+                --qleft;
+            }
+            if (go) {
                 li = __builtin_amdgcn_readfirstlane((int)a.item_lat[item]);
                 const uint32_t need =
                     (uint32_t)lo * (uint32_t)__builtin_amdgcn_readfirstlane((int)a.E[li].nitems);
@@ -1059,14 +1078,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
     }
 }
 
-// Clears the queue, the error flag and the per-lattice counters of a run.
+// Clears the queues, the error flag and the per-lattice counters of a run.
 __global__ void k_persistent_reset(unsigned long long *queue, uint32_t *error, uint32_t *done, int nlat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        *queue = 0ull;
+    if (i < kBatchQueues)
+        queue[i] = 0ull;
+    if (i == 0)
         *error = 0u;
-    }
     for (int j = i; j < nlat; j += gridDim.x * blockDim.x)
         done[j] = 0u;
 }
@@ -1242,6 +1261,13 @@ hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int
     if (grid > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_fused_batch, dim3((unsigned)grid), dim3(kMaxThreads), lds, s, E, item_lat, nitems, round_ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(unsigned long long *queues, uint32_t *error, uint32_t *done, int nlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_persistent_reset, dim3(std::max(1, std::min(64, (nlat + 255) / 256))), dim3(256), 0, s,
+                       queues, error, done, nlat);
     return hipGetLastError();
 }
 

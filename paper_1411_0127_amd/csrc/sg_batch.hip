@@ -5,8 +5,9 @@
 //
 // Two forms of a run.  Persistent (the default): all rounds of the run in one
 // launch of k_batch_persistent, whose workgroups take (round, item) entries from
-// a queue and start a lattice's round as soon as that lattice's previous round is
-// done, so lattices never wait for each other; with rounds_per_graph > 0 the
+// one queue per XCD (items dealt to the XCDs as the per-round launch deals them)
+// and start a lattice's round as soon as that lattice's previous round is done, so
+// lattices never wait for each other; with rounds_per_graph > 0 the
 // launch (and the reset of its counters) is captured once into a hipGraph and
 // replayed while the run's shape stays the same.  Per round: one launch of
 // k_fused_batch per round, eagerly or from a captured graph of rounds_per_graph
@@ -35,7 +36,8 @@ struct sg_batch {
     sg::BatchEntry *d_entries = nullptr;
     uint32_t *d_item_lat = nullptr;
     int64_t *d_round = nullptr;
-    // persistent runs: queue counter, error flag, per-lattice counters, round table
+    // persistent runs: queue counters (one per XCD), error flag, per-lattice
+    // counters, round tables (one per queue)
     unsigned long long *d_queue = nullptr;
     uint32_t *d_error = nullptr;
     uint32_t *d_done = nullptr;
@@ -163,7 +165,8 @@ int sg_batch_footprint(int max_lattices, int max_items, size_t *dev_bytes)
     if (max_lattices < 1 || max_items < 1 || !dev_bytes)
         return fail(SG_EINVAL, "bad batch size");
     *dev_bytes = align256(sizeof(BatchEntry) * (size_t)max_lattices) + align256(4 * (size_t)max_items) + 256 +
-                 align256(4 * (size_t)max_lattices) + align256(8 * (size_t)(kMaxPersistentRounds + 1)) + 256;
+                 align256(4 * (size_t)max_lattices) +
+                 align256(8 * (size_t)kBatchQueues * (size_t)(kMaxPersistentRounds + 1)) + 256;
     return SG_OK;
 }
 
@@ -190,6 +193,7 @@ int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_b
     p += align256(sizeof(BatchEntry) * (size_t)max_lattices);
     b->d_item_lat = reinterpret_cast<uint32_t *>(p);
     p += align256(4 * (size_t)max_items);
+    static_assert(8 * kBatchQueues <= 64, "queue counters fit between the round counter and the error flag");
     b->d_round = reinterpret_cast<int64_t *>(p);
     b->d_queue = reinterpret_cast<unsigned long long *>(p + 64);
     b->d_error = reinterpret_cast<uint32_t *>(p + 128);
@@ -197,6 +201,13 @@ int sg_batch_create(int max_lattices, int max_items, void *dev_buf, size_t dev_b
     b->d_done = reinterpret_cast<uint32_t *>(p);
     p += align256(4 * (size_t)max_lattices);
     b->d_cum = reinterpret_cast<uint64_t *>(p);
+    // the error flag is read after runs of either form, so it starts cleared (the
+    // caller's buffer holds anything); persistent launches clear it again
+    const hipError_t e = launch_batch_reset(b->d_queue, b->d_error, b->d_done, max_lattices, b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch counters");
+    }
     *out = b;
     return SG_OK;
 }
@@ -297,34 +308,44 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
     int64_t done = 0;
     const int G = rounds_per_graph;
     if (b->persistent) {
-        // round table: entries before round r, counting the items of the lattices
-        // still active in each round (a prefix of the layout)
-        b->h_cum.assign((size_t)R + 1, 0);
+        // round tables, one per queue: entries before round r.  Round r has the
+        // items of the lattices still active in it (a prefix of the layout), dealt
+        // to the queues in groups of kBatchGroup, group g to queue g mod kBatchQueues.
+        const size_t stride = (size_t)R + 1;
+        b->h_cum.assign((size_t)kBatchQueues * stride, 0);
         size_t act = b->order.size();
-        uint64_t items_act = (uint64_t)b->nitems;
+        int64_t items_act = b->nitems;
         for (int64_t r = 0; r < R; ++r) {
             while (act > 0) {
                 const size_t j = (size_t)b->order[act - 1];
                 const BatchEntry &en = b->h_entries[j];
                 if (rounds_for(en, en.nsweeps) > r)
                     break;
-                items_act -= (uint64_t)en.nitems;
+                items_act -= en.nitems;
                 --act;
             }
-            b->h_cum[(size_t)r + 1] = b->h_cum[(size_t)r] + items_act;
+            for (int q = 0; q < kBatchQueues; ++q) {
+                int64_t cnt = 0;
+                for (int64_t g = q; g * kBatchGroup < items_act; g += kBatchQueues)
+                    cnt += std::min<int64_t>(kBatchGroup, items_act - g * kBatchGroup);
+                b->h_cum[(size_t)q * stride + (size_t)r + 1] = b->h_cum[(size_t)q * stride + (size_t)r] + (uint64_t)cnt;
+            }
         }
+        uint64_t total = 0;
+        for (int q = 0; q < kBatchQueues; ++q)
+            total += b->h_cum[(size_t)q * stride + (size_t)R];
         e = hipMemcpyAsync(b->d_cum, b->h_cum.data(), 8 * b->h_cum.size(), hipMemcpyHostToDevice, b->stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch round table");
         auto record = [&]() -> hipError_t {
             return launch_batch_persistent(b->d_entries, b->d_item_lat, b->d_cum, (int)R, b->d_queue, b->d_done,
-                                           b->d_error, (int)b->jobs.size(), b->spin_cap, b->lds,
-                                           (int64_t)b->h_cum.back(), b->stream);
+                                           b->d_error, (int)b->jobs.size(), b->spin_cap, b->lds, (int64_t)total,
+                                           b->stream);
         };
         if (G > 0) {
             // the launch reads everything that changes between runs from device
             // memory, so one captured graph serves every run of the same shape
-            if (!b->exec || !b->graph_persistent || b->graph_rounds != (int)R || b->graph_total != b->h_cum.back() ||
+            if (!b->exec || !b->graph_persistent || b->graph_rounds != (int)R || b->graph_total != total ||
                 b->graph_lds != b->lds || b->graph_items != b->nitems || b->graph_lat != (int)b->jobs.size()) {
                 drop_graph(b);
                 e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
@@ -348,7 +369,7 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
                 }
                 b->graph_persistent = true;
                 b->graph_rounds = (int)R;
-                b->graph_total = b->h_cum.back();
+                b->graph_total = total;
                 b->graph_lat = (int)b->jobs.size();
                 b->graph_lds = b->lds;
                 b->graph_items = b->nitems;

@@ -418,11 +418,19 @@ bool fill_batch_entry(BatchEntry &e, int L, int tile_x, int tile_y, int z_chunk,
 size_t fused_batch_lds_bytes(const BatchEntry &e);
 hipError_t launch_fused_batch(const BatchEntry *E, const uint32_t *item_lat, int nitems, const int64_t *round_ctr,
                               size_t lds, hipStream_t s);
-// All rounds of a run in one launch (see k_batch_persistent): cum[r] = queue
-// entries before round r, item_lat in the order of lattices sorted by rounds left.
+// Work items of a batch round are dealt to the XCDs in groups of kBatchGroup
+// consecutive items, group g to XCD g mod kBatchQueues (neighbouring tiles run
+// together on one XCD and share its L2).
+constexpr int kBatchGroup = 32;
+constexpr int kBatchQueues = 8;
+// All rounds of a run in one launch (see k_batch_persistent), one queue per XCD:
+// cum[q * (nrounds + 1) + r] = entries of queue q before round r; a round's
+// active items are the first ones of item_lat (lattices sorted by rounds left).
 hipError_t launch_batch_persistent(const BatchEntry *E, const uint32_t *item_lat, const uint64_t *cum, int nrounds,
-                                   unsigned long long *queue, uint32_t *done, uint32_t *error, int nlat,
+                                   unsigned long long *queues, uint32_t *done, uint32_t *error, int nlat,
                                    uint32_t spin_cap, size_t lds, int64_t total_items, hipStream_t s);
+// Clears the queue counters, the error flag and nlat per-lattice counters.
+hipError_t launch_batch_reset(unsigned long long *queues, uint32_t *error, uint32_t *done, int nlat, hipStream_t s);
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
 hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
 

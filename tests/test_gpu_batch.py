@@ -257,3 +257,34 @@ def test_batch_argument_checks(env):
     with pytest.raises(sg.SGError):
         b.add(other, 2, 1.0)
     b.close()
+
+
+def test_error_flag_starts_cleared_on_a_dirty_buffer(env):
+    """A batch built on a caller buffer full of ones reports no error after runs
+    of the per-round form, which never touch the flag: creation clears it."""
+    import ctypes
+
+    import torch
+
+    sg, stream = env
+    say("batch error flag on a dirty buffer")
+    n = ctypes.c_size_t()
+    sg._check(sg.lib.sg_batch_footprint(4, 1000, ctypes.byref(n)))
+    with torch.cuda.stream(stream):
+        buf = torch.full((int(n.value),), 0xFF, dtype=torch.uint8, device="cuda:0")
+    h = ctypes.c_void_p()
+    sg._check(sg.lib.sg_batch_create(4, 1000, ctypes.c_void_p(buf.data_ptr()), int(n.value),
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+    try:
+        sg._check(sg.lib.sg_batch_set_persistent(h, 0, 0))
+        lat = sg.Lattice(16, 64, "minstd", coupling_seed=7, spin_seed=8, stream=stream)
+        sg._check(sg.lib.sg_batch_add(h, lat.handle, 4, ctypes.c_double(1.0)))
+        done = ctypes.c_int64()
+        sg._check(sg.lib.sg_batch_run(h, 100, 0, ctypes.byref(done)))
+        sg._check(sg.lib.sg_batch_check(h))
+        assert np.array_equal(lat.words(), oracle_words(16, 7, 8, 1.0, 4))
+        lat.close()
+    finally:
+        sg.lib.sg_batch_destroy(h)
+        torch.cuda.synchronize()
+        del buf
