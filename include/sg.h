@@ -271,14 +271,6 @@ int sg_set_kernel(sg_lattice *lat, int kind, int tile_x, int tile_y, int z_chunk
  * sg_set_kernel. */
 int sg_set_ring(sg_lattice *lat, int planes);
 
-/* Library runtime.  Pacing of the two-sweep march: every `every` steps a
- * workgroup marks its progress on a counter shared by the 32 work items that run
- * together on one XCD and waits (a bounded time) until the group's slowest member
- * is at most `slack` marks behind, so that workgroups sharing tile-ring lines stay
- * at nearby planes while those lines are in L2.  every = 0 turns it off (the
- * default).  It only shapes timing; results do not depend on it. */
-int sg_set_pacing(sg_lattice *lat, int every, int slack);
-
 /* Library runtime.  The kernel the next sweeps of this lattice use: out[6] = kind (SG_KERNEL_TWOPASS,
  * _FUSED or _FUSED2), tile_x, tile_y, z_chunk (0 = chosen at launch), band, and the
  * planes in flight of the two-sweep march (0 for the others). */

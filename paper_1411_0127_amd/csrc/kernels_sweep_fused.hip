@@ -55,16 +55,7 @@ struct FusedParams {
     uint64_t pkey[2];    // per-sample numbers (SG_PHILOX): key per replica
     int64_t t;           // sweep index of the (first) sweep of this launch
     Thresholds T;
-    // pacing of the two-sweep march (pace_every = 0: off): every pace_every steps a
-    // workgroup counts itself on its group's counter (kPaceGroup consecutive work
-    // items, which run together on one XCD) and waits, a bounded time, until the
-    // group's slowest member is at most pace_slack counts behind
-    uint32_t *pace_ctr;
-    int pace_every, pace_slack, nitems;
-    int pace_grp, pace_members;  // set per work item
 };
-
-constexpr int kPaceGroup = 32;
 
 template <int NREP>
 struct Plane {
@@ -82,6 +73,7 @@ struct Plane {
 // wait for exactly the plane a step needs while later planes are in flight.
 constexpr uint32_t kOOB = 0x80000000u;
 constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer format word of gfx9 descriptors
+constexpr int kStoreDevice = 16;         // cache policy sc1: a store coherent at device scope
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -99,6 +91,10 @@ __device__ __forceinline__ void ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, 
     hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
 }
 
+// AUX is the store's cache policy: 0 for the sweeps of a launch (the kernel's end
+// makes them visible), kStoreDevice where other workgroups read the words in the
+// same launch (the persistent batch kernel).
+template <int AUX>
 __device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t lo, uint64_t hi)
 {
     u32x4 v;
@@ -106,7 +102,7 @@ __device__ __forceinline__ void st_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, 
     v.y = (uint32_t)(lo >> 32);
     v.z = (uint32_t)hi;
     v.w = (uint32_t)(hi >> 32);
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX);
 }
 
 // Per-lane byte offsets inside a plane (kOOB where the lane reads nothing).
@@ -300,7 +296,7 @@ struct Ring {
 };
 
 // The march of one tile: tile = tile index within the lattice (z chunk major).
-template <int PRNG, int NREP, int... Is>
+template <int PRNG, int NREP, int SAUX, int... Is>
 __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile, uint64_t *lds,
                                             std::integer_sequence<int, Is...>)
 {
@@ -418,7 +414,7 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
             const int64_t qo = (int64_t)wrap(k - 1) * LL * 8;                                                     \
             const uint32_t ost = do_blue ? o_st : kOOB;                                                           \
             _Pragma("unroll") for (int r = 0; r < NREP; ++r)                                                     \
-                st_pair(plane_rsrc(p.dst[r], qo, (uint32_t)(LL * 8)), ost, wlo[r], whi[r]);                       \
+                st_pair<SAUX>(plane_rsrc(p.dst[r], qo, (uint32_t)(LL * 8)), ost, wlo[r], whi[r]);                       \
         }                                                                                                         \
         if (do_pub)                                                                                               \
             __syncthreads();                                                                                      \
@@ -466,7 +462,7 @@ template <int PRNG, int NREP>
 __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused_march<PRNG, NREP>(p, xcd_item(blockIdx.x, gridDim.x), lds,
+    fused_march<PRNG, NREP, 0>(p, xcd_item(blockIdx.x, gridDim.x), lds,
                             std::make_integer_sequence<int, Ring<NREP>::value>{});
 }
 
@@ -487,13 +483,6 @@ __device__ __forceinline__ uint32_t minstd_power(int64_t t)
         e >>= 1;
     }
     return (uint32_t)result;
-}
-
-__global__ void k_pace_reset(uint32_t *ctr, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        ctr[i] = 0u;
 }
 
 __global__ void k_round_advance(int64_t *round_ctr)
@@ -658,25 +647,6 @@ __device__ __forceinline__ void fused2_step(const FusedParams &p, const Lane &c,
     }
 }
 
-// Pacing: count this workgroup's `paced`-th mark on its group's counter, then
-// poll (a bounded number of times: pacing only shapes timing, no result depends on
-// it) until every member of the group has made at least paced - pace_slack marks.
-__device__ __forceinline__ void pace_wait(const FusedParams &p, int paced)
-{
-    uint32_t *ctr = p.pace_ctr + p.pace_grp;
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int behind = paced - p.pace_slack;
-    if (behind <= 0)
-        return;
-    const uint32_t want = (uint32_t)behind * (uint32_t)p.pace_members;
-#pragma unroll 1
-    for (int polls = 0; polls < 64; ++polls) {
-        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want)
-            return;
-        __builtin_amdgcn_s_sleep(4);
-    }
-}
-
 // Planes in flight for the two-sweep march (a plane is requested NS-2 steps before
 // the step that first reads it): 5 or 6, chosen per lattice; batches use 5.
 constexpr int kRing2Batch = 5;
@@ -687,7 +657,7 @@ using Ring2Steps = std::make_integer_sequence<int, NS % 2 ? 2 * NS : NS>;  // un
 // first step) & 1 is the same for a whole wave; with an even ring the pair half
 // of ring slot i is then (P0 + i) & 1, known at compile time, so the steps of a
 // turn of the ring are straight-line code.
-template <int PRNG, int P0, int NS, int... Is>
+template <int PRNG, int P0, int NS, int SAUX, int... Is>
 __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, uint64_t *lds, const int z0,
                                            const int ZCe, const Offsets &o, const uint32_t o_st,
                                            const bool second, std::integer_sequence<int, Is...>)
@@ -732,7 +702,6 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     __syncthreads();
 
     int k = kfirst;
-    int since = 0, paced = 0;  // pacing: steps since the last count, counts made
     uint32_t zk_prev = minstd_plane_key((uint32_t)wrap(kfirst - 1), p.mk[0]);
     // One step with ring slots (A, B, C) = planes (k-1, k, k+1); A's slot receives
     // plane k+NS-1 at the end.
@@ -758,14 +727,8 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
                                     (uint32_t)wrap(k - 1), ar0, ab0, br0, bb0, r0, b0, jxl, jyulo, jyuhi);
         {
             const uint64_t wlo = H ? cy.br1 : bb0, whi = H ? bb0 : cy.br1;
-            st_pair(plane_rsrc(p.dst[0], q_store, (uint32_t)LL8), do_bb ? o_st : kOOB, wlo, whi);
+            st_pair<SAUX>(plane_rsrc(p.dst[0], q_store, (uint32_t)LL8), do_bb ? o_st : kOOB, wlo, whi);
             q_store = q_store + LL8 == V8 ? 0 : q_store + LL8;
-        }
-        if (p.pace_every > 0 && do_pub && ++since == p.pace_every) {
-            since = 0;
-            ++paced;
-            if (threadIdx.x == 0)
-                pace_wait(p, paced);  // the barrier below holds the other waves meanwhile
         }
         if (do_pub)
             __syncthreads();
@@ -792,7 +755,7 @@ __device__ __forceinline__ void fused2_run(const FusedParams &p, const Lane &c, 
     }
 }
 
-template <int PRNG, int NS, int... Is>
+template <int PRNG, int NS, int SAUX, int... Is>
 __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int item, uint64_t *lds,
                                              std::integer_sequence<int, Is...> seq)
 {
@@ -800,8 +763,6 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     const int rep = item % pp.nrep;
     const int tile = item / pp.nrep;
     FusedParams p = pp;
-    p.pace_grp = item / kPaceGroup;
-    p.pace_members = min(kPaceGroup, pp.nitems - p.pace_grp * kPaceGroup);
     p.src[0] = pp.src[rep];
     p.dst[0] = pp.dst[rep];
     p.rnd[0] = pp.rnd[rep];
@@ -863,16 +824,16 @@ __device__ __forceinline__ void fused2_march(const FusedParams &pp, const int it
     o.r = PRNG == SG_MT19937 && full ? col * 4u : kOOB;  // 4-byte draws
     const uint32_t o_st = inter ? col * 8u : kOOB;
     if ((ypar + z0 - 3 + p.L) & 1)
-        fused2_run<PRNG, 1, NS>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 1, NS, SAUX>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
     else
-        fused2_run<PRNG, 0, NS>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
+        fused2_run<PRNG, 0, NS, SAUX>(p, c, lds, z0, ZCe, o, o_st, !outer, seq);
 }
 
 template <int PRNG, int NS>
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused2_march<PRNG, NS>(p, xcd_item(blockIdx.x, gridDim.x), lds, Ring2Steps<NS>{});
+    fused2_march<PRNG, NS, 0>(p, xcd_item(blockIdx.x, gridDim.x), lds, Ring2Steps<NS>{});
 }
 
 // One work item of a batch round: item `local` (tile and z chunk) of lattice e in
@@ -880,6 +841,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 // 2r+1 of its run in round r (only 2r when that is its last), otherwise sweep r;
 // it takes part while that first sweep is below its sweep count for this run.
 // Its current spins are buffer c0 ^ (r & 1).
+template <int SAUX>
 __device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int local, uint64_t *lds)
 {
     const int64_t s0 = e.two ? 2 * r : r;  // first sweep of this round, counted from the run's start
@@ -911,9 +873,6 @@ __device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int l
     p.pkey[0] = p.pkey[1] = 0;
     p.a = minstd_power(e.t0 + s0);
     p.T = Thresholds{e.t4, e.t8, e.t12};
-    p.pace_ctr = nullptr;
-    p.pace_every = p.pace_slack = 0;
-    p.nitems = e.nitems;
     if (deep) {
         p.EX = e.TXp + 4;
         p.EY = e.TY + 8;
@@ -921,14 +880,14 @@ __device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int l
         p.WO[0] = e.WO0;
         p.WO[1] = e.WO1;
         p.a2 = minstd_power(e.t0 + s0 + 1);
-        fused2_march<SG_MINSTD, kRing2Batch>(p, local, lds, Ring2Steps<kRing2Batch>{});
+        fused2_march<SG_MINSTD, kRing2Batch, SAUX>(p, local, lds, Ring2Steps<kRing2Batch>{});
     } else {
         p.EX = e.TXp + 2;
         p.EY = e.TY + 4;
         p.WE = e.WE;
         p.WO[0] = p.WO[1] = 0;
         p.a2 = 0;
-        fused_march<SG_MINSTD, 1>(p, local, lds, std::make_integer_sequence<int, Ring<1>::value>{});
+        fused_march<SG_MINSTD, 1, SAUX>(p, local, lds, std::make_integer_sequence<int, Ring<1>::value>{});
     }
 }
 
@@ -946,7 +905,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused_batch(const BatchEntry *_
         return;
     const int li = __builtin_amdgcn_readfirstlane((int)item_lat[item]);
     const BatchEntry &e = E[li];
-    batch_item(e, *round_ctr, item - e.item0, lds);
+    batch_item<0>(e, *round_ctr, item - e.item0, lds);
 }
 
 // All rounds of a run in one launch.  The work of the run is a set of (round,
@@ -1066,12 +1025,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
             break;
         const BatchEntry &e = a.E[li];
         // the previous round's words, written on any XCD, are visible from here on
+        // (the acquire drops this XCD's stale lines)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        batch_item(e, lo, item - e.item0, lds);
-        // this item's stores reach the device before it is counted; the barrier
-        // also keeps the next entry's LDS writes (the march's and wave 0's) after
-        // every wave's last read
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        batch_item<kStoreDevice>(e, lo, item - e.item0, lds);
+        // The item's spin words went out as device-coherent stores, so they are
+        // visible to every XCD once they have completed: each wave waits for its
+        // stores, and the barrier orders all waves' before wave 0 counts the item.
+        // (An agent-scope release would instead write back this XCD's whole L2 at
+        // every item, which cost the batch a sixth of its speed.)  The barrier also
+        // keeps the next entry's LDS writes after every wave's last read.
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __syncthreads();
         if (wave0)
             __hip_atomic_fetch_add(&a.done[li], one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1362,8 +1327,6 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.WE = fused_waves_even(tile_x, tile_y);
     p.WO[0] = p.WO[1] = 0;
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
-    p.pace_ctr = nullptr;
-    p.pace_every = p.pace_slack = 0;
     const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
     if (threads > max_threads(a.nrep) || lds > (size_t)max_lds_bytes())
@@ -1494,23 +1457,8 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
-    p.nitems = (int)blocks;
-    p.pace_ctr = a.pace_ctr;
-    p.pace_every = a.pace_ctr ? a.pace_every : 0;
-    p.pace_slack = a.pace_slack;
-    if (p.pace_every > 0) {
-        const int64_t groups = (blocks + kPaceGroup - 1) / kPaceGroup;
-        if (groups > a.pace_ctr_words)
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_pace_reset, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, a.pace_ctr,
-                           (int)groups);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
     void *args[] = {&p};
     return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)threads), args, lds, s);
-    
 }
 
 }  // namespace sg

@@ -253,12 +253,6 @@ int sweep_launch(sg_lattice *const *lats, int n, const Thresholds &T, int kind, 
         a.pkey[r] = lats[r]->key_philox;
     }
     const int band = l0->band > 0 ? l0->band : 1;
-    if (l0->pace_every > 0) {  // pacing counters in the reduction area of the first lattice
-        a.pace_ctr = reinterpret_cast<uint32_t *>(l0->scratch);
-        a.pace_ctr_words = (int64_t)kMaxReduceBlocks * 64 * 2;
-        a.pace_every = l0->pace_every;
-        a.pace_slack = l0->pace_slack;
-    }
     int done = 1;
     if (kind == 2) {
         e = launch_sweep_fused2(a, tx, ty, zc, band, l0->ring, l0->stream);
@@ -861,17 +855,6 @@ int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int b
     if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) != 0)
         return fail(SG_EINVAL, "buffers must be 16-byte aligned");
     return check_hip(launch_probe(kind, dst, src, bytes, blocks, static_cast<hipStream_t>(stream)), "probe launch");
-}
-
-int sg_set_pacing(sg_lattice *lat, int every, int slack)
-{
-    if (!lat)
-        return fail(SG_EINVAL, "NULL lattice");
-    if (every < 0 || every > 1024 || slack < 0 || slack > 1024)
-        return fail(SG_EINVAL, "every and slack must be in [0, 1024]");
-    lat->pace_every = every;
-    lat->pace_slack = slack;
-    return SG_OK;
 }
 
 int sg_stream_state_bytes(const sg_lattice *lat, size_t *bytes)

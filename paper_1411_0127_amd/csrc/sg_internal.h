@@ -321,7 +321,6 @@ struct sg_lattice {
     int kernel = SG_KERNEL_AUTO;
     int tile_x = 0, tile_y = 0, z_chunk = 0, band = 0;
     int ring = 0;  // planes in flight of the two-sweep march (0 = default)
-    int pace_every = 0, pace_slack = 0;  // pacing of the two-sweep march (0: off)
 };
 
 namespace sg {
@@ -367,9 +366,6 @@ struct SweepArgs {
     uint64_t pkey[2];      // per replica: key of the per-sample numbers (SG_PHILOX)
     int64_t t;             // sweep index of the (first) sweep of this launch
     Thresholds T;
-    uint32_t *pace_ctr;    // two-sweep march: pacing counters (NULL: no pacing)
-    int64_t pace_ctr_words;
-    int pace_every, pace_slack;
 };
 hipError_t launch_sweep_twopass(const SweepArgs &a, hipStream_t s);
 // Colour-separated layout: conversion of nwords cube arrays (src_stride words

@@ -64,7 +64,6 @@ SIGNATURES = {
     "sg_set_stream_state": (_i, [_p, _p, _sz, _i64]),
     "sg_set_kernel": (_i, [_p, _i, _i, _i, _i, _i]),
     "sg_set_ring": (_i, [_p, _i]),
-    "sg_set_pacing": (_i, [_p, _i, _i]),
     "sg_get_kernel": (_i, [_p, _p]),
     "sg_autotune": (_i, [ctypes.POINTER(_p), _i, _i, _p, ctypes.POINTER(_d)]),
     "sg_batch_footprint": (_i, [_i, _i, ctypes.POINTER(_sz)]),
@@ -237,10 +236,6 @@ class Lattice:
     def set_ring(self, planes: int = 0):
         """Planes in flight of the two-sweep march: 5, 6 or 0 (default)."""
         _check(lib.sg_set_ring(self.handle, int(planes)))
-
-    def set_pacing(self, every: int = 0, slack: int = 0):
-        """Pacing of the two-sweep march (sg_set_pacing); every = 0 turns it off."""
-        _check(lib.sg_set_pacing(self.handle, int(every), int(slack)))
 
     def kernel(self):
         """(kind, tile_x, tile_y, z_chunk, band, planes in flight) the next sweeps use."""
