@@ -15,7 +15,8 @@ The same run adds, outside the timed region:
                  buffers (the paper's analog: a device copy's peak, Sec. 4.1);
   depth1         the one-sweep-per-launch kernel on the same lattice, whose
                  bandwidth is the fraction read at temporal depth 1;
-  c1             L=256, two replicas (MINSTD, MT19937, Parisi-Rapuano);
+  c1             L=256, two replicas (MINSTD, MT19937, Parisi-Rapuano, and one
+                 Philox number per sample);
   c3             the batched mix of 256 lattices, against plain launches;
   c4             the served Poisson job stream: p50/p99 latency, psFlip;
   cpu_baseline   the CPU oracle on bit-planes 0 and 63 of the same L=1024
@@ -170,10 +171,6 @@ def run_single(args, wl, prng=None, steps=None, warmup=None, marker=None, depth1
     elif args.kernel != "auto":
         for l in lats:
             l.set_kernel(args.kernel)
-    if args.pace:
-        every, slack = (int(v) for v in args.pace.split(","))
-        for l in lats:
-            l.set_pacing(every, slack)
     shape = lats[0].kernel()  # kind, tile_x, tile_y, z_chunk, band, planes in flight
     per_launch = 2 if shape[0] == "fused2" and nsw % 2 == 0 else 1
     every = wl.get("energy_every_sweep", False)
@@ -313,6 +310,11 @@ def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: b
     from paper_1411_0127_amd import sg
     from paper_1411_0127_amd.serve import GpuBackend, Server, trace_batch, trace_served
 
+    # memory cached by torch for earlier sections belongs to their streams, which this
+    # mix does not use: hand it back first, so that the mix's lattices are allocated
+    # without synchronising frees in the middle of serving
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     budget = _budget_bytes(torch)
     out = {"workload": MIX_DESC[kind], "sweep_scale": sweep_scale, "seed": seed}
     if kind == "c3":
@@ -341,6 +343,10 @@ def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: b
         rep2 = Server(be, budget, chunk_rounds=100).serve(jobs2)
         s2 = rep2.summary()
         out["ps_per_flip"] = s["ps_per_flip_busy"]
+        t_solo = {L: solo_sweep_ms(sg, torch, L) for L in sorted({j.L for j in jobs})}
+        plain_s = sum(j.nsweeps * t_solo[j.L] for j in jobs) / 1e3
+        out["plain_ps_per_flip"] = plain_s * 1e12 / s["flips"]
+        out["served_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
         out["p50_latency_s"] = s["p50_latency_s"]
         out["p99_latency_s"] = s["p99_latency_s"]
         out["sub_saturating"] = dict(rate_jobs_per_s=rate, **s2)
@@ -353,6 +359,7 @@ def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: b
     out["batch_kernel"] = ("sg::k_batch_persistent (one launch per run, rounds ordered by per-lattice counters)"
                            if persistent else "sg::k_fused_batch (one launch per round)")
     be.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -413,7 +420,6 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
     ap.add_argument("--tile", default="",
                     help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band[,planes] (skips the autotuner)")
-    ap.add_argument("--pace", default="", help="every,slack: pacing of the two-sweep march (default off)")
     ap.add_argument("--extras", default="peak,depth1,c1,c3,c4,cpu",
                     help="comma list of extra sections: peak, depth1, c1, c3, c4, cpu ('' for none)")
     ap.add_argument("--cpu-sweeps", type=int, default=1, help="sweeps of the oracle in cpu_baseline")
@@ -422,6 +428,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
     ap.add_argument("--persistent", type=int, default=1,
                     help="c3/c4: 1 = one persistent launch per run, 0 = one launch per round")
+    ap.add_argument("--scan", default="",
+                    help="also time one MINSTD lattice (64 samples, autotuned) at each of these comma-separated sides")
     ap.add_argument("--layout-ab", action="store_true",
                     help="also time the two-pass kernel on the cube, colour-separated and sliced layouts")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -506,9 +514,11 @@ def main():
         print(f"[bench] peaks: {pk}", file=sys.stderr, flush=True)
     if args.layout_ab:
         line["layout_ab"] = layout_ab(sg, torch, wl)
+    if args.scan:
+        line["scan"] = scan_sides(sg, torch, [int(v) for v in args.scan.split(",")])
     if "c1" in extras and args.workload != "c1":
         c1 = {}
-        for prng in ("minstd", "mt19937", "parisi_rapuano"):
+        for prng in ("minstd", "mt19937", "parisi_rapuano", "philox"):
             r = run_single(args, WORKLOADS["c1"], prng=prng, steps=3, warmup=1)
             c1[prng] = {"ps_per_flip": round(r["ps_per_flip"], 6), "launch_ms": round(r["launch_ms"], 5),
                         "sweeps_per_launch": r["sweeps_per_launch"], "tile": r["tile"]}
@@ -532,6 +542,32 @@ def main():
     if "cpu" in extras:
         line["cpu_baseline"] = cpu_baseline("c2" if args.workload == "c2" else args.workload, args.cpu_sweeps)
     print(json.dumps(line), flush=True)
+
+
+def scan_sides(sg, torch, sides, beta=1 / 0.9):
+    """ms per sweep and psFlip of one MINSTD lattice of 64 samples at each side,
+    autotuned, HIP events around one call (200 sweeps up to L=256, 20 above)."""
+    stream = torch.cuda.current_stream()
+    out = []
+    for L in sides:
+        lat = sg.Lattice(L, 64, "minstd", coupling_seed=1, spin_seed=2, stream=stream)
+        if L >= 32:
+            sg.autotune([lat], reps=3)
+        nsw = 200 if L <= 256 else 20
+        lat.sweep(4, beta)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.sweep(nsw, beta)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / nsw
+        out.append({"L": L, "kernel": list(lat.kernel()), "ms_per_sweep": round(ms, 5),
+                    "ps_per_flip": round(ms * 1e9 / (64 * L**3), 5)})
+        lat.close()
+        torch.cuda.empty_cache()
+        print(f"[bench] scan L={L}: {ms:.4f} ms per sweep", file=sys.stderr, flush=True)
+    return out
 
 
 def layout_ab(sg, torch, wl, nsw=4):
