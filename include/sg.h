@@ -252,9 +252,10 @@ int sg_set_stream_state(sg_lattice *lat, const void *in, size_t bytes, int64_t t
  * is set against (the paper's analog: the peak bandwidth of a device copy, Sec.
  * 4.1).  kind 0: read `bytes` from src, writing blocks*16 bytes of folded words to
  * dst (dst must hold them); 1: copy `bytes` from src to dst; 2: fill `bytes` of
- * dst.  bytes a positive multiple of 16, buffers 16-byte aligned, blocks = 0 for
- * 4096 workgroups of 256 lanes (else 1..65536).  Asynchronous on `stream`; the
- * caller times it. */
+ * dst; 3, 4, 5: the same with non-temporal (streaming) loads and stores.  bytes a
+ * positive multiple of 16, buffers 16-byte aligned, blocks = 0 for 4096
+ * workgroups of 256 lanes (else 1..65536).  Asynchronous on `stream`; the caller
+ * times it. */
 int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int blocks, void *stream);
 
 /* Library runtime (kernel choice; no counterpart in the paper, whose launch

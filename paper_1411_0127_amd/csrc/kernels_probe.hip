@@ -7,7 +7,9 @@
 // 16-byte accesses, four independent ones per lane and iteration, a grid of
 // many workgroups per CU striding over the buffer.  The read probe folds what
 // it reads with XOR and writes one word per wave, so its loads cannot be
-// dropped; those writes are 1/1024 of the bytes read at most.
+// dropped; those writes are 1/1024 of the bytes read at most.  Each probe has a
+// streaming form (NT: non-temporal loads and stores, which do not keep the lines
+// in the caches); the caller takes the faster of the two.
 #include "sg_internal.h"
 
 namespace sg {
@@ -16,6 +18,34 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const uint4 *p)
+{
+    if (NT) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
+    return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(uint4 *p, const uint4 v)
+{
+    if (NT) {
+        u32x4 w;
+        w.x = v.x;
+        w.y = v.y;
+        w.z = v.z;
+        w.w = v.w;
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+    } else {
+        *p = v;
+    }
+}
+
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_probe_read(const uint4 *__restrict__ src, size_t n,
                                                        uint32_t *__restrict__ sink)
 {
@@ -26,13 +56,13 @@ __global__ __launch_bounds__(kBlock) void k_probe_read(const uint4 *__restrict__
         uint4 v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            v[u] = src[i + u * stride];
+            v[u] = ld16<NT>(src + i + u * stride);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
             acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
     for (; i < n; i += stride) {
-        const uint4 v = src[i];
+        const uint4 v = ld16<NT>(src + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     for (int off = 32; off > 0; off >>= 1)
@@ -41,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_read(const uint4 *__restrict__
         sink[((size_t)blockIdx.x * kBlock + threadIdx.x) >> 6] = acc;
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_probe_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                        size_t n)
 {
@@ -50,21 +81,22 @@ __global__ __launch_bounds__(kBlock) void k_probe_copy(const uint4 *__restrict__
         uint4 v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            v[u] = src[i + u * stride];
+            v[u] = ld16<NT>(src + i + u * stride);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            dst[i + u * stride] = v[u];
+            st16<NT>(dst + i + u * stride, v[u]);
     }
     for (; i < n; i += stride)
-        dst[i] = src[i];
+        st16<NT>(dst + i, ld16<NT>(src + i));
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_probe_fill(uint4 *__restrict__ dst, size_t n, uint32_t pattern)
 {
     const size_t stride = (size_t)gridDim.x * kBlock;
     const uint4 v = make_uint4(pattern, pattern ^ 1u, pattern ^ 2u, pattern ^ 3u);
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        dst[i] = v;
+        st16<NT>(dst + i, v);
 }
 
 }  // namespace
@@ -72,14 +104,28 @@ __global__ __launch_bounds__(kBlock) void k_probe_fill(uint4 *__restrict__ dst, 
 hipError_t launch_probe(int kind, void *dst, const void *src, size_t bytes, int blocks, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    if (kind == 0)
-        hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(kBlock), 0, s, static_cast<const uint4 *>(src), n,
-                           static_cast<uint32_t *>(dst));
-    else if (kind == 1)
-        hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(kBlock), 0, s, static_cast<const uint4 *>(src),
-                           static_cast<uint4 *>(dst), n);
-    else
-        hipLaunchKernelGGL(k_probe_fill, dim3(blocks), dim3(kBlock), 0, s, static_cast<uint4 *>(dst), n, 0x5A5A5A5Au);
+    const uint4 *in = static_cast<const uint4 *>(src);
+    uint4 *out = static_cast<uint4 *>(dst);
+    switch (kind) {
+    case 0:
+        hipLaunchKernelGGL(k_probe_read<false>, dim3(blocks), dim3(kBlock), 0, s, in, n, static_cast<uint32_t *>(dst));
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_probe_copy<false>, dim3(blocks), dim3(kBlock), 0, s, in, out, n);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_probe_fill<false>, dim3(blocks), dim3(kBlock), 0, s, out, n, 0x5A5A5A5Au);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_probe_read<true>, dim3(blocks), dim3(kBlock), 0, s, in, n, static_cast<uint32_t *>(dst));
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_probe_copy<true>, dim3(blocks), dim3(kBlock), 0, s, in, out, n);
+        break;
+    default:
+        hipLaunchKernelGGL(k_probe_fill<true>, dim3(blocks), dim3(kBlock), 0, s, out, n, 0x5A5A5A5Au);
+        break;
+    }
     return hipGetLastError();
 }
 

@@ -842,15 +842,15 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
 
 int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int blocks, void *stream)
 {
-    if (kind < 0 || kind > 2)
-        return fail(SG_EINVAL, "kind must be 0 (read), 1 (copy) or 2 (fill)");
+    if (kind < 0 || kind > 5)
+        return fail(SG_EINVAL, "kind must be 0 (read), 1 (copy), 2 (fill), or 3..5 for their streaming forms");
     if (blocks == 0)
         blocks = 4096;
     if (blocks < 1 || blocks > 65536)
         return fail(SG_EINVAL, "blocks must be in [1, 65536]");
     if (bytes < 16 || (bytes & 15) != 0)
         return fail(SG_EINVAL, "bytes must be a positive multiple of 16");
-    if (!dst || (kind != 2 && !src))
+    if (!dst || (kind != 2 && kind != 5 && !src))
         return fail(SG_EINVAL, "NULL buffer");
     if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) != 0)
         return fail(SG_EINVAL, "buffers must be 16-byte aligned");

@@ -430,7 +430,8 @@ hipError_t launch_batch_reset(unsigned long long *queues, uint32_t *error, uint3
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
 hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
 
-// Bandwidth probes (kind 0 read-only into dst[blocks*4] words, 1 copy, 2 fill).
+// Bandwidth probes (kind 0 read-only into dst[blocks*4] words, 1 copy, 2 fill;
+// 3..5 the same with non-temporal loads and stores).
 hipError_t launch_probe(int kind, void *dst, const void *src, size_t bytes, int blocks, hipStream_t s);
 
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,

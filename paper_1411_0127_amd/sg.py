@@ -132,9 +132,10 @@ def sliced_footprint(L: int) -> int:
 
 
 def probe_bandwidth(kind: str, dst, src, nbytes: int, stream, blocks: int = 0):
-    """Queue a bandwidth probe (sg_probe_bandwidth): kind "read", "copy" or "fill";
-    dst / src are device tensors (src unused for "fill")."""
-    k = {"read": 0, "copy": 1, "fill": 2}[kind]
+    """Queue a bandwidth probe (sg_probe_bandwidth): kind "read", "copy" or "fill",
+    or "read_nt", "copy_nt", "fill_nt" for the streaming forms; dst / src are
+    device tensors (src unused for the fills)."""
+    k = {"read": 0, "copy": 1, "fill": 2, "read_nt": 3, "copy_nt": 4, "fill_nt": 5}[kind]
     _check(lib.sg_probe_bandwidth(k, _p(dst.data_ptr()), _p(src.data_ptr()) if src is not None else None,
                                   int(nbytes), int(blocks), _p(stream.cuda_stream)))
 
