@@ -179,13 +179,11 @@ def run_single(args, wl, prng=None, steps=None, warmup=None, marker=None, depth1
         if ev is not None:
             ev[0].record(stream)
         if every:
-            out = []
-            for _ in range(nsw):
-                lats[0].sweep(1, beta)
-                out.append(lats[0].energy())
+            # the energy after every sweep, kept on the device and read back at the end
+            U = lats[0].sweep_energies(nsw, beta)
             if ev is not None:
                 ev[1].record(stream)
-            return [out[-1]]
+            return [(U[-1], (2.0 * U[-1] - 3.0 * V) / V)]
         if R == 1:
             lats[0].sweep(nsw, beta)
         else:

@@ -195,6 +195,14 @@ int sg_sweep_sliced_static(sg_lattice *lat, int64_t nsweeps, double beta);
  * lattice's stream. */
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin);
 
+/* nsweeps sweeps at beta with the energy of Sec. 1, Eq. (1) after every one:
+ * unsat[k * nsamples + j] = unsatisfied bonds of sample j after sweep k+1 of this
+ * call (host array of nsweeps * nsamples).  Same spins as sg_sweep; one sweep per
+ * launch.  The counts stay on the device and are copied back in chunks (of up to
+ * ~2000 sweeps at small L, one at L >= 1024), so the stream is not synchronised
+ * after every sweep.  Synchronises the lattice's stream before returning. */
+int sg_sweep_energies(sg_lattice *lat, int64_t nsweeps, double beta, int64_t *unsat);
+
 /* Two-replica overlap per sample.  The paper simulates replicas (Sec. 2) but
  * does not define the overlap; this is the textbook q_j = (1/V) sum_i
  * s^a_i s^b_i, returned as ndiff[j] = number of sites where the replicas differ

@@ -675,6 +675,59 @@ int sg_sweep_sliced_static(sg_lattice *lat, int64_t nsweeps, double beta)
     return layout_sweep(lat, nsweeps, beta, area, kSliced);
 }
 
+int sg_sweep_energies(sg_lattice *lat, int64_t nsweeps, double beta, int64_t *unsat)
+{
+    if (!lat)
+        return fail(SG_EINVAL, "NULL lattice");
+    if (nsweeps < 0)
+        return fail(SG_EINVAL, "nsweeps < 0");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    if (!unsat && nsweeps > 0)
+        return fail(SG_EINVAL, "unsat is NULL");
+    uint64_t T[3];
+    sg_thresholds(beta, lat->prng, T);
+    const Thresholds th{T[0], T[1], T[2]};
+    // The reduction area holds the per-block rows of one count and, after them, one
+    // row of 64 totals per sweep of a chunk; a chunk is read back with one copy.
+    int nblocks = 0;
+    const size_t words = (size_t)kMaxReduceBlocks * 64 + 64;
+    std::vector<uint64_t> host;
+    for (int64_t done = 0; done < nsweeps;) {
+        int64_t chunk = 0;
+        uint64_t *rows = nullptr;
+        hipError_t e = hipSuccess;
+        for (; done + chunk < nsweeps; ++chunk) {
+            int rc = sweep_n(&lat, 1, 1, th);
+            if (rc != SG_OK)
+                return rc;
+            e = launch_count_unsat(lat->spins[lat->cur], lat->J, lat->L, lat->scratch, nblocks, lat->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "energy launch");
+            rows = lat->scratch + (size_t)nblocks * 64;
+            const int64_t cap = (int64_t)((words - (size_t)nblocks * 64) / 64);  // >= 1
+            e = launch_reduce_partials(lat->scratch, nblocks, rows + (size_t)chunk * 64, lat->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "reduce launch");
+            if (chunk + 1 == cap) {
+                ++chunk;
+                break;
+            }
+        }
+        host.resize((size_t)chunk * 64);
+        e = hipMemcpyAsync(host.data(), rows, 8 * host.size(), hipMemcpyDeviceToHost, lat->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "energy readback");
+        for (int64_t k = 0; k < chunk; ++k)
+            for (int j = 0; j < lat->nsamples; ++j)
+                unsat[(done + k) * lat->nsamples + j] = (int64_t)host[(size_t)k * 64 + j];
+        done += chunk;
+    }
+    return SG_OK;
+}
+
 int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin)
 {
     if (!lat)

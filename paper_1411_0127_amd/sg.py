@@ -74,6 +74,7 @@ SIGNATURES = {
     "sg_sliced_footprint": (_i, [_i, ctypes.POINTER(_sz)]),
     "sg_sweep_sliced": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_sweep_sliced_static": (_i, [_p, _i64, _d]),
+    "sg_sweep_energies": (_i, [_p, _i64, _d, _p]),
     "sg_sweep_separated": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -258,6 +259,13 @@ class Lattice:
         e = np.zeros(self.nsamples, dtype=np.float64)
         _check(lib.sg_energy(self.handle, _ptr(U), _ptr(e)))
         return U, e
+
+    def sweep_energies(self, n: int, beta: float) -> np.ndarray:
+        """n sweeps with the unsatisfied-bond counts after every one
+        (sg_sweep_energies): int64[n][nsamples]."""
+        U = np.zeros((int(n), self.nsamples), dtype=np.int64)
+        _check(lib.sg_sweep_energies(self.handle, int(n), float(beta), _ptr(U) if U.size else None))
+        return U
 
     def spins(self) -> np.ndarray:
         out = np.empty((self.nsamples, self.V), dtype=np.int8)

@@ -713,3 +713,37 @@ def test_autotune_leaves_state_and_parity(sg, prng):
         rb.sweep(n, beta)
     assert_same(a.words(), ra, 64, "after autotune, replica 0")
     assert_same(b.words(), rb, 64, "after autotune, replica 1")
+
+
+# ---------------------------------------------------------------------------
+# energies after every sweep in one call (sg_sweep_energies)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,S,prng,n", [(8, 64, "minstd", 30), (16, 1, "minstd", 200), (16, 64, "mt19937", 25),
+                                        (18, 64, "parisi_rapuano", 21), (12, 64, "philox", 9)])
+def test_energy_after_every_sweep_in_one_call(sg, L, S, prng, n):
+    say("sweep energies", L, S, prng, n)
+    lat = sg.Lattice(L, S, prng, coupling_seed=31, spin_seed=32)
+    ref = oracle_for(L, S, prng, 31, 32)
+    U = lat.sweep_energies(n, 0.8)
+    assert U.shape == (n, S) and lat.t == n
+    for k in range(n):
+        ref.sweep(1, 0.8)
+        assert np.array_equal(U[k], ref.unsatisfied()), f"energies after sweep {k + 1}"
+    assert_same(lat.words(), ref, S, f"L={L} {prng} after {n} sweeps")
+    assert lat.sweep_energies(0, 0.8).shape == (0, S)
+    lat.close()
+
+
+def test_energy_records_across_read_back_chunks(sg):
+    # at L=320 the reduction area holds 49 sweeps' totals: 100 sweeps take three chunks
+    say("sweep energies in chunks")
+    L, n, beta = 320, 100, 0.9
+    a = sg.Lattice(L, 64, "minstd", coupling_seed=33, spin_seed=34)
+    b = sg.Lattice(L, 64, "minstd", coupling_seed=33, spin_seed=34)
+    U = a.sweep_energies(n, beta)
+    for k in range(n):
+        b.sweep(1, beta)
+        assert np.array_equal(U[k], b.energy()[0]), f"energies after sweep {k + 1}"
+    assert np.array_equal(a.words(), b.words())
+    a.close()
+    b.close()
