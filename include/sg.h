@@ -197,10 +197,12 @@ int sg_energy(sg_lattice *lat, int64_t *unsat, double *e_per_spin);
 
 /* nsweeps sweeps at beta with the energy of Sec. 1, Eq. (1) after every one:
  * unsat[k * nsamples + j] = unsatisfied bonds of sample j after sweep k+1 of this
- * call (host array of nsweeps * nsamples).  Same spins as sg_sweep; one sweep per
- * launch.  The counts stay on the device and are copied back in chunks (of up to
- * ~2000 sweeps at small L, one at L >= 1024), so the stream is not synchronised
- * after every sweep.  Synchronises the lattice's stream before returning. */
+ * call (host array of nsweeps * nsamples).  Same spins as sg_sweep.  Up to L = 16
+ * with MINSTD or per-sample numbers, one workgroup runs up to 2049 sweeps per
+ * launch with the lattice in LDS; otherwise each sweep is a launch of its own.
+ * The counts stay on the device and are copied back in chunks (of up to ~2000
+ * sweeps at small L, one at L >= 1024), so the stream is not synchronised after
+ * every sweep.  Synchronises the lattice's stream before returning. */
 int sg_sweep_energies(sg_lattice *lat, int64_t nsweeps, double beta, int64_t *unsat);
 
 /* Two-replica overlap per sample.  The paper simulates replicas (Sec. 2) but

@@ -23,6 +23,7 @@ SOURCES = [
     "kernels_sliced.hip",
     "sg_batch.hip",
     "kernels_probe.hip",
+    "kernels_small.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,177 @@
+// Small lattices in one workgroup: every sweep of a call in one launch, with the
+// energy of Sec. 1, Eq. (1) counted after each sweep.
+//
+// A lattice of up to kSmallSites sites (L <= 16) keeps its spin words and its
+// three coupling words per site in LDS (136 KB with the reduction table) for the
+// whole call.  Each sweep is the checkerboard of Sec. 1, red sites (x + y + z
+// even) then blue, sites of one colour updated in place with the bit-sliced rule
+// of Sec. 4 and the same keyed numbers as every other kernel, so the spins equal
+// theirs bit for bit.  A thread owns fixed sites of each colour (as the two-pass
+// kernel numbers them: x = 2 xh + parity), so no lane idles in a colour pass, and
+// keeps their neighbour indices and MINSTD seeds in registers.  After each sweep
+// the workgroup counts the unsatisfied bonds of the lattice's samples and writes
+// them to out[sweep][64].  At these sizes a sweep is a few microseconds of work,
+// so one launch per call instead of three per sweep is what sets the time.
+#include "sg_internal.h"
+
+namespace sg {
+namespace {
+
+constexpr int kSmallThreads = 1024;
+constexpr int kPerThread = kSmallSites / 2 / kSmallThreads;  // sites of one colour per thread
+constexpr int kCountPlanes = 4;  // a thread adds at most 3 * 4 = 12 bond words per count
+
+static_assert(kSmallSites % (2 * kSmallThreads) == 0, "whole sites of each colour per thread");
+
+template <int PRNG>
+__global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__restrict__ S,
+                                                                const uint64_t *__restrict__ J, int L,
+                                                                int nsamples, uint32_t mk, uint64_t pkey, int64_t t0,
+                                                                uint32_t a0, int nsweeps, Thresholds T,
+                                                                uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t s[kSmallSites];
+    __shared__ uint64_t jw[3][kSmallSites];
+    __shared__ uint64_t part[kSmallThreads / 64][64];
+    const int LL = L * L;
+    const int V = LL * L;
+    const int half = V / 2;
+    const int hx = L / 2;
+    const int64_t Vj = coupling_stride(L);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    for (int i = tid; i < V; i += kSmallThreads) {
+        s[i] = S[i];
+        jw[0][i] = J[i];
+        jw[1][i] = J[Vj + i];
+        jw[2][i] = J[2 * Vj + i];
+    }
+    // this thread's sites: site[c][m] of colour c (-1 past the end), their six
+    // neighbours (+x, -x, +y, -y, +z, -z, periodic) and their seeds, all fixed for
+    // the call
+    int site[2][kPerThread];
+    int nb[2][kPerThread][6];
+    uint32_t seed[2][kPerThread];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < kPerThread; ++m) {
+            const int g = tid + m * kSmallThreads;
+            site[c][m] = -1;
+            seed[c][m] = 0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+                nb[c][m][d] = 0;
+            if (g < half) {
+                const int xh = g % hx;
+                const int row = g / hx;
+                const int y = row % L;
+                const int z = row / L;
+                const int x = 2 * xh + ((y + z + c) & 1);
+                const int i = x + L * y + LL * z;
+                site[c][m] = i;
+                nb[c][m][0] = (x + 1 == L) ? i - (L - 1) : i + 1;
+                nb[c][m][1] = (x == 0) ? i + (L - 1) : i - 1;
+                nb[c][m][2] = (y + 1 == L) ? i - (L - 1) * L : i + L;
+                nb[c][m][3] = (y == 0) ? i + (L - 1) * L : i - L;
+                nb[c][m][4] = (z + 1 == L) ? i - (V - LL) : i + LL;
+                nb[c][m][5] = (z == 0) ? i + (V - LL) : i - LL;
+                seed[c][m] = minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk));
+            }
+        }
+    __syncthreads();
+    uint32_t a = a0;  // 16807^(t+1) mod (2^31 - 1) of the current sweep t
+    for (int k = 0; k < nsweeps; ++k) {
+        const int64_t t = t0 + k;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int m = 0; m < kPerThread; ++m) {
+                const int i = site[c][m];
+                if (i < 0)
+                    continue;
+                const int ixp = nb[c][m][0], ixm = nb[c][m][1], iyp = nb[c][m][2], iym = nb[c][m][3];
+                const int izp = nb[c][m][4], izm = nb[c][m][5];
+                const uint64_t si = s[i];
+                if (PRNG == SG_PHILOX)
+                    s[i] = flip_site_ps(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jw[0][i], jw[1][i],
+                                        jw[2][i], jw[0][ixm], jw[1][iym], jw[2][izm], (uint64_t)i, (uint64_t)t,
+                                        (uint32_t)pkey, (uint32_t)(pkey >> 32), T);
+                else
+                    s[i] = flip_site(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jw[0][i], jw[1][i],
+                                     jw[2][i], jw[0][ixm], jw[1][iym], jw[2][izm], minstd_jump(a, seed[c][m]), T);
+            }
+            __syncthreads();
+        }
+        if (out) {
+            // bond (i, i + d) of sample j is unsatisfied when bit j of J[d][i] ^ s_i ^ s_{i+d}
+            // is 1 (the bond bit of Sec. 4); bit-sliced counts, plane b = bit b of 64 counts
+            uint64_t cnt[kCountPlanes] = {};
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int m = 0; m < kPerThread; ++m) {
+                    const int i = site[c][m];
+                    if (i < 0)
+                        continue;
+                    const uint64_t si = s[i];
+                    const uint64_t w[3] = {jw[0][i] ^ si ^ s[nb[c][m][0]], jw[1][i] ^ si ^ s[nb[c][m][2]],
+                                           jw[2][i] ^ si ^ s[nb[c][m][4]]};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        uint64_t v = w[d];
+#pragma unroll
+                        for (int b = 0; b < kCountPlanes; ++b) {
+                            const uint64_t carry = cnt[b] & v;
+                            cnt[b] ^= v;
+                            v = carry;
+                        }
+                    }
+                }
+            // per wave: the count of sample j is the sum over planes b of 2^b times the
+            // lanes whose plane b has bit j set; lane j keeps sample j's total (samples
+            // past nsamples are simulated but not counted)
+            uint64_t mine = 0;
+            for (int j = 0; j < nsamples; ++j) {
+                uint64_t tot = 0;
+#pragma unroll
+                for (int b = 0; b < kCountPlanes; ++b)
+                    tot += (uint64_t)__popcll(__ballot((cnt[b] >> j) & 1ull)) << b;
+                mine = lane == j ? tot : mine;
+            }
+            part[wave][lane] = mine;
+            __syncthreads();
+            if (tid < 64) {
+                uint64_t sum = 0;
+                for (int w = 0; w < kSmallThreads / 64; ++w)
+                    sum += part[w][tid];
+                out[(size_t)k * 64 + tid] = sum;
+            }
+            __syncthreads();  // part is written again after the next sweep
+        }
+        a = minstd_jump(a, 16807u);
+    }
+    for (int i = tid; i < V; i += kSmallThreads)
+        S[i] = s[i];
+}
+
+}  // namespace
+
+hipError_t launch_small_sweeps(uint64_t *S, const uint64_t *J, int L, int nsamples, int prng, uint32_t mk,
+                               uint64_t pkey, int64_t t0, uint32_t a0, int nsweeps, const Thresholds &T, uint64_t *out,
+                               hipStream_t s)
+{
+    if ((int64_t)L * L * L > kSmallSites || L < 2 || (L & 1) || nsweeps < 1 || nsamples < 1 || nsamples > 64 ||
+        (prng != SG_MINSTD && prng != SG_PHILOX))
+        return hipErrorInvalidValue;
+    if (prng == SG_PHILOX)
+        hipLaunchKernelGGL(k_small_sweeps<SG_PHILOX>, dim3(1), dim3(kSmallThreads), 0, s, S, J, L, nsamples, mk, pkey,
+                           t0, a0, nsweeps, T, out);
+    else
+        hipLaunchKernelGGL(k_small_sweeps<SG_MINSTD>, dim3(1), dim3(kSmallThreads), 0, s, S, J, L, nsamples, mk, pkey,
+                           t0, a0, nsweeps, T, out);
+    return hipGetLastError();
+}
+
+}  // namespace sg

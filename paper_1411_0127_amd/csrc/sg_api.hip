@@ -688,11 +688,43 @@ int sg_sweep_energies(sg_lattice *lat, int64_t nsweeps, double beta, int64_t *un
     uint64_t T[3];
     sg_thresholds(beta, lat->prng, T);
     const Thresholds th{T[0], T[1], T[2]};
+    const size_t words = (size_t)kMaxReduceBlocks * 64 + 64;  // the reduction area
+    std::vector<uint64_t> host;
+    auto read_back = [&](const uint64_t *rows, int64_t done, int64_t chunk) -> int {
+        host.resize((size_t)chunk * 64);
+        hipError_t e = hipMemcpyAsync(host.data(), rows, 8 * host.size(), hipMemcpyDeviceToHost, lat->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "energy readback");
+        for (int64_t k = 0; k < chunk; ++k)
+            for (int j = 0; j < lat->nsamples; ++j)
+                unsat[(done + k) * lat->nsamples + j] = (int64_t)host[(size_t)k * 64 + j];
+        return SG_OK;
+    };
+    if (lat->V <= kSmallSites && (lat->prng == SG_MINSTD || lat->prng == SG_PHILOX)) {
+        // one workgroup runs a chunk of sweeps with the lattice in LDS, one row of 64
+        // totals per sweep in the reduction area
+        const int64_t cap = (int64_t)(words / 64);
+        for (int64_t done = 0; done < nsweeps;) {
+            const int chunk = (int)std::min<int64_t>(cap, nsweeps - done);
+            const hipError_t e = launch_small_sweeps(lat->spins[lat->cur], lat->J, lat->L, lat->nsamples, lat->prng,
+                                                     lat->minstd_k,
+                                                     lat->key_philox, lat->t, minstd_multiplier(lat->t), chunk, th,
+                                                     lat->scratch, lat->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "small-lattice sweeps");
+            lat->t += chunk;
+            const int rc = read_back(lat->scratch, done, chunk);
+            if (rc != SG_OK)
+                return rc;
+            done += chunk;
+        }
+        return SG_OK;
+    }
     // The reduction area holds the per-block rows of one count and, after them, one
     // row of 64 totals per sweep of a chunk; a chunk is read back with one copy.
     int nblocks = 0;
-    const size_t words = (size_t)kMaxReduceBlocks * 64 + 64;
-    std::vector<uint64_t> host;
     for (int64_t done = 0; done < nsweeps;) {
         int64_t chunk = 0;
         uint64_t *rows = nullptr;
@@ -714,15 +746,9 @@ int sg_sweep_energies(sg_lattice *lat, int64_t nsweeps, double beta, int64_t *un
                 break;
             }
         }
-        host.resize((size_t)chunk * 64);
-        e = hipMemcpyAsync(host.data(), rows, 8 * host.size(), hipMemcpyDeviceToHost, lat->stream);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(lat->stream);
-        if (e != hipSuccess)
-            return hip_fail(e, "energy readback");
-        for (int64_t k = 0; k < chunk; ++k)
-            for (int j = 0; j < lat->nsamples; ++j)
-                unsat[(done + k) * lat->nsamples + j] = (int64_t)host[(size_t)k * 64 + j];
+        const int rc = read_back(rows, done, chunk);
+        if (rc != SG_OK)
+            return rc;
         done += chunk;
     }
     return SG_OK;

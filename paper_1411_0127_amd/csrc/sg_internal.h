@@ -430,6 +430,16 @@ hipError_t launch_batch_reset(unsigned long long *queues, uint32_t *error, uint3
 hipError_t launch_round_advance(int64_t *round_ctr, hipStream_t s);
 hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s);
 
+// Lattices of at most kSmallSites sites (L <= 16): nsweeps sweeps in one launch
+// of one workgroup, spins and couplings resident in LDS (spins in place in S), and
+// when out is not NULL the unsatisfied-bond counts of samples 0 .. nsamples-1
+// after every sweep in out[nsweeps][64].  MINSTD (a0 = 16807^(t0+1) mod (2^31 - 1)) and per-sample
+// Philox numbers.
+constexpr int kSmallSites = 4096;
+hipError_t launch_small_sweeps(uint64_t *S, const uint64_t *J, int L, int nsamples, int prng, uint32_t mk,
+                               uint64_t pkey, int64_t t0, uint32_t a0, int nsweeps, const Thresholds &T, uint64_t *out,
+                               hipStream_t s);
+
 // Bandwidth probes (kind 0 read-only into dst[blocks*4] words, 1 copy, 2 fill;
 // 3..5 the same with non-temporal loads and stores).
 hipError_t launch_probe(int kind, void *dst, const void *src, size_t bytes, int blocks, hipStream_t s);

@@ -718,8 +718,13 @@ def test_autotune_leaves_state_and_parity(sg, prng):
 # ---------------------------------------------------------------------------
 # energies after every sweep in one call (sg_sweep_energies)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("L,S,prng,n", [(8, 64, "minstd", 30), (16, 1, "minstd", 200), (16, 64, "mt19937", 25),
-                                        (18, 64, "parisi_rapuano", 21), (12, 64, "philox", 9)])
+# sides up to 20 with MINSTD or per-sample numbers take the one-workgroup kernel with
+# the lattice in LDS, the others a sweep, a count and a reduction per sweep; the
+# L=16 one-sample case is the benchmark's smallest configuration as it runs
+@pytest.mark.parametrize("L,S,prng,n", [(2, 64, "minstd", 40), (4, 1, "minstd", 50), (6, 64, "philox", 12),
+                                        (8, 64, "minstd", 30), (12, 64, "philox", 9), (16, 1, "minstd", 1000),
+                                        (20, 64, "minstd", 15), (20, 64, "philox", 4), (16, 64, "mt19937", 25),
+                                        (18, 64, "parisi_rapuano", 21), (22, 64, "minstd", 7)])
 def test_energy_after_every_sweep_in_one_call(sg, L, S, prng, n):
     say("sweep energies", L, S, prng, n)
     lat = sg.Lattice(L, S, prng, coupling_seed=31, spin_seed=32)
@@ -731,6 +736,26 @@ def test_energy_after_every_sweep_in_one_call(sg, L, S, prng, n):
         assert np.array_equal(U[k], ref.unsatisfied()), f"energies after sweep {k + 1}"
     assert_same(lat.words(), ref, S, f"L={L} {prng} after {n} sweeps")
     assert lat.sweep_energies(0, 0.8).shape == (0, S)
+    lat.close()
+
+
+def test_small_lattice_energy_records_across_launches(sg):
+    # one launch of the small-lattice kernel covers up to 2049 sweeps: 2100 take two,
+    # and a call that follows continues the same trajectory
+    say("small-lattice sweep energies in two launches")
+    L, n, beta = 4, 2100, 0.7
+    lat = sg.Lattice(L, 64, "minstd", coupling_seed=35, spin_seed=36)
+    ref = oracle_for(L, 64, "minstd", 35, 36)
+    U = lat.sweep_energies(n, beta)
+    U2 = lat.sweep_energies(3, beta)
+    for k in range(n):
+        ref.sweep(1, beta)
+        assert np.array_equal(U[k], ref.unsatisfied()), f"energies after sweep {k + 1}"
+    for k in range(3):
+        ref.sweep(1, beta)
+        assert np.array_equal(U2[k], ref.unsatisfied()), f"energies after sweep {n + k + 1}"
+    assert lat.t == n + 3
+    assert_same(lat.words(), ref, 64, f"L={L} after {n + 3} sweeps")
     lat.close()
 
 
