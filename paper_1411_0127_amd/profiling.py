@@ -139,7 +139,7 @@ def _per_dispatch(path: str, counter: str, part: str = "all"):
     return vals
 
 
-def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str) -> str:
+def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str, out_dir: str = "") -> str:
     # the sweep launches of the timed region only (no autotuner candidate), and the
     # calibration copies made after it (not the autotuner's copies of the spins)
     ft = _per_dispatch(fetch_csv, "FETCH_SIZE", "timed")
@@ -181,7 +181,7 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
         "command_fetch": command.replace("<COUNTER>", "FETCH_SIZE"),
         "command_write": command.replace("<COUNTER>", "WRITE_SIZE"),
     }
-    out = os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{workload}.json")
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_sweep_fused_{workload}.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     return out
