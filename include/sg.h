@@ -258,6 +258,19 @@ int sg_stream_state_bytes(const sg_lattice *lat, size_t *bytes);
 int sg_get_stream_state(const sg_lattice *lat, void *out, size_t bytes);
 int sg_set_stream_state(sg_lattice *lat, const void *in, size_t bytes, int64_t t);
 
+/* Library runtime (verification of Sec. 4): the bit-sliced flip rule applied to
+ * n given local configurations, so that a test can drive every pattern of a
+ * site's spin, six neighbours and six couplings (64 samples per word) through
+ * each acceptance region of R.  in: n * 13 device words per configuration (s,
+ * n0..n5, j0..j5; bond k joins n_k with coupling j_k, bit 1 <=> J = -1 and
+ * sigma = +1); R: n device numbers; out: n device words, the new spin words.
+ * Thresholds from sg_thresholds(beta, prng).  form: bit 0 the count of the
+ * six-plane march (else the five-plane one), bit 1 the 64-bit comparisons of the
+ * buffered and per-sample generators (else MINSTD's 32-bit ones, which only
+ * MINSTD's thresholds allow: SG_EINVAL otherwise).  Asynchronous on `stream`. */
+int sg_flip_words(int form, const uint64_t *in, const uint32_t *R, uint64_t n, double beta, int prng, uint64_t *out,
+                  void *stream);
+
 /* Library runtime (measurement): bandwidth probes, the measured peaks the sweep
  * is set against (the paper's analog: the peak bandwidth of a device copy, Sec.
  * 4.1).  kind 0: read `bytes` from src, writing blocks*16 bytes of folded words to

@@ -24,6 +24,7 @@ SOURCES = [
     "sg_batch.hip",
     "kernels_probe.hip",
     "kernels_small.hip",
+    "kernels_check.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -919,6 +919,26 @@ int sg_set_sweep_count(sg_lattice *lat, int64_t t)
     return check_hip(hipStreamSynchronize(lat->stream), "synchronize");
 }
 
+int sg_flip_words(int form, const uint64_t *in, const uint32_t *R, uint64_t n, double beta, int prng, uint64_t *out,
+                  void *stream)
+{
+    if (form < 0 || form > 3)
+        return fail(SG_EINVAL, "form must be 0..3");
+    if (check_beta(beta) != SG_OK)
+        return SG_EINVAL;
+    if (!valid_prng(prng))
+        return fail(SG_EINVAL, "unknown prng");
+    if ((form & 2) == 0 && prng != SG_MINSTD)
+        return fail(SG_EINVAL, "the 32-bit comparisons (forms 0, 1) hold only for MINSTD's thresholds");
+    if (n > 0 && (!in || !R || !out))
+        return fail(SG_EINVAL, "NULL buffer");
+    uint64_t T[3];
+    sg_thresholds(beta, prng, T);
+    return check_hip(launch_flip_words(form, in, R, n, Thresholds{T[0], T[1], T[2]}, out,
+                                       static_cast<hipStream_t>(stream)),
+                     "flip rule launch");
+}
+
 int sg_probe_bandwidth(int kind, void *dst, const void *src, size_t bytes, int blocks, void *stream)
 {
     if (kind < 0 || kind > 5)

@@ -440,6 +440,11 @@ hipError_t launch_small_sweeps(uint64_t *S, const uint64_t *J, int L, int nsampl
                                uint64_t pkey, int64_t t0, uint32_t a0, int nsweeps, const Thresholds &T, uint64_t *out,
                                hipStream_t s);
 
+// The flip rule applied to n sets of 13 words (s, n0..n5, j0..j5) with one R each:
+// out[q] = flip_site<Narrow = !(form & 2), Fold = form & 1>.  Verification only.
+hipError_t launch_flip_words(int form, const uint64_t *in, const uint32_t *R, uint64_t n, const Thresholds &T,
+                             uint64_t *out, hipStream_t s);
+
 // Bandwidth probes (kind 0 read-only into dst[blocks*4] words, 1 copy, 2 fill;
 // 3..5 the same with non-temporal loads and stores).
 hipError_t launch_probe(int kind, void *dst, const void *src, size_t bytes, int blocks, hipStream_t s);

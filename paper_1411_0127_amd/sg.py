@@ -75,6 +75,7 @@ SIGNATURES = {
     "sg_sweep_sliced": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_sweep_sliced_static": (_i, [_p, _i64, _d]),
     "sg_sweep_energies": (_i, [_p, _i64, _d, _p]),
+    "sg_flip_words": (_i, [_i, _p, _p, _u64, _d, _i, _p, _p]),
     "sg_sweep_separated": (_i, [_p, _i64, _d, _p, _sz]),
     "sg_batch_rounds_left": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -139,6 +140,24 @@ def probe_bandwidth(kind: str, dst, src, nbytes: int, stream, blocks: int = 0):
     k = {"read": 0, "copy": 1, "fill": 2, "read_nt": 3, "copy_nt": 4, "fill_nt": 5}[kind]
     _check(lib.sg_probe_bandwidth(k, _p(dst.data_ptr()), _p(src.data_ptr()) if src is not None else None,
                                   int(nbytes), int(blocks), _p(stream.cuda_stream)))
+
+
+def flip_words(form: int, words: np.ndarray, R: np.ndarray, beta: float, prng="minstd", stream=None) -> np.ndarray:
+    """The flip rule on given configurations (sg_flip_words): words uint64[n][13]
+    (s, n0..n5, j0..j5), R uint32[n]; returns the new spin words uint64[n]."""
+    torch = _torch()
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    r = np.ascontiguousarray(R, dtype=np.uint32)
+    n = r.size
+    assert w.shape == (n, 13)
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    dw = torch.from_numpy(w.view(np.int64)).to("cuda")
+    dr = torch.from_numpy(r.view(np.int32)).to("cuda")
+    out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+    _check(lib.sg_flip_words(int(form), _p(dw.data_ptr()), _p(dr.data_ptr()), n, float(beta), PRNGS[prng],
+                             _p(out.data_ptr()), _p(stream.cuda_stream)))
+    stream.synchronize()
+    return out[:n].cpu().numpy().view(np.uint64)
 
 
 def footprint(L: int, prng="minstd", own_couplings: bool = True, nsamples: int = 64) -> int:

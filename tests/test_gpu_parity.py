@@ -772,3 +772,70 @@ def test_energy_records_across_read_back_chunks(sg):
     assert np.array_equal(a.words(), b.words())
     a.close()
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# the flip rule on every local configuration (sg_flip_words)
+# ---------------------------------------------------------------------------
+def _oracle_decisions(beta, prng, rs):
+    """accept[v][k]: the oracle's Metropolis decision for a red site with v of its
+    six bonds satisfied (dE = 4v - 12) and R = rs[k], read off one oracle sweep of a
+    4x4x4 lattice whose other sites cannot flip."""
+    from test_oracle_pins import _site_bonds
+
+    ext, V = (4, 4, 4), 64
+    T = oracle.thresholds(beta, prng)
+    site = (1, 2, 1)
+    i0 = site[0] + 4 * (site[1] + 4 * site[2])
+    acc = np.zeros((7, len(rs)), dtype=bool)
+    top = 0x7FFFFFFE if prng == oracle.MINSTD else 0xFFFFFFFF
+    for v in range(7):
+        s = np.ones(V, dtype=np.int8)
+        J = np.ones((3, V), dtype=np.int8)
+        for k, (d, owner) in enumerate(_site_bonds(ext, *site)):
+            J[d, owner] = 1 if k < v else -1  # all spins +1: J = +1 is a satisfied bond
+        for k, r in enumerate(rs):
+            R = np.full(V, top, dtype=np.uint32)
+            R[i0] = r
+            acc[v, k] = oracle.sweep_once(ext, s, J, R, T)[i0] != s[i0]
+    return acc
+
+
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
+def test_flip_rule_on_every_local_configuration(sg, form):
+    """All 2^13 patterns of (s, n0..n5, j0..j5), 64 per word, at R on both sides of
+    every threshold, through each compiled form of the bit-sliced rule; each bit
+    must follow the oracle's Metropolis decision for its number of satisfied
+    bonds (a bond is satisfied when J s_i s_k = +1, i.e. when its three bits XOR to
+    0 under the bit mapping of Sec. 4)."""
+    say("flip rule", form)
+    prng_name = "minstd" if form < 2 else "mt19937"
+    prng = oracle.MINSTD if form < 2 else oracle.MT19937
+    beta = 0.37
+    T = [int(v) for v in oracle.thresholds(beta, prng)]
+    top = 0x7FFFFFFE if form < 2 else 0xFFFFFFFF
+    rs = sorted({0, T[2] - 1, T[2], T[1] - 1, T[1], T[0] - 1, T[0], top} - {-1})
+    acc = _oracle_decisions(beta, prng, rs)
+    c = np.arange(1 << 13, dtype=np.uint64).reshape(128, 64)  # config 64w + j in bit j of word w
+    bit = lambda b: (((c >> np.uint64(b)) & np.uint64(1)) << np.arange(64, dtype=np.uint64)).sum(
+        axis=1, dtype=np.uint64)
+    base = np.stack([bit(b) for b in range(13)], axis=1)  # [128][13]: s, n0..n5, j0..j5
+    words = np.repeat(base, len(rs), axis=0)
+    R = np.tile(np.array(rs, dtype=np.uint32), 128)
+    got = sg.flip_words(form, words, R, beta, prng_name)
+    sb = (c & np.uint64(1)).astype(np.int64)
+    v = np.zeros(c.shape, dtype=np.int64)
+    for k in range(6):
+        nb = ((c >> np.uint64(1 + k)) & np.uint64(1)).astype(np.int64)
+        jb = ((c >> np.uint64(7 + k)) & np.uint64(1)).astype(np.int64)
+        v += (sb ^ nb ^ jb) == 0
+    for w in range(128):
+        for k, r in enumerate(rs):
+            flip = acc[v[w], k]
+            want = int(base[w, 0]) ^ int((flip.astype(np.uint64) << np.arange(64, dtype=np.uint64)).sum(
+                dtype=np.uint64))
+            assert int(got[w * len(rs) + k]) == want, (form, w, r)
+    # forms with 32-bit comparisons take MINSTD's thresholds only
+    if form < 2:
+        with pytest.raises(sg.SGError):
+            sg.flip_words(form, words[:1], R[:1], beta, "mt19937")
