@@ -420,6 +420,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=0, help="sweeps per step (default: the workload's)")
+    ap.add_argument("--prng", default="", choices=["", "minstd", "mt19937", "parisi_rapuano", "philox"],
+                    help="generator of the main run (default: the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "twopass"])
     ap.add_argument("--tile", default="",
                     help="kernel and tile [fused|fused2,]tile_x,tile_y,z_chunk,band[,planes] (skips the autotuner)")
@@ -450,7 +452,9 @@ def main():
     from paper_1411_0127_amd import sg
 
     extras = {e.strip() for e in args.extras.split(",") if e.strip()}
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.prng:
+        wl["prng"] = args.prng
     torch.cuda.set_device(0)
     marker = Marker(torch, sg, torch.cuda.current_stream())
     main_res = run_single(args, wl, marker=marker, depth1="depth1" in extras)
@@ -460,7 +464,8 @@ def main():
     V = L**3
     bps = algorithmic_bytes_per_site(wl["prng"], R, main_res["sweeps_per_launch"])
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
+    # counters are taken with the workload's own generator
+    traffic = load_traffic(args.workload) if wl["prng"] == WORKLOADS[args.workload]["prng"] else None
     line = {
         "metric": METRIC,
         "value": round(main_res["ps_per_flip"], 6),
