@@ -453,8 +453,9 @@ def main():
 
     extras = {e.strip() for e in args.extras.split(",") if e.strip()}
     wl = dict(WORKLOADS[args.workload])
-    if args.prng:
+    if args.prng and args.prng != wl["prng"]:
         wl["prng"] = args.prng
+        wl["desc"] = wl["desc"].replace("MINSTD per-site streams", f"{args.prng} numbers")
     torch.cuda.set_device(0)
     marker = Marker(torch, sg, torch.cuda.current_stream())
     main_res = run_single(args, wl, marker=marker, depth1="depth1" in extras)
