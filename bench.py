@@ -85,10 +85,11 @@ def kernel_source_sha() -> str:
     return sha()
 
 
-def load_traffic(workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{workload}.json")
+def load_traffic(name: str, kind: str):
+    """HBM bytes per launch of the sweep kernel `kind` ("fused2", "fused") from
+    committed rocprofv3 counter runs, if they were taken on that kernel and on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{name}.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -96,7 +97,19 @@ def load_traffic(workload: str):
         return None
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
+    if not str(rec.get("kernel", "")).startswith(f"sg::k_{kind}<"):
+        return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def kernel_label(kind: str, sweeps_per_launch: int) -> str:
+    if sweeps_per_launch == 2:
+        return "sg::k_fused2 (two sweeps per launch)"
+    if kind == "fused2":
+        return "sg::k_fused2 and a last sg::k_fused (odd sweep count; figures per sweep)"
+    if kind == "twopass":
+        return "sg::k_twopass (one launch per colour)"
+    return "sg::k_fused (one sweep per launch)"
 
 
 def host_threads() -> int:
@@ -466,7 +479,9 @@ def main():
     bps = algorithmic_bytes_per_site(wl["prng"], R, main_res["sweeps_per_launch"])
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
     # counters are taken with the workload's own generator
-    traffic = load_traffic(args.workload) if wl["prng"] == WORKLOADS[args.workload]["prng"] else None
+    main_kind = "fused2" if main_res["sweeps_per_launch"] == 2 else main_res["kind"]
+    traffic = (load_traffic(args.workload, main_kind) if wl["prng"] == WORKLOADS[args.workload]["prng"]
+               else None)
     line = {
         "metric": METRIC,
         "value": round(main_res["ps_per_flip"], 6),
@@ -500,8 +515,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": ("sg::k_fused2 (two sweeps per launch)" if main_res["sweeps_per_launch"] == 2
-                       else "sg::k_fused (one sweep per launch)"),
+            "kernel": kernel_label(main_res["kind"], main_res["sweeps_per_launch"]),
             "bytes_per_site": bps,
             "sites_per_launch": V,
             "sweeps_per_launch": main_res["sweeps_per_launch"],
@@ -513,6 +527,10 @@ def main():
         line["roofline"]["traffic_gbs"] = round(traffic / (main_res["launch_ms"] * 1e-3) / 1e9, 1)
     if "depth1" in main_res:
         line["depth1"] = main_res["depth1"]
+        t1 = load_traffic(f"{args.workload}_depth1", "fused")
+        if t1 and wl["prng"] == WORKLOADS[args.workload]["prng"]:
+            g1 = t1 / (line["depth1"]["ms_per_sweep"] * 1e-3) / 1e9
+            line["depth1"].update(traffic=t1, traffic_gbs=round(g1, 1), traffic_frac_of_spec=round(g1 / HBM_PEAK_GBS, 4))
     if "peak" in extras:
         pk = measure_peaks()
         line["measured_peak"] = pk

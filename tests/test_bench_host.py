@@ -42,10 +42,19 @@ def test_traffic_record_needs_the_current_kernel_source(monkeypatch):
     with open(os.path.join(ROOT, "profiles", "traffic_sweep_fused_c1.json")) as f:
         rec = json.load(f)
     want = rec["hbm_bytes_per_launch"] if rec["kernel_source_sha"] == b.kernel_source_sha() else None
-    assert b.load_traffic("c1") == want
-    assert b.load_traffic("no-such-workload") is None
+    assert b.load_traffic("c1", "fused2") == want
+    assert b.load_traffic("c1", "fused") is None  # the record is of the two-sweep kernel
+    assert b.load_traffic("no-such-workload", "fused2") is None
     monkeypatch.setattr(b, "kernel_source_sha", lambda: "0" * 16)
-    assert b.load_traffic("c1") is None
+    assert b.load_traffic("c1", "fused2") is None
+
+
+def test_kernel_labels():
+    b = load_bench()
+    assert b.kernel_label("fused2", 2).startswith("sg::k_fused2")
+    assert "odd sweep count" in b.kernel_label("fused2", 1)
+    assert b.kernel_label("fused", 1).startswith("sg::k_fused ")
+    assert b.kernel_label("twopass", 1).startswith("sg::k_twopass")
 
 
 def test_cpu_baseline_record():
