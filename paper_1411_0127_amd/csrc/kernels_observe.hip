@@ -3,51 +3,130 @@
 //   of sample j is unsatisfied (Sec. 4, bond bit e_ik); the energy of Eq. (1) is
 //   E_j = 2 U_j - 3V;
 //   replica difference: bit j of A[i] ^ B[i].
-// Each thread adds its words into a 16-plane bit-sliced ("vertical") counter --
-// plane b holds bit b of 64 per-sample counts -- then the block turns the planes
-// into 64 integers and writes one row of partial sums; a second kernel adds the
-// rows.  No atomics, so the result is deterministic.
+// Each thread adds its words into a bit-sliced ("vertical") count per sample --
+// plane b holds bit b of 64 per-sample counts, kept as two 32-sample halves --
+// then the block turns the planes into 64 integers and writes one row of partial
+// sums; a second kernel adds the rows.  No atomics, so the result is
+// deterministic.
+//
+// The count has two levels: a 4-plane counter takes the words of a few sites (at
+// most 15 ones per sample) and is added into the 16-plane total only when full,
+// so a word costs a short carry chain instead of a 16-plane one.  The bond count
+// walks each thread's (x, y) column up z, so the +z neighbour word read for one
+// site is the spin word of the next, and coordinates are found once per column.
+#include <algorithm>
+
 #include "sg_internal.h"
 
 namespace sg {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPlanes = 16;  // a thread may add at most 2^16 - 1 words
+constexpr int kPlanes = 16;  // a thread may add at most 2^16 - 1 ones per sample
+constexpr int kLowMax = 15;  // ones per sample the 4-plane counter holds
 
-struct VCounter {
-    uint64_t c[kPlanes];
+struct Count2 {
+    uint32_t lo[2][4];
+    uint32_t tot[2][kPlanes];
+    int held;  // ones per sample lo may hold (an upper bound)
+
     __device__ void clear()
     {
 #pragma unroll
-        for (int b = 0; b < kPlanes; ++b)
-            c[b] = 0;
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                lo[h][b] = 0;
+#pragma unroll
+            for (int b = 0; b < kPlanes; ++b)
+                tot[h][b] = 0;
+        }
+        held = 0;
     }
-    __device__ void add(uint64_t w)
+    // lo into tot (ripple-carry add of a 4-bit vertical number), lo cleared
+    __device__ void spill()
     {
 #pragma unroll
-        for (int b = 0; b < kPlanes; ++b) {
-            const uint64_t k = c[b] & w;
-            c[b] ^= w;
-            w = k;
+        for (int h = 0; h < 2; ++h) {
+            uint32_t c = tot[h][0] & lo[h][0];
+            tot[h][0] ^= lo[h][0];
+#pragma unroll
+            for (int b = 1; b < 4; ++b) {
+                const uint32_t t = bop3<bop::kXor3>(tot[h][b], lo[h][b], c);
+                c = bop3<bop::kMaj>(tot[h][b], lo[h][b], c);
+                tot[h][b] = t;
+            }
+#pragma unroll
+            for (int b = 4; b < kPlanes; ++b) {
+                const uint32_t t = tot[h][b] & c;
+                tot[h][b] ^= c;
+                c = t;
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                lo[h][b] = 0;
         }
+        held = 0;
+    }
+    // one word: bit j adds 1 to sample j
+    __device__ void add1(uint64_t w)
+    {
+        if (held + 1 > kLowMax)
+            spill();
+        const uint32_t v[2] = {(uint32_t)w, (uint32_t)(w >> 32)};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t c = v[h];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const uint32_t t = lo[h][b] & c;
+                lo[h][b] ^= c;
+                c = t;
+            }
+            lo[h][3] ^= c;
+        }
+        held += 1;
+    }
+    // three words: bit j of each adds 1 to sample j (a full adder first)
+    __device__ void add3(uint64_t a, uint64_t b, uint64_t c)
+    {
+        if (held + 3 > kLowMax)
+            spill();
+        const uint32_t va[2] = {(uint32_t)a, (uint32_t)(a >> 32)};
+        const uint32_t vb[2] = {(uint32_t)b, (uint32_t)(b >> 32)};
+        const uint32_t vc[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t b0 = bop3<bop::kXor3>(va[h], vb[h], vc[h]);  // weight 1
+            const uint32_t b1 = bop3<bop::kMaj>(va[h], vb[h], vc[h]);   // weight 2
+            const uint32_t k0 = lo[h][0] & b0;
+            lo[h][0] ^= b0;
+            const uint32_t n1 = bop3<bop::kXor3>(lo[h][1], b1, k0);
+            const uint32_t k1 = bop3<bop::kMaj>(lo[h][1], b1, k0);
+            lo[h][1] = n1;
+            const uint32_t k2 = lo[h][2] & k1;
+            lo[h][2] ^= k1;
+            lo[h][3] ^= k2;
+        }
+        held += 3;
     }
 };
 
 // Move the 64 counts of every thread of the block into partials[blockIdx.x][0..63],
 // 32 samples at a time to keep the table within 33 KB of LDS.
-__device__ void block_flush(const VCounter &vc, uint64_t *__restrict__ partials)
+__device__ void block_flush(Count2 &vc, uint64_t *__restrict__ partials)
 {
     __shared__ uint32_t tab[32][kThreads + 1];
+    vc.spill();
     const int tid = threadIdx.x;
+#pragma unroll
     for (int half = 0; half < 2; ++half) {
 #pragma unroll 4
         for (int jj = 0; jj < 32; ++jj) {
-            const int j = half * 32 + jj;
             uint32_t v = 0;
 #pragma unroll
             for (int b = 0; b < kPlanes; ++b)
-                v |= (uint32_t)((vc.c[b] >> j) & 1ull) << b;
+                v |= ((vc.tot[half][b] >> jj) & 1u) << b;
             tab[jj][tid] = v;
         }
         __syncthreads();
@@ -61,26 +140,37 @@ __device__ void block_flush(const VCounter &vc, uint64_t *__restrict__ partials)
     }
 }
 
+// Work item = one (x, y) column over one z range of zc planes; items are numbered
+// x fastest, so a wave reads consecutive words of a row.
 __global__ __launch_bounds__(kThreads) void k_count_unsat(const uint64_t *__restrict__ S,
-                                                          const uint64_t *__restrict__ J, int L,
+                                                          const uint64_t *__restrict__ J, int L, int zc, int nzc,
                                                           uint64_t *__restrict__ partials)
 {
-    const int64_t V = (int64_t)L * L * L;
-    const int64_t Vj = coupling_stride(L);
     const int64_t LL = (int64_t)L * L;
-    VCounter vc;
+    const int64_t Vj = coupling_stride(L);
+    const int64_t items = LL * nzc;
+    Count2 vc;
     vc.clear();
-    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < V; i += (int64_t)gridDim.x * kThreads) {
-        const int x = (int)(i % L);
-        const int y = (int)((i / L) % L);
-        const int64_t z = i / LL;
-        const uint64_t s = S[i];
-        const int64_t ix = (x + 1 == L) ? i - (L - 1) : i + 1;
-        const int64_t iy = (y + 1 == L) ? i - (int64_t)(L - 1) * L : i + L;
-        const int64_t iz = (z + 1 == L) ? i - (V - LL) : i + LL;
-        vc.add(J[i] ^ s ^ S[ix]);
-        vc.add(J[Vj + i] ^ s ^ S[iy]);
-        vc.add(J[2 * Vj + i] ^ s ^ S[iz]);
+    for (int64_t it = blockIdx.x * (int64_t)kThreads + threadIdx.x; it < items; it += (int64_t)gridDim.x * kThreads) {
+        const int64_t col = it % LL;
+        const int z0 = (int)(it / LL) * zc;
+        const int z1 = min(L, z0 + zc);
+        const int y = (int)(col / L);
+        const int x = (int)(col - (int64_t)y * L);
+        const int64_t dx = (x + 1 == L) ? -(int64_t)(L - 1) : 1;
+        const int64_t dy = (y + 1 == L) ? -(int64_t)(L - 1) * L : (int64_t)L;
+        int64_t i = (int64_t)z0 * LL + col;
+        uint64_t s = S[i];
+#pragma unroll 4
+        for (int z = z0; z < z1; ++z, i += LL) {
+            // bond (i, i + d) of sample j is unsatisfied when bit j of J[d][i] ^ s_i ^ s_{i+d} is 1
+            const uint64_t sz = S[(z + 1 == L) ? col : i + LL];
+            const uint64_t wx = J[i] ^ s ^ S[i + dx];
+            const uint64_t wy = J[Vj + i] ^ s ^ S[i + dy];
+            const uint64_t wz = J[2 * Vj + i] ^ s ^ sz;
+            vc.add3(wx, wy, wz);
+            s = sz;
+        }
     }
     block_flush(vc, partials);
 }
@@ -89,15 +179,13 @@ __global__ __launch_bounds__(kThreads) void k_count_diff(const uint64_t *__restr
                                                          const uint64_t *__restrict__ B, int64_t V,
                                                          uint64_t *__restrict__ partials)
 {
-    VCounter vc;
+    Count2 vc;
     vc.clear();
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < V; i += (int64_t)gridDim.x * kThreads)
-        vc.add(A[i] ^ B[i]);
+        vc.add1(A[i] ^ B[i]);
     block_flush(vc, partials);
 }
 
-// Sum the per-block rows: 16 threads per sample each add every 16th row, then
-// the 16 partial sums of a sample are added in LDS.
 __global__ __launch_bounds__(1024) void k_reduce_partials(const uint64_t *__restrict__ partials, int nblocks,
                                                           uint64_t *__restrict__ out)
 {
@@ -105,6 +193,7 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const uint64_t *__rest
     const int j = threadIdx.x & 63;
     const int q = threadIdx.x >> 6;
     uint64_t s = 0;
+#pragma unroll 8
     for (int b = q; b < nblocks; b += 16)
         s += partials[(size_t)b * 64 + j];
     part[q][j] = s;
@@ -138,11 +227,21 @@ int blocks_for(int64_t words_per_site, int64_t V)
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,
                               hipStream_t s)
 {
-    const int64_t V = (int64_t)L * L * L;
-    nblocks = blocks_for(3, V);
-    if ((int64_t)nblocks * kThreads * (((1 << kPlanes) - 1) / 3) < V)
+    if (L < 2)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_count_unsat, dim3(nblocks), dim3(kThreads), 0, s, S, J, L, partials);
+    // z range per work item: whole columns where one plane has an item for every
+    // thread of kMaxReduceBlocks blocks, shorter ranges below that
+    const int64_t LL = (int64_t)L * L;
+    const int64_t want = (int64_t)kMaxReduceBlocks * kThreads;
+    const int64_t n = std::min<int64_t>(L, std::max<int64_t>(1, (want + LL - 1) / LL));
+    const int zc = (int)((L + n - 1) / n);
+    const int nzc = (L + zc - 1) / zc;
+    const int64_t items = LL * nzc;
+    nblocks = (int)std::min<int64_t>(kMaxReduceBlocks, (items + kThreads - 1) / kThreads);
+    const int64_t per_thread = (items + (int64_t)nblocks * kThreads - 1) / ((int64_t)nblocks * kThreads);
+    if (3 * (int64_t)zc * per_thread > (1 << kPlanes) - 1)  // the count of one thread must fit 16 planes
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_count_unsat, dim3(nblocks), dim3(kThreads), 0, s, S, J, L, zc, nzc, partials);
     return hipGetLastError();
 }
 
