@@ -151,13 +151,15 @@ def flip_words(form: int, words: np.ndarray, R: np.ndarray, beta: float, prng="m
     n = r.size
     assert w.shape == (n, 13)
     stream = stream if stream is not None else torch.cuda.current_stream()
-    dw = torch.from_numpy(w.view(np.int64)).to("cuda")
-    dr = torch.from_numpy(r.view(np.int32)).to("cuda")
-    out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
-    _check(lib.sg_flip_words(int(form), _p(dw.data_ptr()), _p(dr.data_ptr()), n, float(beta), PRNGS[prng],
-                             _p(out.data_ptr()), _p(stream.cuda_stream)))
+    with torch.cuda.stream(stream):  # the copies, the kernel and the read-back in one stream order
+        dw = torch.from_numpy(w.view(np.int64)).to("cuda")
+        dr = torch.from_numpy(r.view(np.int32)).to("cuda")
+        out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        _check(lib.sg_flip_words(int(form), _p(dw.data_ptr()), _p(dr.data_ptr()), n, float(beta), PRNGS[prng],
+                                 _p(out.data_ptr()), _p(stream.cuda_stream)))
+        res = out[:n].cpu()
     stream.synchronize()
-    return out[:n].cpu().numpy().view(np.uint64)
+    return res.numpy().view(np.uint64)
 
 
 def footprint(L: int, prng="minstd", own_couplings: bool = True, nsamples: int = 64) -> int:
