@@ -23,10 +23,11 @@
 // because a site's random number depends only on (stream, site, sweep).  A z-chunk
 // likewise recomputes the red plane below and above it.
 //
-// Launch.  One workgroup per (tile, z-chunk); block ids are spread so that
-// consecutive tiles land on the same XCD (blocks are dealt to the 8 XCDs round
-// robin), and tiles are numbered in column-major blocks a few tiles tall, so the
-// workgroups resident on an XCD together cover a compact block of the plane.
+// Launch.  One workgroup per (tile, z-chunk); block ids are spread so that as many
+// consecutive tiles as an XCD holds workgroups land on the same XCD (blocks are
+// dealt to the 8 XCDs round robin), and tiles are numbered in column-major blocks
+// a few tiles tall, so the workgroups resident on an XCD together cover a compact
+// block of the plane, next to the blocks the other XCDs run at the same time.
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -48,6 +49,7 @@ struct FusedParams {
     int WE;              // waves holding the even tile rows
     int WO[2];           // two sweeps per launch: waves of outer ring rows, even and odd class
     int band;            // tile rows per group of the tile order
+    int xgroup;          // consecutive work items given to one XCD in turn (its resident workgroups)
     uint32_t a;          // MINSTD multiplier of this sweep
     uint32_t a2;         // two sweeps per launch: multiplier of the second sweep
     int nrep;            // two sweeps per launch: replicas, one per workgroup (interleaved items)
@@ -442,9 +444,26 @@ __device__ __forceinline__ void fused_march(const FusedParams &p, const int tile
 #undef SG_FUSED_STEP
 }
 
-// Block b -> work item: blocks are dealt to the 8 XCDs round robin, so consecutive
-// items go to the same XCD when the grid is a multiple of 8.
-__device__ __forceinline__ int xcd_item(int b, int nb) { return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b; }
+// Block b -> work item.  Blocks are dealt to the 8 XCDs round robin; here groups of
+// G consecutive items go to one XCD in turn, G = the workgroups an XCD holds at
+// once, so that those workgroups cover one compact block of tiles (their shared
+// ring lines are read once into the XCD's L2) and the blocks of the eight XCDs
+// running at the same time are neighbours (lines shared across XCDs are then read
+// at about the same time, while the memory-side cache still holds them).  Grids
+// below 8 G use groups of nb / 8; blocks past the last whole round keep their
+// index.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_item(int b, int nb, int G)
+{
+    if (nb < 8 * G)
+        G = nb / 8;
+    if (G < 1)
+        return b;
+    const int full = nb / (8 * G) * (8 * G);
+    if (b >= full)
+        return b;
+    const int x = b & 7, k = b >> 3;
+    return ((k / G) * 8 + x) * G + k % G;
+}
 
 // Block b -> work item of a batch, whose items differ in length (lattices of
 // different sides): groups of kBatchGroup consecutive items are dealt to the XCDs
@@ -462,7 +481,7 @@ template <int PRNG, int NREP>
 __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused_march<PRNG, NREP, 0>(p, xcd_item(blockIdx.x, gridDim.x), lds,
+    fused_march<PRNG, NREP, 0>(p, xcd_item(blockIdx.x, gridDim.x, p.xgroup), lds,
                             std::make_integer_sequence<int, Ring<NREP>::value>{});
 }
 
@@ -833,7 +852,7 @@ template <int PRNG, int NS>
 __global__ __launch_bounds__(kMaxThreads) void k_fused2(FusedParams p)
 {
     extern __shared__ uint64_t lds[];
-    fused2_march<PRNG, NS, 0>(p, xcd_item(blockIdx.x, gridDim.x), lds, Ring2Steps<NS>{});
+    fused2_march<PRNG, NS, 0>(p, xcd_item(blockIdx.x, gridDim.x, p.xgroup), lds, Ring2Steps<NS>{});
 }
 
 // One work item of a batch round: item `local` (tile and z chunk) of lattice e in
@@ -868,6 +887,7 @@ __device__ __forceinline__ void batch_item(const BatchEntry &e, int64_t r, int l
     p.nty = e.nty;
     p.nzc = e.nzc;
     p.band = e.band;
+    p.xgroup = kBatchGroup;  // unused: batch items are placed by the run's own order
     p.nrep = 1;
     p.t = e.t0 + s0;
     p.pkey[0] = p.pkey[1] = 0;
@@ -1164,6 +1184,22 @@ void fused_default_shape(int L, int nrep, int &tile_x, int &tile_y, int &z_chunk
         }
 }
 
+// Workgroups of kernel `fn` resident at once: per XCD (the item group of xcd_item)
+// and on the device.
+struct Residency {
+    int per_xcd;
+    int64_t slots;
+};
+static Residency residency(const void *fn, int threads, size_t lds)
+{
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return Residency{std::max(1, cus / 8 * per_cu), (int64_t)cus * per_cu};
+}
+
 // z chunk length for a grid of `tiles` work items per chunk: workgroups run in
 // rounds of `slots`; take the chunk count with the shortest rounds * (ZC + extra)
 // (`extra` planes are loaded per chunk beyond its own: 4 for one sweep per launch,
@@ -1278,26 +1314,17 @@ hipError_t launch_round_reset(int64_t *round_ctr, hipStream_t s)
 
 hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_chunk, int band, hipStream_t s)
 {
+    const void *fn = a.nrep == 1 ? (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 1>
+                                     : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 1>
+                                                           : (const void *)k_fused<SG_MT19937, 1>)
+                                  : (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 2>
+                                     : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 2>
+                                                           : (const void *)k_fused<SG_MT19937, 2>);
+    const Residency res = residency(fn, fused_threads(tile_x, tile_y), fused_lds_bytes(a.nrep, tile_x, tile_y));
     if (z_chunk == 0) {
-        // workgroups resident at once: CUs x workgroups per CU
-        const int threads = fused_threads(tile_x, tile_y);
-        const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
-        int dev = 0, cus = 256, per_cu = 1;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const void *fn =
-            a.nrep == 1
-                ? (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 1>
-                   : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 1>
-                                          : (const void *)k_fused<SG_MT19937, 1>)
-                : (a.prng == SG_MINSTD    ? (const void *)k_fused<SG_MINSTD, 2>
-                   : a.prng == SG_PHILOX ? (const void *)k_fused<SG_PHILOX, 2>
-                                          : (const void *)k_fused<SG_MT19937, 2>);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
-            per_cu = 1;
         const int P = a.L / 2;
         const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((a.L + tile_y - 1) / tile_y);
-        z_chunk = choose_z_chunk(a.L, tiles, (int64_t)cus * per_cu, 4);
+        z_chunk = choose_z_chunk(a.L, tiles, res.slots, 4);
     }
     FusedParams p;
     p.J = a.J;
@@ -1327,6 +1354,7 @@ hipError_t launch_sweep_fused(const SweepArgs &a, int tile_x, int tile_y, int z_
     p.WE = fused_waves_even(tile_x, tile_y);
     p.WO[0] = p.WO[1] = 0;
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
+    p.xgroup = res.per_xcd;
     const int threads = fused_threads(tile_x, tile_y);
     const size_t lds = fused_lds_bytes(a.nrep, tile_x, tile_y);
     if (threads > max_threads(a.nrep) || lds > (size_t)max_lds_bytes())
@@ -1414,16 +1442,9 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     const size_t lds = fused2_lds_bytes(tile_x, tile_y);
     const int P = a.L / 2;
     const int64_t tiles = (int64_t)((P + tile_x - 1) / tile_x) * ((a.L + tile_y - 1) / tile_y);
-    if (z_chunk == 0) {
-        int dev = 0, cus = 256, per_cu = 1;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        z_chunk = choose_z_chunk(a.L, tiles * a.nrep, (int64_t)cus * per_cu, 8);
-    }
+    const Residency res = residency(fn, threads, lds);
+    if (z_chunk == 0)
+        z_chunk = choose_z_chunk(a.L, tiles * a.nrep, res.slots, 8);
     FusedParams p;
     p.J = a.J;
     for (int r = 0; r < 2; ++r) {
@@ -1454,6 +1475,7 @@ hipError_t launch_sweep_fused2(const SweepArgs &a, int tile_x, int tile_y, int z
     p.WO[0] = fw.outer[0];
     p.WO[1] = fw.outer[1];
     p.band = band < 1 ? 1 : (band > p.nty ? p.nty : band);
+    p.xgroup = res.per_xcd;
     const int64_t blocks = (int64_t)p.ntx * p.nty * p.nzc * a.nrep;
     if (blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
