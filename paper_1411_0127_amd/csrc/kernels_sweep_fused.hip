@@ -29,6 +29,9 @@
 // a few tiles tall, so the workgroups resident on an XCD together cover a compact
 // block of the plane, next to the blocks the other XCDs run at the same time.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 
@@ -1192,12 +1195,27 @@ struct Residency {
 };
 static Residency residency(const void *fn, int threads, size_t lds)
 {
+    // queried once per (device, kernel, shape): launches of one lattice repeat them
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int, size_t>, Residency> known;
     int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess)
+    if (hipGetDevice(&dev) != hipSuccess)
+        dev = -1;
+    const auto key = std::make_tuple(dev, fn, threads, lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto it = known.find(key);
+        if (it != known.end())
+            return it->second;
+    }
+    if (dev >= 0)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    return Residency{std::max(1, cus / 8 * per_cu), (int64_t)cus * per_cu};
+    const Residency r{std::max(1, cus / 8 * per_cu), (int64_t)cus * per_cu};
+    std::lock_guard<std::mutex> g(mu);
+    known[key] = r;
+    return r;
 }
 
 // z chunk length for a grid of `tiles` work items per chunk: workgroups run in
