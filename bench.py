@@ -85,21 +85,28 @@ def kernel_source_sha() -> str:
     return sha()
 
 
-def load_traffic(name: str, kind: str):
+def load_traffic(name: str, kind: str, tile=None):
     """HBM bytes per launch of the sweep kernel `kind` ("fused2", "fused") from
-    committed rocprofv3 counter runs, if they were taken on that kernel and on the
-    current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{name}.json")
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_source_sha") != kernel_source_sha():
-        return None
-    if not str(rec.get("kernel", "")).startswith(f"sg::k_{kind}<"):
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    committed rocprofv3 counter runs of workload `name`, if they were taken on that
+    kernel, on the current kernel source and (when `tile` is given) on launches of
+    that shape (kind, tile_x, tile_y, z_chunk, band, planes); else None."""
+    import glob
+
+    sha = kernel_source_sha()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{name}*.json"))):
+        try:
+            with open(path) as f:
+                rec = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if rec.get("workload") != name or rec.get("kernel_source_sha") != sha:
+            continue
+        if not str(rec.get("kernel", "")).startswith(f"sg::k_{kind}<"):
+            continue
+        if tile is not None and [str(v) for v in rec.get("tile", [])] != [str(v) for v in tile]:
+            continue
+        return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def kernel_label(kind: str, sweeps_per_launch: int) -> str:
@@ -480,8 +487,8 @@ def main():
     achieved = bps * V / (main_res["launch_ms"] * 1e-3) / 1e9
     # counters are taken with the workload's own generator
     main_kind = "fused2" if main_res["sweeps_per_launch"] == 2 else main_res["kind"]
-    traffic = (load_traffic(args.workload, main_kind) if wl["prng"] == WORKLOADS[args.workload]["prng"]
-               else None)
+    traffic = (load_traffic(args.workload, main_kind, main_res["tile"])
+               if wl["prng"] == WORKLOADS[args.workload]["prng"] else None)
     line = {
         "metric": METRIC,
         "value": round(main_res["ps_per_flip"], 6),
@@ -527,7 +534,7 @@ def main():
         line["roofline"]["traffic_gbs"] = round(traffic / (main_res["launch_ms"] * 1e-3) / 1e9, 1)
     if "depth1" in main_res:
         line["depth1"] = main_res["depth1"]
-        t1 = load_traffic(f"{args.workload}_depth1", "fused")
+        t1 = load_traffic(f"{args.workload}_depth1", "fused", line["depth1"]["tile"])
         if t1 and wl["prng"] == WORKLOADS[args.workload]["prng"]:
             g1 = t1 / (line["depth1"]["ms_per_sweep"] * 1e-3) / 1e9
             line["depth1"].update(traffic=t1, traffic_gbs=round(g1, 1), traffic_frac_of_spec=round(g1 / HBM_PEAK_GBS, 4))

@@ -139,7 +139,11 @@ def _per_dispatch(path: str, counter: str, part: str = "all"):
     return vals
 
 
-def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str, out_dir: str = "") -> str:
+def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str, out_dir: str = "",
+            tile: str = "") -> str:
+    """HBM bytes per sweep launch of `workload`; `tile` ("kind,tile_x,tile_y,z_chunk,band,planes", the
+    `bench.py --tile` the counter runs were given) is recorded and names the file, so that a
+    benchmark run applies the record only to launches of that shape."""
     # the sweep launches of the timed region only (no autotuner candidate), and the
     # calibration copies made after it (not the autotuner's copies of the spins)
     ft = _per_dispatch(fetch_csv, "FETCH_SIZE", "timed")
@@ -181,7 +185,12 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
         "command_fetch": command.replace("<COUNTER>", "FETCH_SIZE"),
         "command_write": command.replace("<COUNTER>", "WRITE_SIZE"),
     }
-    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_sweep_fused_{workload}.json")
+    name = workload
+    if tile:
+        parts = [t.strip() for t in tile.split(",")]
+        rec["tile"] = [parts[0]] + [int(v) for v in parts[1:]]
+        name += "_" + "_".join(parts)
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_sweep_fused_{name}.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     return out
@@ -193,6 +202,7 @@ if __name__ == "__main__":
     elif sys.argv[1] == "trace":
         print(trace(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "traffic":
-        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6]))
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6],
+                      tile=sys.argv[7] if len(sys.argv) > 7 else ""))
     else:
         raise SystemExit(__doc__)

@@ -1,6 +1,7 @@
 """Host logic of bench.py, without a GPU: the one-GPU contract, the algorithmic
 bytes of each launch kind, the source check of the traffic record and the CPU
 baseline record."""
+import glob
 import importlib.util
 import json
 import os
@@ -37,16 +38,20 @@ def test_algorithmic_bytes_per_site():
     assert b.algorithmic_bytes_per_site("parisi_rapuano", 1, 2) == 48
 
 
-def test_traffic_record_needs_the_current_kernel_source(monkeypatch):
+def test_traffic_record_needs_the_current_kernel_source_and_shape(monkeypatch):
     b = load_bench()
-    with open(os.path.join(ROOT, "profiles", "traffic_sweep_fused_c1.json")) as f:
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_sweep_fused_c1_*.json")))
+    assert paths, "the L=256 workload has committed counter records"
+    with open(paths[0]) as f:
         rec = json.load(f)
+    tile = rec["tile"]
     want = rec["hbm_bytes_per_launch"] if rec["kernel_source_sha"] == b.kernel_source_sha() else None
-    assert b.load_traffic("c1", "fused2") == want
-    assert b.load_traffic("c1", "fused") is None  # the record is of the two-sweep kernel
-    assert b.load_traffic("no-such-workload", "fused2") is None
+    assert b.load_traffic("c1", "fused2", tile) == want
+    assert b.load_traffic("c1", "fused", tile) is None  # the record is of the two-sweep kernel
+    assert b.load_traffic("c1", "fused2", tile[:4] + [tile[4] + 100] + tile[5:]) is None  # another band
+    assert b.load_traffic("no-such-workload", "fused2", tile) is None
     monkeypatch.setattr(b, "kernel_source_sha", lambda: "0" * 16)
-    assert b.load_traffic("c1", "fused2") is None
+    assert b.load_traffic("c1", "fused2", tile) is None
 
 
 def test_kernel_labels():
