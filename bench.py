@@ -85,15 +85,15 @@ def kernel_source_sha() -> str:
     return sha()
 
 
-def load_traffic(name: str, kind: str, tile=None):
-    """HBM bytes per launch of the sweep kernel `kind` ("fused2", "fused") from
-    committed rocprofv3 counter runs of workload `name`, if they were taken on that
-    kernel, on the current kernel source and (when `tile` is given) on launches of
-    that shape (kind, tile_x, tile_y, z_chunk, band, planes); else None."""
+def _load_record(prefix: str, field: str, name: str, kind: str, tile=None):
+    """`field` of the committed rocprofv3 counter record (profiles/<prefix>_<name>*.json)
+    of workload `name`, if it was taken on sweep kernel `kind` ("fused2", "fused"), on
+    the current kernel source and (when `tile` is given) on launches of that shape
+    (kind, tile_x, tile_y, z_chunk, band, planes); else None."""
     import glob
 
     sha = kernel_source_sha()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_sweep_fused_{name}*.json"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{prefix}_{name}*.json"))):
         try:
             with open(path) as f:
                 rec = json.load(f)
@@ -105,8 +105,31 @@ def load_traffic(name: str, kind: str, tile=None):
             continue
         if tile is not None and [str(v) for v in rec.get("tile", [])] != [str(v) for v in tile]:
             continue
-        return rec.get("hbm_bytes_per_launch")
+        return rec.get(field)
     return None
+
+
+def load_traffic(name: str, kind: str, tile=None):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a device copy)."""
+    return _load_record("traffic_sweep_fused", "hbm_bytes_per_launch", name, kind, tile)
+
+
+def load_valu(name: str, kind: str, tile=None):
+    """VALU wave instructions per launch (SQ_INSTS_VALU over the device)."""
+    return _load_record("valu_sweep_fused", "valu_wave_insts_per_launch", name, kind, tile)
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs, each issuing one wave64 instruction every 4
+# cycles (16 lanes) at 2.4 GHz: 614.4 G wave instructions/s, i.e. 39.3 T lane-ops/s
+# of 32-bit integer and bitwise work.
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def alu_roofline(insts: float, launch_ms: float) -> dict:
+    rate = insts / (launch_ms * 1e-3)
+    return {"bound": "alu", "achieved": round(rate / 1e9, 1), "peak": round(VALU_PEAK_WAVE_INSTS / 1e9, 1),
+            "unit": "G wave64 VALU instr/s", "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+            "valu_wave_insts_per_launch": insts}
 
 
 def kernel_label(kind: str, sweeps_per_launch: int) -> str:
@@ -532,6 +555,10 @@ def main():
     }
     if traffic:
         line["roofline"]["traffic_gbs"] = round(traffic / (main_res["launch_ms"] * 1e-3) / 1e9, 1)
+    insts = (load_valu(args.workload, main_kind, main_res["tile"])
+             if wl["prng"] == WORKLOADS[args.workload]["prng"] else None)
+    if insts:
+        line["alu_roofline"] = alu_roofline(insts, main_res["launch_ms"])
     if "depth1" in main_res:
         line["depth1"] = main_res["depth1"]
         t1 = load_traffic(f"{args.workload}_depth1", "fused", line["depth1"]["tile"])
@@ -559,6 +586,10 @@ def main():
             if prng == "minstd":
                 b1 = algorithmic_bytes_per_site("minstd", 2, r["sweeps_per_launch"])
                 c1[prng]["alg_gbs_per_launch"] = round(b1 * 256**3 / (r["launch_ms"] * 1e-3) / 1e9, 1)
+                k1 = "fused2" if r["sweeps_per_launch"] == 2 else r["kind"]
+                insts = load_valu("c1", k1, r["tile"])
+                if insts:
+                    c1[prng]["alu_roofline"] = alu_roofline(insts, r["launch_ms"])
         line["c1"] = {"workload": WORKLOADS["c1"]["desc"], **c1}
         print(f"[bench] c1 done", file=sys.stderr, flush=True)
     for kind in ("c3", "c4"):

@@ -10,10 +10,14 @@ device copy of known size (``bench.py --calibrate-copy``): each counter is scale
 by what it reads for that copy, which moves exactly its size in each direction;
 only the sweep dispatches between the two marker fills count, and only the copies
 after the second one (the autotuner copies spins before the timed region).
+``valu``: VALU wave instructions per launch of the timed sweep launches, from a
+``--pmc SQ_INSTS_VALU GRBM_GUI_ACTIVE`` run, for the ALU roofline of sizes that
+the VALU rather than HBM bounds.
 
     python -m paper_1411_0127_amd.profiling stats  <stats.csv> <out.md> "<command>"
     python -m paper_1411_0127_amd.profiling trace  <kernel_trace.csv> <out.md> "<command>"
-    python -m paper_1411_0127_amd.profiling traffic <fetch.csv> <write.csv> <workload> <copy_bytes> "<command>"
+    python -m paper_1411_0127_amd.profiling traffic <fetch.csv> <write.csv> <workload> <copy_bytes> "<command>" [tile]
+    python -m paper_1411_0127_amd.profiling valu <counters.csv> <workload> "<command>" <tile>
 """
 from __future__ import annotations
 
@@ -187,10 +191,45 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, comm
     }
     name = workload
     if tile:
-        parts = [t.strip() for t in tile.split(",")]
-        rec["tile"] = [parts[0]] + [int(v) for v in parts[1:]]
-        name += "_" + "_".join(parts)
+        rec["tile"], tag = _tile_list(tile)
+        name += "_" + tag
     out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_sweep_fused_{name}.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return out
+
+
+def _tile_list(tile: str):
+    parts = [t.strip() for t in tile.split(",")]
+    return [parts[0]] + [int(v) for v in parts[1:]], "_".join(parts)
+
+
+def valu(csv_path: str, workload: str, command: str, tile: str, out_dir: str = "") -> str:
+    """VALU wave instructions (SQ_INSTS_VALU, summed over the device) and GPU-active
+    cycles (GRBM_GUI_ACTIVE) per timed sweep launch of `bench.py --tile <tile>`."""
+    insts = _per_dispatch(csv_path, "SQ_INSTS_VALU", "timed")
+    active = _per_dispatch(csv_path, "GRBM_GUI_ACTIVE", "timed")
+
+    def sweep(d):
+        v = [x for k in d if SWEEP_KERNEL in k for x in d[k]]
+        if not v:
+            raise SystemExit("no sweep dispatches in the timed region of the counter file")
+        return v
+
+    names = sorted({k for k in insts if SWEEP_KERNEL in k})
+    short = sorted({n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0] for n in names})
+    tl, tag = _tile_list(tile)
+    rec = {
+        "kernel": ", ".join(short),
+        "workload": workload,
+        "tile": tl,
+        "kernel_source_sha": kernel_source_sha(),
+        "valu_wave_insts_per_launch": statistics.median(sweep(insts)),
+        "gui_active_cycles_per_launch": statistics.median(sweep(active)),
+        "launches": len(sweep(insts)),
+        "command": command,
+    }
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"valu_sweep_fused_{workload}_{tag}.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     return out
@@ -204,5 +243,7 @@ if __name__ == "__main__":
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6],
                       tile=sys.argv[7] if len(sys.argv) > 7 else ""))
+    elif sys.argv[1] == "valu":
+        print(valu(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5]))
     else:
         raise SystemExit(__doc__)

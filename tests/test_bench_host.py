@@ -54,6 +54,13 @@ def test_traffic_record_needs_the_current_kernel_source_and_shape(monkeypatch):
     assert b.load_traffic("c1", "fused2", tile) is None
 
 
+def test_alu_roofline_figures():
+    b = load_bench()
+    assert b.VALU_PEAK_WAVE_INSTS == 614.4e9
+    r = b.alu_roofline(614.4e6, 2.0)  # 614.4 M wave instructions in 2 ms: half the issue peak
+    assert r["bound"] == "alu" and r["frac"] == 0.5 and r["peak"] == 614.4 and r["achieved"] == 307.2
+
+
 def test_kernel_labels():
     b = load_bench()
     assert b.kernel_label("fused2", 2).startswith("sg::k_fused2")

@@ -70,3 +70,22 @@ def test_traffic_needs_the_markers(tmp_path):
     write_counters(wp, "WRITE_SIZE", [(SWEEP, 1.0), (COPY, 1.0)])
     with pytest.raises(SystemExit):
         profiling.traffic(str(fp), str(wp), "cx", 1 << 30, "cmd", out_dir=str(tmp_path))
+
+
+def test_valu_record_counts_the_timed_launches(tmp_path):
+    rows = []
+    for k, (name, insts, cyc) in enumerate([(SWEEP, 5.0, 9.0), (MARK, 0.0, 1.0), (SWEEP, 100.0, 50.0),
+                                            (SWEEP, 102.0, 52.0), (SWEEP, 101.0, 51.0), (MARK, 0.0, 1.0),
+                                            (SWEEP, 7.0, 3.0)]):
+        rows.append({"Dispatch_Id": k + 1, "Kernel_Name": name, "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": insts})
+        rows.append({"Dispatch_Id": k + 1, "Kernel_Name": name, "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": cyc})
+    p = tmp_path / "v.csv"
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        w.writerows(rows)
+    out = profiling.valu(str(p), "cx", "cmd", "fused2,16,16,0,1,5", out_dir=str(tmp_path))
+    assert out.endswith("valu_sweep_fused_cx_fused2_16_16_0_1_5.json")
+    rec = json.load(open(out))
+    assert rec["valu_wave_insts_per_launch"] == 101.0 and rec["gui_active_cycles_per_launch"] == 51.0
+    assert rec["launches"] == 3 and rec["tile"] == ["fused2", 16, 16, 0, 1, 5]
