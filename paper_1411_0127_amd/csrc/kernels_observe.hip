@@ -224,22 +224,34 @@ int blocks_for(int64_t words_per_site, int64_t V)
 
 }  // namespace
 
+// Shape of the bond count with at most max_blocks blocks: a thread for every 16
+// sites (short walks, for latency at small sides), at most max_blocks blocks; z range per work item
+// (whole columns where one plane has an item for every thread, shorter ranges
+// below that), items and blocks; false if a thread would add more than 2^16 - 1
+// ones per sample.
+static bool unsat_shape(int L, int max_blocks, int &zc, int &nzc, int &nblocks)
+{
+    const int64_t LL = (int64_t)L * L;
+    const int64_t want = std::min<int64_t>((int64_t)max_blocks * kThreads, (LL * L + 15) / 16);
+    const int64_t n = std::min<int64_t>(L, std::max<int64_t>(1, (want + LL - 1) / LL));
+    zc = (int)((L + n - 1) / n);
+    nzc = (L + zc - 1) / zc;
+    const int64_t items = LL * nzc;
+    nblocks = (int)std::min<int64_t>(max_blocks, (items + kThreads - 1) / kThreads);
+    const int64_t per_thread = (items + (int64_t)nblocks * kThreads - 1) / ((int64_t)nblocks * kThreads);
+    return 3 * (int64_t)zc * per_thread <= (1 << kPlanes) - 1;
+}
+
 hipError_t launch_count_unsat(const uint64_t *S, const uint64_t *J, int L, uint64_t *partials, int &nblocks,
                               hipStream_t s)
 {
     if (L < 2)
         return hipErrorInvalidValue;
-    // z range per work item: whole columns where one plane has an item for every
-    // thread of kMaxReduceBlocks blocks, shorter ranges below that
-    const int64_t LL = (int64_t)L * L;
-    const int64_t want = (int64_t)kMaxReduceBlocks * kThreads;
-    const int64_t n = std::min<int64_t>(L, std::max<int64_t>(1, (want + LL - 1) / LL));
-    const int zc = (int)((L + n - 1) / n);
-    const int nzc = (L + zc - 1) / zc;
-    const int64_t items = LL * nzc;
-    nblocks = (int)std::min<int64_t>(kMaxReduceBlocks, (items + kThreads - 1) / kThreads);
-    const int64_t per_thread = (items + (int64_t)nblocks * kThreads - 1) / ((int64_t)nblocks * kThreads);
-    if (3 * (int64_t)zc * per_thread > (1 << kPlanes) - 1)  // the count of one thread must fit 16 planes
+    // half the reduction rows where the count fits them (one resident round of
+    // blocks; the rest of the reduction area then holds the totals of many sweeps),
+    // all of them for the largest sides
+    int zc = 0, nzc = 0;
+    if (!unsat_shape(L, kMaxReduceBlocks / 2, zc, nzc, nblocks) && !unsat_shape(L, kMaxReduceBlocks, zc, nzc, nblocks))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_count_unsat, dim3(nblocks), dim3(kThreads), 0, s, S, J, L, zc, nzc, partials);
     return hipGetLastError();
