@@ -20,6 +20,44 @@ namespace {
 constexpr int kSmallThreads = 1024;
 constexpr int kPerThread = kSmallSites / 2 / kSmallThreads;  // sites of one colour per thread
 constexpr int kCountPlanes = 4;  // a thread adds at most 3 * 4 = 12 bond words per count
+constexpr int kWavePlanes = 10;  // a wave's count is at most 64 * 12 = 768 < 2^10
+constexpr int kBallotSamples = 16;  // up to this many samples the counts are read by ballots
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Per-sample totals of the wave's bit-sliced counts (planes cnt[0..3], bit j of
+// plane b = bit b of lane's count of sample j), for every sample: a butterfly of
+// bit-sliced additions across the lanes, after which every lane holds the wave's
+// ten planes, and lane j reads sample j's total out of them.
+__device__ __forceinline__ uint64_t wave_counts(const uint64_t (&cnt)[kCountPlanes], int lane)
+{
+    uint64_t w[kWavePlanes];
+#pragma unroll
+    for (int b = 0; b < kWavePlanes; ++b)
+        w[b] = b < kCountPlanes ? cnt[b] : 0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        // counts are below 12 * 2^l before this level: 4 + l planes in use, one more after it
+        uint64_t c = 0;
+#pragma unroll
+        for (int b = 0; b < kCountPlanes + l + 1 && b < kWavePlanes; ++b) {
+            const uint64_t o = shfl_xor64(w[b], 1 << l);
+            const uint64_t sum = w[b] ^ o ^ c;
+            c = (w[b] & o) | (c & (w[b] ^ o));
+            w[b] = sum;
+        }
+    }
+    uint64_t tot = 0;
+#pragma unroll
+    for (int b = 0; b < kWavePlanes; ++b)
+        tot |= ((w[b] >> lane) & 1ull) << b;
+    return tot;
+}
 
 static_assert(kSmallSites % (2 * kSmallThreads) == 0, "whole sites of each colour per thread");
 
@@ -129,16 +167,20 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                         }
                     }
                 }
-            // per wave: the count of sample j is the sum over planes b of 2^b times the
-            // lanes whose plane b has bit j set; lane j keeps sample j's total (samples
-            // past nsamples are simulated but not counted)
+            // per wave, lane j keeps sample j's total: for a few samples, the sum over
+            // planes b of 2^b times the lanes whose plane b has bit j set (samples past
+            // nsamples are simulated but not counted); for more, the butterfly
             uint64_t mine = 0;
-            for (int j = 0; j < nsamples; ++j) {
-                uint64_t tot = 0;
+            if (nsamples <= kBallotSamples) {
+                for (int j = 0; j < nsamples; ++j) {
+                    uint64_t tot = 0;
 #pragma unroll
-                for (int b = 0; b < kCountPlanes; ++b)
-                    tot += (uint64_t)__popcll(__ballot((cnt[b] >> j) & 1ull)) << b;
-                mine = lane == j ? tot : mine;
+                    for (int b = 0; b < kCountPlanes; ++b)
+                        tot += (uint64_t)__popcll(__ballot((cnt[b] >> j) & 1ull)) << b;
+                    mine = lane == j ? tot : mine;
+                }
+            } else {
+                mine = wave_counts(cnt, lane);
             }
             part[wave][lane] = mine;
             __syncthreads();
