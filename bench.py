@@ -143,8 +143,8 @@ def kernel_label(kind: str, sweeps_per_launch: int) -> str:
 
 
 def host_threads() -> int:
-    """Host threads this job may use: the box's share (OMP_NUM_THREADS), else the
-    cores the process may run on, at most 16."""
+    """Host threads this job may use: OMP_NUM_THREADS when set, else the cores the
+    process may run on, at most 16."""
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit() and int(env) > 0:
         return int(env)

@@ -1,5 +1,5 @@
-"""CPU checks of the paper's sliced-layout transformation (Sec. 2), as this build
-reads it: x' = x, y' = y - x, z' = x - y + z (mod L) is a bijection of the periodic
+"""CPU checks of the paper's sliced-layout transformation (Sec. 2), as the layout
+kernels read it: x' = x, y' = y - x, z' = x - y + z (mod L) is a bijection of the periodic
 cube, every z' plane holds sites of one colour, and each site's six neighbours sit
 at the transformed offsets the paper lists, three in the plane above and three in
 the plane below.  These are properties of the transformation itself, checked by
