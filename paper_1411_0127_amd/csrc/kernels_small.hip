@@ -91,6 +91,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
     int site[2][kPerThread];
     int nb[2][kPerThread][6];
     uint32_t seed[2][kPerThread];
+    uint64_t jown[2][kPerThread][3];  // couplings of the site's +x, +y, +z bonds (static)
+    uint64_t sown[2][kPerThread];     // the site's spin word (only this thread writes it)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -98,6 +100,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
             const int g = tid + m * kSmallThreads;
             site[c][m] = -1;
             seed[c][m] = 0;
+            jown[c][m][0] = jown[c][m][1] = jown[c][m][2] = 0;
+            sown[c][m] = 0;
 #pragma unroll
             for (int d = 0; d < 6; ++d)
                 nb[c][m][d] = 0;
@@ -116,6 +120,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                 nb[c][m][4] = (z + 1 == L) ? i - (V - LL) : i + LL;
                 nb[c][m][5] = (z == 0) ? i + (V - LL) : i - LL;
                 seed[c][m] = minstd_seed((uint32_t)(x + L * y), minstd_plane_key((uint32_t)z, mk));
+                sown[c][m] = S[i];
+                jown[c][m][0] = J[i];
+                jown[c][m][1] = J[Vj + i];
+                jown[c][m][2] = J[2 * Vj + i];
             }
         }
     __syncthreads();
@@ -131,14 +139,17 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                     continue;
                 const int ixp = nb[c][m][0], ixm = nb[c][m][1], iyp = nb[c][m][2], iym = nb[c][m][3];
                 const int izp = nb[c][m][4], izm = nb[c][m][5];
-                const uint64_t si = s[i];
+                const uint64_t si = sown[c][m];
+                uint64_t sn;
                 if (PRNG == SG_PHILOX)
-                    s[i] = flip_site_ps(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jw[0][i], jw[1][i],
-                                        jw[2][i], jw[0][ixm], jw[1][iym], jw[2][izm], (uint64_t)i, (uint64_t)t,
-                                        (uint32_t)pkey, (uint32_t)(pkey >> 32), T);
+                    sn = flip_site_ps(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jown[c][m][0],
+                                        jown[c][m][1], jown[c][m][2], jw[0][ixm], jw[1][iym], jw[2][izm], (uint64_t)i,
+                                        (uint64_t)t, (uint32_t)pkey, (uint32_t)(pkey >> 32), T);
                 else
-                    s[i] = flip_site(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jw[0][i], jw[1][i],
-                                     jw[2][i], jw[0][ixm], jw[1][iym], jw[2][izm], minstd_jump(a, seed[c][m]), T);
+                    sn = flip_site(si, s[ixp], s[iyp], s[izp], s[ixm], s[iym], s[izm], jown[c][m][0], jown[c][m][1],
+                                     jown[c][m][2], jw[0][ixm], jw[1][iym], jw[2][izm], minstd_jump(a, seed[c][m]), T);
+                s[i] = sn;
+                sown[c][m] = sn;
             }
             __syncthreads();
         }
@@ -153,9 +164,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                     const int i = site[c][m];
                     if (i < 0)
                         continue;
-                    const uint64_t si = s[i];
-                    const uint64_t w[3] = {jw[0][i] ^ si ^ s[nb[c][m][0]], jw[1][i] ^ si ^ s[nb[c][m][2]],
-                                           jw[2][i] ^ si ^ s[nb[c][m][4]]};
+                    const uint64_t si = sown[c][m];
+                    const uint64_t w[3] = {jown[c][m][0] ^ si ^ s[nb[c][m][0]], jown[c][m][1] ^ si ^ s[nb[c][m][2]],
+                                           jown[c][m][2] ^ si ^ s[nb[c][m][4]]};
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         uint64_t v = w[d];
