@@ -22,6 +22,7 @@ constexpr int kPerThread = kSmallSites / 2 / kSmallThreads;  // sites of one col
 constexpr int kCountPlanes = 4;  // a thread adds at most 3 * 4 = 12 bond words per count
 constexpr int kWavePlanes = 10;  // a wave's count is at most 64 * 12 = 768 < 2^10
 constexpr int kBallotSamples = 16;  // up to this many samples the counts are read by ballots
+constexpr int kDirectSamples = 4;   // up to this many, counted per sample directly
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int d)
 {
@@ -153,9 +154,53 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
             }
             __syncthreads();
         }
-        if (out) {
+        if (out && nsamples <= kDirectSamples) {
             // bond (i, i + d) of sample j is unsatisfied when bit j of J[d][i] ^ s_i ^ s_{i+d}
-            // is 1 (the bond bit of Sec. 4); bit-sliced counts, plane b = bit b of 64 counts
+            // is 1 (the bond bit of Sec. 4).  A few samples: an integer count per sample
+            // and thread from the low word, summed over the wave by a butterfly; lane j
+            // keeps sample j's total.
+            uint32_t cj[kDirectSamples] = {};
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int m = 0; m < kPerThread; ++m) {
+                    const int i = site[c][m];
+                    if (i < 0)
+                        continue;
+                    const uint32_t si = (uint32_t)sown[c][m];
+                    const uint32_t w0 = bop3<bop::kXor3>((uint32_t)jown[c][m][0], si, (uint32_t)s[nb[c][m][0]]);
+                    const uint32_t w1 = bop3<bop::kXor3>((uint32_t)jown[c][m][1], si, (uint32_t)s[nb[c][m][2]]);
+                    const uint32_t w2 = bop3<bop::kXor3>((uint32_t)jown[c][m][2], si, (uint32_t)s[nb[c][m][4]]);
+#pragma unroll
+                    for (int j = 0; j < kDirectSamples; ++j) {
+                        if (j >= nsamples)
+                            break;
+                        cj[j] += ((w0 >> j) & 1u) + ((w1 >> j) & 1u) + ((w2 >> j) & 1u);
+                    }
+                }
+            uint64_t mine = 0;
+#pragma unroll
+            for (int j = 0; j < kDirectSamples; ++j) {
+                if (j >= nsamples)
+                    break;
+                uint32_t v = cj[j];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1)
+                    v += (uint32_t)__shfl_xor((int)v, d, 64);
+                mine = lane == j ? v : mine;
+            }
+            part[wave][lane] = mine;
+            __syncthreads();
+            if (tid < 64) {
+                uint64_t sum = 0;
+                for (int w = 0; w < kSmallThreads / 64; ++w)
+                    sum += part[w][tid];
+                out[(size_t)k * 64 + tid] = sum;
+            }
+            // no barrier here: part is written again only after the next sweep's two
+            // colour barriers, which these threads reach once their sums are done
+        } else if (out) {
+            // the same bond bits, bit-sliced counts: plane b = bit b of 64 counts
             uint64_t cnt[kCountPlanes] = {};
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -178,9 +223,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                         }
                     }
                 }
-            // per wave, lane j keeps sample j's total: for a few samples, the sum over
-            // planes b of 2^b times the lanes whose plane b has bit j set (samples past
-            // nsamples are simulated but not counted); for more, the butterfly
+            // per wave, lane j keeps sample j's total: up to kBallotSamples samples, the
+            // sum over planes b of 2^b times the lanes whose plane b has bit j set
+            // (samples past nsamples are simulated but not counted); for more, the
+            // butterfly
             uint64_t mine = 0;
             if (nsamples <= kBallotSamples) {
                 for (int j = 0; j < nsamples; ++j) {
@@ -201,7 +247,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_sweeps(uint64_t *__rest
                     sum += part[w][tid];
                 out[(size_t)k * 64 + tid] = sum;
             }
-            __syncthreads();  // part is written again after the next sweep
+            // no barrier here: part is written again only after the next sweep's two
+            // colour barriers, which these threads reach once their sums are done
         }
         a = minstd_jump(a, 16807u);
     }

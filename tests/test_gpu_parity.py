@@ -719,13 +719,15 @@ def test_autotune_leaves_state_and_parity(sg, prng):
 # energies after every sweep in one call (sg_sweep_energies)
 # ---------------------------------------------------------------------------
 # sides up to 16 with MINSTD or per-sample numbers take the one-workgroup kernel with
-# the lattice in LDS (its counts read by ballots up to 16 samples, by a butterfly of
-# bit-sliced additions above), the others a sweep, a count and a reduction per sweep;
+# the lattice in LDS (its counts taken per sample up to 4 samples, read by ballots up
+# to 16, by a butterfly of bit-sliced additions above), the others a sweep, a count
+# and a reduction per sweep;
 # the L=16 one-sample case is the benchmark's smallest configuration as it runs
 @pytest.mark.parametrize("L,S,prng,n", [(2, 64, "minstd", 40), (4, 1, "minstd", 50), (6, 64, "philox", 12),
                                         (8, 64, "minstd", 30), (12, 64, "philox", 9), (16, 1, "minstd", 1000),
                                         (16, 64, "minstd", 30), (10, 33, "philox", 7), (14, 17, "minstd", 11),
-                                        (12, 16, "minstd", 9),
+                                        (12, 16, "minstd", 9), (8, 4, "philox", 13), (6, 3, "minstd", 20),
+                                        (10, 5, "minstd", 8),
                                         (20, 64, "minstd", 15), (20, 64, "philox", 4), (16, 64, "mt19937", 25),
                                         (18, 64, "parisi_rapuano", 21), (22, 64, "minstd", 7)])
 def test_energy_after_every_sweep_in_one_call(sg, L, S, prng, n):
