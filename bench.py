@@ -331,22 +331,26 @@ def _budget_bytes(torch, frac=0.8):
     return int(torch.cuda.get_device_properties(0).total_memory * frac)
 
 
-def solo_sweep_ms(sg, torch, L, nsw=6):
-    """ms per sweep of one lattice alone (autotuned kernel), on its own stream."""
+def solo_sweep_ms(sg, torch, L, nsw=20, repeats=3):
+    """ms per sweep of one lattice alone (autotuned kernel), on its own stream: the
+    best of `repeats` timings of `nsw` sweeps."""
     stream = torch.cuda.Stream(torch.device("cuda:0"))
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)
     if L >= 64:
         sg.autotune([lat], reps=3)
     lat.sweep(2, 1.0)
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    lat.sweep(nsw, 1.0)
-    b.record(stream)
-    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(repeats):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.sweep(nsw, 1.0)
+        b.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) / nsw)
     lat.close()
-    return a.elapsed_time(b) / nsw
+    return best
 
 
 def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: bool = False):
