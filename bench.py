@@ -17,8 +17,11 @@ The same run adds, outside the timed region:
                  bandwidth is the fraction read at temporal depth 1;
   c1             L=256, two replicas (MINSTD, MT19937, Parisi-Rapuano, and one
                  Philox number per sample);
-  c3             the batched mix of 256 lattices, against plain launches;
-  c4             the served Poisson job stream: p50/p99 latency, psFlip;
+  c3             the batched mix of 256 lattices, against plain launches: every
+                 job alone, its lattice created, swept and its energies read
+                 back, from per-side timings of the same steps;
+  c4             the served Poisson job stream: p50/p99 latency, psFlip, and the
+                 same comparison;
   cpu_baseline   the CPU oracle on bit-planes 0 and 63 of the same L=1024
                  lattice, threaded over all host cores, plus the L=16 one-sample
                  configuration on one core and on all cores.
@@ -332,9 +335,21 @@ def _budget_bytes(torch, frac=0.8):
 
 
 def solo_sweep_ms(sg, torch, L, nsw=20, repeats=3):
-    """ms per sweep of one lattice alone (autotuned kernel), on its own stream: the
-    best of `repeats` timings of `nsw` sweeps."""
+    """(ms per sweep, ms per job outside its sweeps) of one lattice alone (autotuned
+    kernel), on its own stream: the best of `repeats` timings of `nsw` sweeps, and
+    the best of `repeats` of what a job costs besides: creating the lattice
+    (couplings and spins initialised on the device) and reading its energies back
+    (count, sum and copy to the host), as the server does for every job."""
     stream = torch.cuda.Stream(torch.device("cuda:0"))
+    c_best = float("inf")
+    for k in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tmp = sg.Lattice(L, 64, "minstd", coupling_seed=5 + k, spin_seed=6 + k, stream=stream)
+        torch.cuda.synchronize()
+        c_best = min(c_best, (time.perf_counter() - t0) * 1e3)
+        tmp.close()
+        del tmp
     lat = sg.Lattice(L, 64, "minstd", coupling_seed=3, spin_seed=4, stream=stream)
     if L >= 64:
         sg.autotune([lat], reps=3)
@@ -349,11 +364,17 @@ def solo_sweep_ms(sg, torch, L, nsw=20, repeats=3):
         b.record(stream)
         torch.cuda.synchronize()
         best = min(best, a.elapsed_time(b) / nsw)
+    e_best = float("inf")
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        lat.energy()
+        e_best = min(e_best, (time.perf_counter() - t0) * 1e3)
     lat.close()
-    return best
+    return best, c_best + e_best
 
 
-def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: bool = False):
+def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: bool = False,
+            group_bytes=None):
     """Batched (c3) or served (c4) mix through the continuous-batching server."""
     import torch
 
@@ -369,21 +390,22 @@ def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: b
     out = {"workload": MIX_DESC[kind], "sweep_scale": sweep_scale, "seed": seed}
     if kind == "c3":
         jobs = trace_batch(jobs_n or 256, seed=seed, sweep_scale=sweep_scale)
-        be = GpuBackend(rounds_per_graph=8, persistent=persistent)
+        be = GpuBackend(rounds_per_graph=8, persistent=persistent, group_bytes=group_bytes)
         be.pretune(j.L for j in jobs)  # one-time per side, outside the measured span
         rep = Server(be, budget, chunk_rounds=200, min_rounds=8).serve(jobs)
         s = rep.summary()
         sizes = sorted({j.L for j in jobs})
         t_solo = {L: solo_sweep_ms(sg, torch, L) for L in sizes}
-        plain_s = sum(j.nsweeps * t_solo[j.L] for j in jobs) / 1e3
+        plain_s = sum(j.nsweeps * t_solo[j.L][0] + t_solo[j.L][1] for j in jobs) / 1e3
         out["ps_per_flip"] = s["ps_per_flip_makespan"]
         out["plain_ps_per_flip"] = plain_s * 1e12 / s["flips"]
         out["batched_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
-        out["solo_ms_per_sweep"] = {str(L): round(v, 4) for L, v in t_solo.items()}
+        out["solo_ms_per_sweep"] = {str(L): round(v[0], 4) for L, v in t_solo.items()}
+        out["solo_ms_per_job_outside_sweeps"] = {str(L): round(v[1], 4) for L, v in t_solo.items()}
         out["seconds"] = s["makespan_s"]
     else:
         jobs = trace_served(jobs_n or 64, rate=50.0, seed=seed, sweep_scale=sweep_scale)
-        be = GpuBackend(rounds_per_graph=8, persistent=persistent)
+        be = GpuBackend(rounds_per_graph=8, persistent=persistent, group_bytes=group_bytes)
         be.pretune(j.L for j in jobs)
         rep = Server(be, budget, chunk_rounds=100).serve(jobs)
         s = rep.summary()
@@ -394,7 +416,7 @@ def run_mix(kind: str, jobs_n: int, sweep_scale: float, seed: int, persistent: b
         s2 = rep2.summary()
         out["ps_per_flip"] = s["ps_per_flip_busy"]
         t_solo = {L: solo_sweep_ms(sg, torch, L) for L in sorted({j.L for j in jobs})}
-        plain_s = sum(j.nsweeps * t_solo[j.L] for j in jobs) / 1e3
+        plain_s = sum(j.nsweeps * t_solo[j.L][0] + t_solo[j.L][1] for j in jobs) / 1e3
         out["plain_ps_per_flip"] = plain_s * 1e12 / s["flips"]
         out["served_over_plain"] = out["ps_per_flip"] / out["plain_ps_per_flip"]
         out["p50_latency_s"] = s["p50_latency_s"]
@@ -478,6 +500,9 @@ def main():
     ap.add_argument("--sweep-scale", type=float, default=0.1, help="c3: sweep counts x this (c4: x this / 2)")
     ap.add_argument("--jobs", type=int, default=0, help="c3/c4: number of jobs (default 256 / 64)")
     ap.add_argument("--seed", type=int, default=1, help="c3/c4: trace seed")
+    ap.add_argument("--group-gib", type=float, default=-1,
+                    help="batched and served mixes: GiB of lattices per persistent launch (0: all; default: the "
+                         "library's)")
     ap.add_argument("--persistent", type=int, default=1,
                     help="c3/c4: 1 = one persistent launch per run, 0 = one launch per round")
     ap.add_argument("--scan", default="",
@@ -599,7 +624,8 @@ def main():
     for kind in ("c3", "c4"):
         if kind in extras:
             scale = args.sweep_scale if kind == "c3" else args.sweep_scale / 2
-            line[kind] = run_mix(kind, args.jobs, scale, args.seed, persistent=bool(args.persistent))
+            line[kind] = run_mix(kind, args.jobs, scale, args.seed, persistent=bool(args.persistent),
+                                 group_bytes=None if args.group_gib < 0 else int(args.group_gib * (1 << 30)))
             print(f"[bench] {kind} done", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         src = torch.empty(args.calibrate_copy, dtype=torch.uint8, device="cuda:0").fill_(1)

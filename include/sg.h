@@ -359,6 +359,14 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
  * reports SG_EDEVICE (0 = the default, 2^22).  Takes effect at the next run. */
 int sg_batch_set_persistent(sg_batch *b, int on, uint32_t spin_cap);
 
+/* Library runtime.  Persistent runs launch the active lattices in groups taken in
+ * order (one launch per group, one after another on the batch's stream), each
+ * group holding lattices whose spins and couplings (40 B per site) add up to at
+ * most `bytes` (a lattice larger than that alone); bytes = 0 puts every lattice in
+ * one launch, and so does a run of fewer than 4 rounds.  Results do not depend on
+ * it.  Default 12 GiB; takes effect at the next run. */
+int sg_batch_set_group_bytes(sg_batch *b, size_t bytes);
+
 /* Library runtime.  Synchronise the batch's stream and report whether every
  * persistent run queued so far completed (SG_OK) or gave up waiting
  * (SG_EDEVICE: the lattices of that run hold no valid state). */

@@ -9,7 +9,10 @@
 // and start a lattice's round as soon as that lattice's previous round is done, so
 // lattices never wait for each other; with rounds_per_graph > 0 the
 // launch (and the reset of its counters) is captured once into a hipGraph and
-// replayed while the run's shape stays the same.  Per round: one launch of
+// replayed while the run's shape stays the same.  A run of several rounds over
+// more lattice memory than group_bytes is split into launches of groups of
+// lattices, one after another, so that a launch streams over one group's memory
+// rather than the whole resident set.  Per round: one launch of
 // k_fused_batch per round, eagerly or from a captured graph of rounds_per_graph
 // rounds (the round number lives in device memory, so the graph needs no new
 // arguments).  Lattices join and leave between runs: a serving loop admits and
@@ -44,6 +47,14 @@ struct sg_batch {
     uint64_t *d_cum = nullptr;
     bool persistent = true;
     uint32_t spin_cap = 1u << 22;
+    // persistent runs: lattices whose spins and couplings (40 B per site) add up to
+    // at most this many bytes share one launch; 0: one launch for all
+    size_t group_bytes = (size_t)12 << 30;
+    // host tables of the groups of the last grouped run (copied from pageable memory,
+    // which the runtime stages before the copy call returns; kept until the next run)
+    std::vector<std::vector<sg::BatchEntry>> g_entries;
+    std::vector<std::vector<uint32_t>> g_items;
+    std::vector<std::vector<uint64_t>> g_cum;
     std::vector<uint64_t> h_cum;
     std::vector<int> order;  // job indices in layout order (persistent: by rounds left, descending)
     std::vector<Job> jobs;
@@ -81,11 +92,15 @@ void drop_graph(sg_batch *b)
     b->graph_total = 0;
 }
 
+// Persistent runs of fewer rounds than this stay one launch: each group launch ends
+// with a drain of its last round, which a run of a round or two does not win back.
+constexpr int64_t kMinGroupRounds = 4;
+
 // Rounds one persistent launch covers at most (size of the device round table).
 constexpr int kMaxPersistentRounds = 4096;
 
 // Tile of a lattice inside a batch: its chosen (autotuned) tile or the default of
-// its kernel; z chunks of the whole column up to L = 256 and half of it above for
+// its kernel; z chunks of the whole column up to L = 512 and half of it above for
 // the two-sweep march, of up to 128 planes for the one-sweep march.  Lattices on
 // any kernel but SG_KERNEL_FUSED get two-sweep rounds when the tile allows them
 // (a batch has no two-pass form: a lattice set to it takes the default march).
@@ -103,7 +118,7 @@ int batch_tile(const sg_lattice *lat, BatchEntry &e)
     }
     // a chunk of the two-sweep march recomputes six planes, of the one-sweep march two
     if (want_two && lat->L >= 8 && fused2_shape_ok(lat->L, tx, ty, 0))
-        zc = lat->L <= 256 ? lat->L : lat->L / 2;
+        zc = lat->L <= 512 ? lat->L : lat->L / 2;
     else
         zc = lat->L <= 128 ? lat->L : std::max(64, std::min(128, lat->L / 4));
     if (!fill_batch_entry(e, lat->L, tx, ty, zc, lat->band > 0 ? lat->band : 1, want_two))
@@ -113,6 +128,39 @@ int batch_tile(const sg_lattice *lat, BatchEntry &e)
 
 // Rounds a lattice needs for `left` sweeps.
 int64_t rounds_for(const BatchEntry &e, int64_t left) { return e.two ? (left + 1) / 2 : left; }
+
+// Round tables of a persistent launch, one per queue: cum[q * (R + 1) + r] = entries of
+// queue q before round r.  Round r has the items of the lattices still active in it,
+// which `order` (indices into ent, by rounds needed, most first) puts first, dealt to
+// the queues in groups of kBatchGroup, group g to queue g mod kBatchQueues.  Returns
+// the entries of all queues.
+uint64_t round_tables(const std::vector<BatchEntry> &ent, const std::vector<int> &order, int64_t nitems, int64_t R,
+                      std::vector<uint64_t> &cum)
+{
+    const size_t stride = (size_t)R + 1;
+    cum.assign((size_t)kBatchQueues * stride, 0);
+    size_t act = order.size();
+    int64_t items_act = nitems;
+    for (int64_t r = 0; r < R; ++r) {
+        while (act > 0) {
+            const BatchEntry &en = ent[(size_t)order[act - 1]];
+            if (rounds_for(en, en.nsweeps) > r)
+                break;
+            items_act -= en.nitems;
+            --act;
+        }
+        for (int q = 0; q < kBatchQueues; ++q) {
+            int64_t cnt = 0;
+            for (int64_t g = q; g * kBatchGroup < items_act; g += kBatchQueues)
+                cnt += std::min<int64_t>(kBatchGroup, items_act - g * kBatchGroup);
+            cum[(size_t)q * stride + (size_t)r + 1] = cum[(size_t)q * stride + (size_t)r] + (uint64_t)cnt;
+        }
+    }
+    uint64_t total = 0;
+    for (int q = 0; q < kBatchQueues; ++q)
+        total += cum[(size_t)q * stride + (size_t)R];
+    return total;
+}
 
 // Lay out the work items of the current jobs (after jobs joined or left).
 int build_layout(sg_batch *b)
@@ -307,33 +355,66 @@ int sg_batch_run(sg_batch *b, int64_t max_rounds, int rounds_per_graph, int64_t 
 
     int64_t done = 0;
     const int G = rounds_per_graph;
-    if (b->persistent) {
-        // round tables, one per queue: entries before round r.  Round r has the
-        // items of the lattices still active in it (a prefix of the layout), dealt
-        // to the queues in groups of kBatchGroup, group g to queue g mod kBatchQueues.
-        const size_t stride = (size_t)R + 1;
-        b->h_cum.assign((size_t)kBatchQueues * stride, 0);
-        size_t act = b->order.size();
-        int64_t items_act = b->nitems;
-        for (int64_t r = 0; r < R; ++r) {
-            while (act > 0) {
-                const size_t j = (size_t)b->order[act - 1];
-                const BatchEntry &en = b->h_entries[j];
-                if (rounds_for(en, en.nsweeps) > r)
-                    break;
-                items_act -= en.nitems;
-                --act;
+    // persistent runs: groups of consecutive lattices of the layout order (a group's
+    // own order is then by rounds needed too) whose swept bytes stay within
+    // group_bytes, one launch each; a launch then streams over one group's memory,
+    // not the whole resident set
+    std::vector<size_t> gstart{0};
+    if (b->persistent && b->group_bytes > 0 && R >= kMinGroupRounds) {
+        size_t acc = 0;
+        for (size_t o = 0; o < b->order.size(); ++o) {
+            const size_t bytes = 40 * (size_t)b->jobs[(size_t)b->order[o]].lat->V;
+            if (o > gstart.back() && acc + bytes > b->group_bytes) {
+                gstart.push_back(o);
+                acc = 0;
             }
-            for (int q = 0; q < kBatchQueues; ++q) {
-                int64_t cnt = 0;
-                for (int64_t g = q; g * kBatchGroup < items_act; g += kBatchQueues)
-                    cnt += std::min<int64_t>(kBatchGroup, items_act - g * kBatchGroup);
-                b->h_cum[(size_t)q * stride + (size_t)r + 1] = b->h_cum[(size_t)q * stride + (size_t)r] + (uint64_t)cnt;
-            }
+            acc += bytes;
         }
-        uint64_t total = 0;
-        for (int q = 0; q < kBatchQueues; ++q)
-            total += b->h_cum[(size_t)q * stride + (size_t)R];
+    }
+    gstart.push_back(b->order.size());
+    if (b->persistent && gstart.size() > 2) {
+        // launches of the groups one after another on the batch's stream: each one's
+        // entries, item table and round tables are copied over the previous ones
+        // after that launch (stream order)
+        std::vector<std::vector<BatchEntry>> &gent = b->g_entries;
+        std::vector<std::vector<uint32_t>> &gitem = b->g_items;
+        std::vector<std::vector<uint64_t>> &gcum = b->g_cum;
+        gent.assign(gstart.size() - 1, {});
+        gitem.assign(gstart.size() - 1, {});
+        gcum.assign(gstart.size() - 1, {});
+        for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+            std::vector<int> gorder;
+            int64_t Rg = 0;
+            int items = 0;
+            for (size_t o = gstart[g]; o < gstart[g + 1]; ++o) {
+                BatchEntry en = b->h_entries[(size_t)b->order[o]];
+                en.item0 = items;
+                gitem[g].insert(gitem[g].end(), (size_t)en.nitems, (uint32_t)(o - gstart[g]));
+                items += en.nitems;
+                Rg = std::max(Rg, rounds_for(en, en.nsweeps));
+                gorder.push_back((int)(o - gstart[g]));
+                gent[g].push_back(en);
+            }
+            if (Rg == 0)
+                continue;
+            const uint64_t total = round_tables(gent[g], gorder, items, Rg, gcum[g]);
+            e = hipMemcpyAsync(b->d_entries, gent[g].data(), sizeof(BatchEntry) * gent[g].size(),
+                               hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->d_item_lat, gitem[g].data(), 4 * gitem[g].size(), hipMemcpyHostToDevice,
+                                   b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->d_cum, gcum[g].data(), 8 * gcum[g].size(), hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = launch_batch_persistent(b->d_entries, b->d_item_lat, b->d_cum, (int)Rg, b->d_queue, b->d_done,
+                                            b->d_error, (int)gent[g].size(), b->spin_cap, b->lds, (int64_t)total,
+                                            b->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "grouped persistent batch launch");
+        }
+        done = R;
+    } else if (b->persistent) {
+        uint64_t total = round_tables(b->h_entries, b->order, b->nitems, R, b->h_cum);
         e = hipMemcpyAsync(b->d_cum, b->h_cum.data(), 8 * b->h_cum.size(), hipMemcpyHostToDevice, b->stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch round table");
@@ -455,6 +536,14 @@ int sg_batch_set_persistent(sg_batch *b, int on, uint32_t spin_cap)
         drop_graph(b);
     b->persistent = on != 0;
     b->spin_cap = spin_cap == 0 ? (1u << 22) : spin_cap;
+    return SG_OK;
+}
+
+int sg_batch_set_group_bytes(sg_batch *b, size_t bytes)
+{
+    if (!b)
+        return fail(SG_EINVAL, "NULL batch");
+    b->group_bytes = bytes;
     return SG_OK;
 }
 

@@ -81,7 +81,8 @@ class GpuBackend:
     is one persistent launch (persistent=True) or one launch per round."""
 
     def __init__(self, device="cuda:0", max_lattices: int = 512, max_items: int = 1 << 20,
-                 rounds_per_graph: int = 0, autotune: bool = True, persistent: bool = True):
+                 rounds_per_graph: int = 0, autotune: bool = True, persistent: bool = True,
+                 group_bytes: Optional[int] = None):
         import torch
 
         from paper_1411_0127_amd import sg
@@ -95,6 +96,8 @@ class GpuBackend:
         self.autotune = autotune
         self.persistent = bool(persistent)
         self.batch.set_persistent(self.persistent)
+        if group_bytes is not None:  # else the library's default
+            self.batch.set_group_bytes(group_bytes)
         self._inflight = []  # events of queued runs; at most two are kept in flight
         self._tuned = set()
 

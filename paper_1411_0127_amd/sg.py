@@ -81,6 +81,7 @@ SIGNATURES = {
     "sg_batch_size": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "sg_batch_destroy": (_i, [_p]),
     "sg_batch_set_persistent": (_i, [_p, _i, _u32]),
+    "sg_batch_set_group_bytes": (_i, [_p, _sz]),
     "sg_batch_check": (_i, [_p]),
     "sg_probe_bandwidth": (_i, [_i, _p, _p, _sz, _i, _p]),
     "sg_destroy": (_i, [_p]),
@@ -381,6 +382,11 @@ class Batch:
                                    _p(stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
         self._members = {}  # handle value -> Lattice, keeps them alive while queued
+
+    def set_group_bytes(self, nbytes: int):
+        """Persistent runs launch lattices in groups of at most nbytes of spins and
+        couplings (0: all in one launch)."""
+        _check(lib.sg_batch_set_group_bytes(self.handle, int(nbytes)))
 
     def set_persistent(self, on: bool = True, spin_cap: int = 0):
         """One persistent launch per run (True, the default) or one launch per round."""

@@ -166,22 +166,65 @@ def test_graph_replays_one_by_one(env, mode):
     b.close()
 
 
+GROUP_JOBS = [(8, 11, 12, 0.5, 71), (16, 13, 14, 0.8, 100), (24, 15, 16, 1.2, 66), (32, 17, 18, 1.5, 90),
+              (48, 19, 20, 2.0, 64), (16, 21, 22, 1 / 0.7, 129)]
+
+
+@pytest.mark.parametrize("graph", [0, 2])
+@pytest.mark.parametrize("cap_sites", [1, 20000, 60000])
+def test_grouped_persistent_runs(env, graph, cap_sites):
+    """Persistent runs of 4 rounds or more launch the lattices in groups of bounded
+    memory, one after another: a cap of one site puts each lattice in a group of its
+    own, the others form groups of several.  A short first run stays one launch;
+    every lattice must equal the same lattice swept alone, and L = 8 and 16 the
+    oracle."""
+    sg, stream = env
+    say("grouped persistent", graph, cap_sites)
+    b = make_batch(sg, stream, "persistent")
+    b.set_group_bytes(40 * cap_sites)
+    lats = []
+    for (L, cs, ss, beta, n) in GROUP_JOBS:
+        lat = sg.Lattice(L, 64, "minstd", coupling_seed=cs, spin_seed=ss, stream=stream)
+        b.add(lat, n, beta)
+        lats.append(lat)
+    # runs of 32 rounds (grouped launches while at least 4 are left), after a short
+    # first run (one launch)
+    b.run(2, graph)
+    runs = 1
+    while b.rounds_left()[1] > 0:
+        b.run(32, graph)
+        runs += 1
+    assert runs >= 2
+    b.check()
+    done = b.take_finished()
+    assert len(done) == len(GROUP_JOBS)
+    for lat, (L, cs, ss, beta, n) in zip(lats, GROUP_JOBS):
+        assert lat.t == n
+        w = lat.words()
+        assert np.array_equal(w, solo_words(sg, stream, L, cs, ss, beta, n)), f"L={L} vs solo"
+        if L <= 16:
+            assert np.array_equal(w, oracle_words(L, cs, ss, beta, n)), f"L={L} vs oracle"
+        lat.close()
+    b.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_large_sides_with_tuned_tiles(env, mode):
-    """One lattice each of L = 64, 128, 256 and 512 with the autotuned tiles the
+    """One lattice each of L = 64, 128, 256, 512 and 544 with the autotuned tiles the
     benchmark uses (pretuned as the server does), odd sweep counts, and runs replayed
-    from a graph at least twice: two z chunks of the two-sweep march at L = 512,
-    four of the one-sweep march for a lattice set to it at L = 256.  Each lattice
-    must equal the same lattice swept alone, L = 64 also the oracle."""
+    from a graph at least twice: whole columns of the two-sweep march up to L = 512,
+    two z chunks of it at L = 544, four of the one-sweep march for a lattice set to
+    it at L = 256.  Each lattice must equal the same lattice swept alone, L = 64
+    also the oracle."""
     sg, stream = env
     from paper_1411_0127_amd.serve import GpuBackend
 
     say("batch large sides", mode)
     be = GpuBackend(max_lattices=8, max_items=200000, rounds_per_graph=2, persistent=(mode == "persistent"))
-    be.pretune([64, 128, 256, 512])
+    be.pretune([64, 128, 256, 512, 544])
     specs = [  # L, coupling seed, spin seed, beta, sweeps, kernel
         (64, 61, 62, 0.9, 7, None), (128, 63, 64, 1.1, 5, None), (256, 65, 66, 0.7, 9, None),
-        (512, 67, 68, 1.3, 5, None), (256, 69, 70, 1.0, 5, "fused"),
+        (512, 67, 68, 1.3, 5, None), (256, 69, 70, 1.0, 5, "fused"), (544, 71, 72, 0.8, 3, None),
     ]
     b = make_batch(sg, be.stream, mode, max_lat=8, max_items=200000)
     lats = []
