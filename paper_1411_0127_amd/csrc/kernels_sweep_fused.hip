@@ -1032,6 +1032,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
                     }
                     __builtin_amdgcn_s_sleep(32);
                 }
+                // the previous round's words, written on any XCD, are visible from here
+                // on: the acquire drops this CU's and this XCD's stale lines, which
+                // serves every wave of the workgroup, as the others read only after the
+                // barrier below (one invalidation per item, not one per wave); the wait
+                // makes the invalidation complete before that barrier
+                if (go) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                }
             }
             // every lane of the wave writes the same values
             s_round = lo;
@@ -1047,9 +1058,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
         if (go == 0u)
             break;
         const BatchEntry &e = a.E[li];
-        // the previous round's words, written on any XCD, are visible from here on
-        // (the acquire drops this XCD's stale lines)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         batch_item<kStoreDevice>(e, lo, item - e.item0, lds);
         // The item's spin words went out as device-coherent stores, so they are
         // visible to every XCD once they have completed: each wave waits for its
