@@ -987,6 +987,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
     const int stride = a.nrounds + 1;
     int q = (int)(blockIdx.x % kBatchQueues);  // current queue (wave 0's copy is the one used)
     int qleft = kBatchQueues;                  // queues not yet found empty
+    int acq_lat = -1, acq_round = -1;          // (lattice, round) of wave 0's last acquire
     for (;;) {
         if (wave0) {
             uint32_t go = 0u;
@@ -1036,12 +1037,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_persistent(PersistentArgs
                 // on: the acquire drops this CU's and this XCD's stale lines, which
                 // serves every wave of the workgroup, as the others read only after the
                 // barrier below (one invalidation per item, not one per wave); the wait
-                // makes the invalidation complete before that barrier
-                if (go) {
+                // makes the invalidation complete before that barrier.  An item of the
+                // lattice and round of this workgroup's last acquire needs none: that
+                // acquire came after the whole previous round was done, and nothing can
+                // bring an older copy of those words into the caches since.
+                if (go && (li != acq_lat || lo != acq_round)) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     __builtin_amdgcn_s_waitcnt(0);
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    acq_lat = li;
+                    acq_round = lo;
                 }
             }
             // every lane of the wave writes the same values
